@@ -1,0 +1,132 @@
+"""Kernel, per-strut integral and field sums of the convolution surface.
+
+Test infrastructure (see the package docstring).  Everything is float64.
+Only +, -, *, / and sqrt are used, so each element's value does not depend on
+how numpy vectorises the array it sits in.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _dot3(A, B):
+    """Row-wise dot product of [...,3] arrays, summed x + y + z in order."""
+    A = np.broadcast_to(A, np.broadcast_shapes(np.shape(A), np.shape(B)))
+    B = np.broadcast_to(B, A.shape)
+    return A[..., 0] * B[..., 0] + A[..., 1] * B[..., 1] + A[..., 2] * B[..., 2]
+
+
+def kernel(dist, R: float):
+    """Eq. (5): f = (1 - |p - x|^2 / R^2)^2 where |p - x| < R, else 0."""
+    d = np.asarray(dist, dtype=np.float64)
+    t = 1.0 - d * d / (R * R)
+    return np.where(d < R, t * t, 0.0)
+
+
+def strut_integral(P, vs, ve, R: float) -> np.ndarray:
+    """Integral of the kernel over the edge (vs, ve) for each point of P.
+
+    Sec. 2.2, Eq. (6)-(7).  For a query point p, the line of the edge meets
+    the sphere of radius R around p at p1 and p2 (p1 before p2 in the
+    direction vs -> ve); s1, s2 are the parameters of the edge ends along the
+    chord x(s) = (1 - s) p1 + s p2, clipped to [0, 1]; with l = |p2 - p1| and
+    a = (p - p1).(p2 - p1) the s-integral of f has the closed form
+
+        (3 l^4 s^5 - 15 a l^2 s^4 + 20 a^2 s^3) / (15 R^4)  from s1 to s2.
+
+    Eq. (6) integrates with respect to arclength on the edge, and
+    d(arclength) = l ds along the chord, so the result is l times that
+    difference (the printed Eq. (7) omits the factor l).  The term is zero
+    when the line misses the open ball (no chord), when the edge has zero
+    length, or when the edge lies outside the chord (s2 <= s1).
+
+    P: [..., 3] points; vs, ve: [3].  Returns float64 [...].
+    """
+    P = np.asarray(P, dtype=np.float64)
+    vs = np.asarray(vs, dtype=np.float64)
+    ve = np.asarray(ve, dtype=np.float64)
+    shape = P.shape[:-1]
+    P = P.reshape(-1, 3)
+    d = ve - vs
+    L2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2]
+    if L2 == 0.0:
+        return np.zeros(shape)
+    u = d / np.sqrt(L2)
+    # foot of p on the line, and squared distance of p from the line
+    w = P - vs
+    t0 = _dot3(w, u[None, :])
+    perp = w - t0[:, None] * u
+    dperp2 = _dot3(perp, perp)
+    hit = dperp2 < R * R
+    h = np.sqrt(np.where(hit, R * R - dperp2, 0.0))
+    foot = vs + t0[:, None] * u
+    p1 = foot - h[:, None] * u
+    p2 = foot + h[:, None] * u
+    e = p2 - p1
+    l2 = _dot3(e, e)
+    l = np.sqrt(l2)
+    safe = np.where(hit, l2, 1.0)
+    s1 = np.maximum(0.0, _dot3(vs - p1, e) / safe)
+    s2 = np.minimum(1.0, _dot3(ve - p1, e) / safe)
+    a = _dot3(P - p1, e)
+
+    def F(s):
+        s3 = s * s * s
+        s4 = s3 * s
+        s5 = s4 * s
+        l4 = l2 * l2
+        return (3.0 * l4 * s5 - 15.0 * a * l2 * s4 + 20.0 * a * a * s3) / (
+            15.0 * R ** 4)
+
+    val = l * (F(s2) - F(s1))
+    val = np.where(hit & (s2 > s1), val, 0.0)
+    return val.reshape(shape)
+
+
+def field_at(points, nodes, edges, weight, R: float, struts=None) -> np.ndarray:
+    """g(p) = sum_i r_i * integral_i(p) (Eq. 6 without the -C), summed in
+    ascending strut id, one strut at a time.  `struts` restricts the sum to a
+    subset of ids (given in ascending order); omitted struts must contribute
+    exactly zero for the result to equal the full sum."""
+    points = np.asarray(points, dtype=np.float64)
+    nodes = np.asarray(nodes, dtype=np.float64)
+    weight = np.asarray(weight, dtype=np.float64)
+    g = np.zeros(points.shape[:-1])
+    ids = range(len(edges)) if struts is None else struts
+    for i in ids:
+        if weight[i] == 0.0:
+            continue
+        g = g + weight[i] * strut_integral(points, nodes[edges[i, 0]],
+                                           nodes[edges[i, 1]], R)
+    return g
+
+
+def line_integral_quadrature(p, vs, ve, R: float, epsabs=1e-13, epsrel=1e-11):
+    """Eq. (6) for one strut by adaptive quadrature of the kernel along the
+    edge (arclength): an independent route to strut_integral."""
+    from scipy.integrate import quad
+    p = np.asarray(p, dtype=np.float64)
+    vs = np.asarray(vs, dtype=np.float64)
+    ve = np.asarray(ve, dtype=np.float64)
+    L = float(np.linalg.norm(ve - vs))
+    if L == 0.0:
+        return 0.0
+    u = (ve - vs) / L
+
+    def f(t):
+        x = vs + t * u
+        return float(kernel(np.linalg.norm(p - x), R))
+
+    # split at the chord ends so the integrand is smooth on each piece
+    t0 = float(np.dot(p - vs, u))
+    dperp2 = float(np.dot(p - vs - t0 * u, p - vs - t0 * u))
+    pts = [0.0, L]
+    if dperp2 < R * R:
+        h = np.sqrt(R * R - dperp2)
+        pts += [t for t in (t0 - h, t0, t0 + h) if 0.0 < t < L]
+    pts = sorted(pts)
+    total = 0.0
+    for lo, hi in zip(pts[:-1], pts[1:]):
+        v, _ = quad(f, lo, hi, epsabs=epsabs, epsrel=epsrel, limit=200)
+        total += v
+    return total

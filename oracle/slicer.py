@@ -1,0 +1,106 @@
+"""The streaming slicer of Sec. 3, in float64.
+
+Test infrastructure (see the package docstring).
+
+* slice_heights: Step 1 puts the first plane half a layer above the start
+  height and Step 5 moves up by one layer, so plane k is z0 + (k + 1/2) t.
+* active_set: Eq. (8), the struts whose swept sphere of radius R meets the
+  plane, with the lower end written v_s (the paper orders the ends by z).
+* sweep_active_sets: Steps 1-6, the edge list sorted by lower z plus the
+  active list, as a second route to the same sets.
+* slice_field: Step 4, the field at every pixel centre of one plane using the
+  active struts only; inside where the sum reaches the iso-value.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .field import strut_integral
+
+
+def slice_heights(z0: float, t: float, n: int) -> np.ndarray:
+    return z0 + (np.arange(n, dtype=np.float64) + 0.5) * t
+
+
+def strut_z_range(nodes, edges):
+    """(lower z, upper z) of each strut's two ends."""
+    z = np.asarray(nodes, dtype=np.float64)[:, 2]
+    za = z[edges[:, 0]]
+    zb = z[edges[:, 1]]
+    return np.minimum(za, zb), np.maximum(za, zb)
+
+
+def active_set(zlo, zhi, R: float, z: float) -> np.ndarray:
+    """Eq. (8): ids j with v_s^z - R <= z and v_e^z + R >= z, ascending."""
+    return np.nonzero((zlo - R <= z) & (zhi + R >= z))[0]
+
+
+def sweep_active_sets(zlo, zhi, R: float, heights):
+    """Steps 1-6: returns the active set (ascending ids) of every plane."""
+    order = np.argsort(zlo, kind="stable")     # list sorted by lower z
+    m = len(order)
+    k = 0                                      # first edge not yet added
+    active: list[int] = []
+    out = []
+    for z in heights:
+        # Step 2: add edges until one lies completely above the plane
+        while k < m and not (zlo[order[k]] - R > z):
+            active.append(int(order[k]))
+            k += 1
+        # Step 3: drop edges lying completely below the plane
+        active = [j for j in active if not (zhi[j] + R < z)]
+        out.append(np.array(sorted(active), dtype=np.int64))
+    return out
+
+
+def _pixel_window(lo, hi, origin, step, n):
+    """Index range of pixel centres origin + (i + 1/2) step inside [lo, hi],
+    widened by one pixel on each side (a superset; pixels outside the
+    kernel's support add exact zeros)."""
+    i0 = int(np.floor((lo - origin) / step - 0.5)) - 1
+    i1 = int(np.ceil((hi - origin) / step - 0.5)) + 1
+    return max(i0, 0), min(i1, n - 1)
+
+
+def slice_field(nodes, edges, weight, R: float, grid, k: int,
+                struts=None) -> np.ndarray:
+    """g at every pixel centre of plane k: array [H, W] float64, g[j, i] at
+    (x0 + (i+1/2) dx, y0 + (j+1/2) dy).  Struts of the active set (Eq. 8)
+    are added in ascending id, each over the window of pixels its support
+    can reach; outside that window its term is exactly zero."""
+    nodes = np.asarray(nodes, dtype=np.float64)
+    weight = np.asarray(weight, dtype=np.float64)
+    z = float(grid.slice_z(k))
+    zlo, zhi = strut_z_range(nodes, edges)
+    ids = active_set(zlo, zhi, R, z) if struts is None else struts
+    g = np.zeros((grid.H, grid.W))
+    xs = grid.pixel_x()
+    ys = grid.pixel_y()
+    for i in ids:
+        if weight[i] == 0.0:
+            continue
+        a = nodes[edges[i, 0]]
+        b = nodes[edges[i, 1]]
+        ix0, ix1 = _pixel_window(min(a[0], b[0]) - R, max(a[0], b[0]) + R,
+                                 grid.x0, grid.dx, grid.W)
+        iy0, iy1 = _pixel_window(min(a[1], b[1]) - R, max(a[1], b[1]) + R,
+                                 grid.y0, grid.dy, grid.H)
+        if ix0 > ix1 or iy0 > iy1:
+            continue
+        X, Y = np.meshgrid(xs[ix0:ix1 + 1], ys[iy0:iy1 + 1], indexing="xy")
+        P = np.stack([X, Y, np.full_like(X, z)], axis=-1)
+        g[iy0:iy1 + 1, ix0:ix1 + 1] += weight[i] * strut_integral(P, a, b, R)
+    return g
+
+
+def slice_points(grid, k: int, px: np.ndarray, py: np.ndarray) -> np.ndarray:
+    """Pixel-centre points [n,3] of plane k for pixel indices (px, py)."""
+    x = grid.x0 + (np.asarray(px, dtype=np.float64) + 0.5) * grid.dx
+    y = grid.y0 + (np.asarray(py, dtype=np.float64) + 0.5) * grid.dy
+    z = np.full(x.shape, float(grid.slice_z(k)))
+    return np.stack([x, y, z], axis=-1)
+
+
+def inside(g, C: float):
+    """Binary slice image: inside where the field sum reaches C."""
+    return np.asarray(g) >= C
