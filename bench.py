@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""Benchmark of the slicing hot path on one MI355X.
+
+Workload (default): Kuhn tetrahedral lattice of 52^3 cubes in a 100 mm cube,
+1,008,748 struts, graded radii 0.2-1.0 mm (R = 1.5 mm), sliced into 1000
+planes at 0.1 mm on a 2048 x 2048 grid -- the lattice recipe of the adaptive
+tetrahedral configuration at one million struts.  Seeded synthetic input.
+
+A step is one pass of the whole path over the lattice, inputs already in HBM:
+  lattice_bin (strut prep, z-ordered edge list, slab/tile buckets)
+  slice_batch (persistent field kernel, binary image, marching squares)
+and, for the fwd+bwd step, a soft-occupancy loss on the field (torch
+elementwise) and slice_field_backward over all planes.
+
+Printed: one JSON line.  value = useful pixel-strut field evaluations per
+second of the forward step (pairs with a non-zero term, counted exactly by
+slice_field_stats, untimed).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOP_PER_USEFUL_PAIR = 36          # see the field kernel's op count
+PEAK_FP32_VECTOR = 157.3e12        # MI355X published FP32 vector peak
+HBM_PEAK = 8.0e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="M1", choices=["M1", "A2", "D4", "P1", "B3"])
+    ap.add_argument("--slices", type=int, default=0, help="limit planes (0 = all)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--slab", type=int, default=0)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this path runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_2101_05031_amd import api, synth
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    lat, grid = synth.config(args.workload)
+    if args.slices:
+        grid.n_slices = min(grid.n_slices, args.slices)
+    S = grid.n_slices
+    dtype = torch.float64 if lat.nodes.dtype == np.float64 else torch.float32
+    nodes = torch.from_numpy(lat.nodes).to(dev)
+    edges = torch.from_numpy(lat.edges).to(dev)
+    weight = torch.from_numpy(lat.weight).to(dev)
+    stream = torch.cuda.current_stream()
+    W, H = grid.W, grid.H
+    print(f"[bench] workload {args.workload}: E={lat.n_edges} N={lat.n_nodes} "
+          f"{S} planes of {W}x{H}", file=sys.stderr, flush=True)
+
+    field = torch.empty((S, H, W), dtype=dtype, device=dev)
+    bits = torch.empty((S, H, (W + 31) // 32), dtype=torch.int32, device=dev)
+    offsets = torch.empty(S + 1, dtype=torch.int64, device=dev)
+
+    def binit():
+        return api.lattice_bin(nodes, edges, weight, lat.R, lat.C, grid, tile=args.tile,
+                               slab=args.slab)
+
+    # size the segment buffer once (untimed)
+    b = binit()
+    st, total, _, _ = api.slice_batch(b, 0, S, field=field, bits=bits, capacity=0,
+                                      offsets=offsets)
+    capacity = int(total * 1.05) + 1024
+    segs = torch.empty((capacity, 4), dtype=torch.float32, device=dev)
+    stats = api.slice_field_stats(b, 0, S)
+    info = b.info()
+    del b
+    print(f"[bench] useful pairs {stats['useful']:.4e}, candidates {stats['candidates']:.4e}, "
+          f"segments {total}, bins {info['total_pairs']} pairs", file=sys.stderr, flush=True)
+
+    # the loss target (input generation, untimed): seeded 8-blob density
+    target = None
+    if not args.no_backward:
+        rng = np.random.default_rng(4)
+        c = torch.tensor(rng.uniform(0.0, 100.0, size=(8, 3)), device=dev, dtype=torch.float32)
+        s = torch.tensor(rng.uniform(10.0, 30.0, size=8), device=dev, dtype=torch.float32)
+        xs = torch.tensor(grid.pixel_x(), device=dev, dtype=torch.float32)
+        ys = torch.tensor(grid.pixel_y(), device=dev, dtype=torch.float32)
+        target = torch.empty((S, H, W), dtype=dtype, device=dev)
+        for k in range(S):
+            z = float(grid.slice_z(k))
+            acc = torch.zeros((H, W), device=dev, dtype=torch.float32)
+            for q in range(8):
+                d2 = (xs[None, :] - c[q, 0]) ** 2 + (ys[:, None] - c[q, 1]) ** 2 + (z - c[q, 2]) ** 2
+                acc += torch.exp(-d2 / (2.0 * s[q] ** 2))
+            target[k] = acc.clamp(max=1.0).to(dtype)
+        tau = 0.05
+    grad_weight = torch.empty(lat.n_edges, dtype=dtype, device=dev)
+    grad_nodes = torch.empty((lat.n_nodes, 3), dtype=dtype, device=dev)
+
+    def fwd_step():
+        bb = binit()
+        st, tot, _, _ = api.slice_batch(bb, 0, S, field=field, bits=bits, capacity=capacity,
+                                        segs=segs, offsets=offsets)
+        return bb
+
+    def fwd_bwd_step():
+        bb = fwd_step()
+        occ = torch.sigmoid((field - lat.C) / tau)
+        G = (2.0 / tau) * (occ - target) * occ * (1.0 - occ)
+        api.slice_field_backward(bb, 0, S, G, grad_weight, grad_nodes)
+        return bb
+
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        field_ms = 0.0
+        for i in range(k):
+            bb = fn()
+            field_ms += bb.info()["last_field_ms"]
+            print(f"[bench] step {i + 1}/{k} done", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k, field_ms / k
+
+    for i in range(args.warmup):
+        fwd_step()
+        if not args.no_backward:
+            fwd_bwd_step()
+        print(f"[bench] warmup {i + 1}/{args.warmup}", file=sys.stderr, flush=True)
+    t_fwd, field_ms = timed(fwd_step, args.steps)
+    t_fb = None
+    if not args.no_backward:
+        t_fb, _ = timed(fwd_bwd_step, args.steps)
+
+    useful = stats["useful"]
+    value = useful / t_fwd
+    field_s = field_ms * 1e-3
+    achieved = useful * FLOP_PER_USEFUL_PAIR / field_s if field_s > 0 else None
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
+    if os.path.exists(tpath):
+        try:
+            from paper_2101_05031_amd import build as B
+            rec = json.load(open(tpath))
+            if rec.get("kernel_hash") == B.kernel_hash("field"):
+                traffic = rec.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    out = {
+        "metric": "pixel-strut field evals/s (useful pairs) and slices/s at 1M struts; "
+                  "fwd+bwd/fwd time ratio",
+        "value": value,
+        "unit": "pixel*strut evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_fwd * 1e3,
+        "ms_per_step_fwd_bwd": None if t_fb is None else t_fb * 1e3,
+        "fwd_bwd_ratio": None if t_fb is None else t_fb / t_fwd,
+        "slices_per_s": S / t_fwd,
+        "executed_evals_per_s": stats["candidates"] / t_fwd,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if dtype == torch.float64 else "f32",
+        "data": "synthetic (seeded lattice generator)",
+        "config": {
+            "workload": {
+                "M1": "Kuhn 52^3 tetrahedral lattice, 100 mm cube, 1,008,748 struts, graded "
+                      "radius 0.2-1.0 mm, R=1.5 mm, 1000 planes at 0.1 mm, 2048x2048",
+                "A2": "Kuhn 40^3 tetrahedral lattice, 462,520 struts, 1000 planes, 2048x2048",
+                "D4": "Kuhn 25^3 tetrahedral lattice, 115,075 struts, 64 planes, 1024x1024",
+                "P1": "BCC 4^3 cells, 812 struts, 50 planes, 256x256, float64",
+                "B3": "Kuhn 110^3, 9,426,230 struts, 2000 planes, 4096x4096",
+            }[args.workload],
+            "n_struts": lat.n_edges, "planes": S, "grid": [W, H],
+            "tile": info["tile"], "slab": info["slab"],
+            "useful_pairs": useful, "candidate_pairs": stats["candidates"],
+            "segments": total,
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_persistent (field)",
+            "achieved": None if achieved is None else achieved / 1e12,
+            "peak": PEAK_FP32_VECTOR / 1e12,
+            "unit": "TFLOP/s",
+            "frac": None if achieved is None else achieved / PEAK_FP32_VECTOR,
+            "traffic": traffic,
+            "field_ms_per_launch": field_ms,
+            "flop_per_useful_pair": FLOP_PER_USEFUL_PAIR,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(lat, grid)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(lat, grid):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload: a
+    1024 x 1024 pixel window of the middle plane (one core)."""
+    import copy
+
+    from oracle import field as OF
+    from oracle import slicer as OS
+    k = grid.n_slices // 2
+    sub = copy.copy(grid)
+    i0 = (grid.W - 1024) // 2 if grid.W > 1024 else 0
+    j0 = (grid.H - 1024) // 2 if grid.H > 1024 else 0
+    sub.x0 = grid.x0 + i0 * grid.dx
+    sub.y0 = grid.y0 + j0 * grid.dy
+    sub.W = min(1024, grid.W)
+    sub.H = min(1024, grid.H)
+    count = [0]
+    orig = OF.strut_integral
+
+    def counting(*a, **kw):
+        r = orig(*a, **kw)
+        count[0] += int(np.count_nonzero(r))
+        return r
+
+    OS.strut_integral = counting
+    try:
+        t0 = time.perf_counter()
+        OS.slice_field(lat.nodes, lat.edges, lat.weight, lat.R, sub, k)
+        dt = time.perf_counter() - t0
+    finally:
+        OS.strut_integral = orig
+    return {"value": count[0] / dt, "unit": "pixel*strut evals/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"plane {k}, {sub.W}x{sub.H} pixel window ({count[0]} useful pairs, "
+                      f"{dt:.1f} s, numpy float64, one thread)"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,262 @@
+/*
+ * lsl.h -- C ABI of liblsl, an MI355X (gfx950) slicer for lattice structures
+ * whose solid is a convolution surface with a compactly supported kernel
+ * (Liu et al., "Memory-Efficient Modeling and Slicing of Large-Scale Adaptive
+ * Lattice Structures").
+ *
+ * What is computed.  A lattice is a strut graph: nodes v_i in R^3 and edges
+ * e_j = (v_s, v_e, r_j) (Sec. 3.1).  Its field at a point p is
+ *
+ *     g(p) = sum_j r_j * integral over e_j of f(p - x) d(arclength)   (Eq. 6)
+ *     f(d) = (1 - |d|^2 / R^2)^2  for |d| < R, else 0                  (Eq. 5)
+ *
+ * and p lies inside the solid where g(p) >= C (the paper writes the implicit
+ * function as F = -C + g; inside is where the skeleton's sum reaches the
+ * iso-value).  Slices are planes z_k = z0 + (k + 1/2) dz (Sec. 4, Steps 1
+ * and 5); each plane is sampled at pixel centres
+ * (x0 + (i + 1/2) dx, y0 + (j + 1/2) dy), i < W, j < H, giving a field image,
+ * a binary image (Sec. 4) and its marching-squares contours (Sec. 4).
+ *
+ * Conventions for every call:
+ *  - Pointers are DEVICE pointers unless marked [host].  The caller owns every
+ *    buffer it passes; the library never frees them.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued on it in order.  Calls that must read a size back from
+ *    the device synchronise that stream; this is stated per call.
+ *  - Errors are returned, never thrown, and leave outputs unspecified.
+ *    lsl_last_error() gives a message for the calling thread's last error.
+ *  - dtype LSL_F32 computes in float32 (compensated sums), LSL_F64 in
+ *    float64.  Field, weight and gradient arrays use the lattice's dtype.
+ *  - Image layout: [slice][row j][column i], i fastest.
+ *  - A handle may be used by one stream at a time.
+ */
+#ifndef LSL_H
+#define LSL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lsl_status;
+#define LSL_OK          0
+#define LSL_EINVAL     (-1) /* bad argument or lattice (message says which)   */
+#define LSL_ENOMEM     (-2) /* device allocation failed or budget exceeded    */
+#define LSL_ECAPACITY  (-3) /* output buffer too small; required size given   */
+#define LSL_EDEVICE    (-4) /* HIP runtime error (also from earlier work)     */
+#define LSL_EINTERNAL  (-5) /* internal invariant failed                      */
+
+#define LSL_F32 0
+#define LSL_F64 1
+
+/* The strut graph (Sec. 3.1).  [host] struct; arrays are device memory and are
+ * only read during lattice_bin (they may be freed after it returns). */
+typedef struct lsl_lattice {
+    int64_t n_nodes;        /* >= 1                                              */
+    int64_t n_edges;        /* >= 0                                              */
+    int32_t dtype;          /* LSL_F32 or LSL_F64: element type of nodes, weight */
+    const void* nodes;      /* [n_nodes][3] positions v_i, finite                */
+    const int32_t* edges;   /* [n_edges][2] node indices (v_s, v_e), in range    */
+    const void* weight;     /* [n_edges] r_j of Eq. (6), finite, >= 0;
+                               0 marks an absent strut (never binned)            */
+    double R;               /* kernel support of Eq. (5), finite, > 0            */
+    double C;               /* iso-value, finite, > 0                            */
+} lsl_lattice;
+
+/* Pixel grid and slice planes.  [host] struct. */
+typedef struct lsl_grid {
+    double x0, y0;          /* origin: pixel (i,j) centre is                     */
+    double dx, dy;          /*   (x0 + (i+1/2) dx, y0 + (j+1/2) dy); dx, dy > 0  */
+    int32_t W, H;           /* pixels per row / rows, >= 2                       */
+    double z0, dz;          /* plane k at z0 + (k+1/2) dz; dz > 0               */
+    int32_t n_slices;       /* >= 1                                              */
+} lsl_grid;
+
+/* Binning choices.  [host] struct; a zero field takes the default. */
+typedef struct lsl_bin_params {
+    int32_t tile;           /* square xy tile edge in pixels: 8, 16, 32 or 64
+                               (default 16)                                      */
+    int32_t slab;           /* consecutive slices per z-slab, 1..16 (default 8)  */
+    int64_t max_pairs;      /* most (slab, tile, strut) pairs binned at once;
+                               more slabs than that are binned group by group
+                               as slices are requested (default 2^30)            */
+} lsl_bin_params;
+
+/* Opaque handle: the prepared struts in edge-list order (ascending z of the
+ * lower end, Sec. 4), their slab/tile ranges, the slab-group plan and the
+ * bucket lists of the group binned last.  Owned by the library. */
+typedef struct lattice_bins lattice_bins;
+
+typedef struct lsl_bins_info {
+    int64_t n_edges;        /* as given                                          */
+    int64_t n_nodes;
+    int64_t n_binned;       /* struts with w > 0, v_s != v_e, meeting the grid   */
+    int64_t total_pairs;    /* (slab, tile, strut) pairs over all slabs          */
+    int64_t max_group_pairs;
+    int64_t device_bytes;   /* device memory the handle holds now                */
+    int64_t peak_device_bytes;
+    int32_t dtype, tile, slab;
+    int32_t tiles_x, tiles_y, n_slabs, n_groups;
+    int32_t current_group;  /* group whose bucket lists are resident, or -1      */
+    double last_field_ms;   /* device time of the persistent field launches of
+                               the last slice_batch call (HIP events around the
+                               kernel on its stream); -1 if unavailable          */
+} lsl_bins_info;
+
+/* ---------------------------------------------------------------------------
+ * lattice_bin -- prepare a lattice for slicing (Sec. 4).
+ *
+ * Builds the paper's edge list sorted by the z of each strut's lower end
+ * (Sec. 4, the first of its two lists), the per-strut slab and tile ranges of
+ * the swept sphere of radius R around the strut (Sec. 4; only struts within R
+ * of p contribute, Sec. 3.2), and a plan that splits the slabs into groups
+ * of at most max_pairs bucket entries.  The first group's bucket lists are
+ * built at once; later groups are built when their slices are requested,
+ * reusing the active struts of the previous group (the active list of
+ * Eq. (8), Steps 2-3).
+ *
+ * Bin set (exact; evaluated in float64 in this operation order, no fused
+ * multiply-add): for each strut with ends a, b and each axis with origin o,
+ * step s, count n:  i0 = floor(((min(a,b) - R) - o) * (1/s) - 0.5),
+ * i1 = ceil(((max(a,b) + R) - o) * (1/s) - 0.5), clamped to [0, n-1]
+ * (strut dropped if empty).  Slab range [k0/slab, k1/slab], tile range
+ * [i0/tile, i1/tile] x [j0/tile, j1/tile].  A bucket (slab, tile_y, tile_x)
+ * lists the struts covering it in edge-list order.
+ *
+ * On success *out holds a new handle.  Synchronises `stream` (reads back the
+ * plan).  Errors: LSL_EINVAL (bad argument, edge index out of range,
+ * negative or non-finite weight, non-finite node used by an edge),
+ * LSL_ENOMEM, LSL_EDEVICE.
+ * ------------------------------------------------------------------------- */
+lsl_status lattice_bin(const lsl_lattice* lattice, const lsl_grid* grid,
+                       const lsl_bin_params* params, lattice_bins** out,
+                       void* stream);
+
+/* Frees the handle and its device memory (synchronises the device first).
+ * NULL is accepted. */
+lsl_status lattice_bins_free(lattice_bins* bins);
+
+/* Sizes and memory use of a handle.  `out` is [host]. */
+lsl_status lattice_bins_info(const lattice_bins* bins, lsl_bins_info* out);
+
+/* Slab range and pair count of plan group g.  Outputs are [host]. */
+lsl_status lattice_bins_group(const lattice_bins* bins, int32_t g,
+                              int32_t* slab_first, int32_t* slab_last,
+                              int64_t* pairs);
+
+/* Builds group g's bucket lists (if not resident) and copies them out:
+ * offsets [n_buckets + 1] int64 (bucket b = (slab - slab_first) * tiles_y *
+ * tiles_x + tile_y * tiles_x + tile_x) and ids [pairs] int32 original edge
+ * ids.  Either output may be NULL.  Stream-ordered; no synchronisation. */
+lsl_status lattice_bins_export(lattice_bins* bins, int32_t g, int64_t* offsets,
+                               int32_t* ids, void* stream);
+
+/* The edge list: original ids of the binned struts in ascending (z of the
+ * lower end, id) order, [n_binned] int32.  Stream-ordered. */
+lsl_status lattice_bins_order(const lattice_bins* bins, int32_t* order,
+                              void* stream);
+
+/* ---------------------------------------------------------------------------
+ * slice_field -- evaluate g (Eq. 6, closed form of Eq. 7 over arclength) at
+ * every pixel centre of planes k0 .. k0+nk-1 (Sec. 4, Step 4).
+ *
+ * field: [nk][H][W] of the lattice dtype (required).  bits: optional
+ * [nk][H][ceil(W/32)] uint32, bit (i % 32) of word i/32 set where
+ * field >= C (the binary image of Sec. 4).  Per pixel the sum runs over the
+ * struts of its tile's bucket in edge-list order; terms outside the support
+ * are exactly zero.  float32 sums are compensated.  Builds missing groups
+ * (stream-ordered, no synchronisation).  Errors: LSL_EINVAL (range outside
+ * [0, n_slices)), LSL_ENOMEM, LSL_EDEVICE.
+ * ------------------------------------------------------------------------- */
+lsl_status slice_field(lattice_bins* bins, int32_t k0, int32_t nk, void* field,
+                       uint32_t* bits, void* stream);
+
+/* Candidate and useful (non-zero term) pixel-strut pair counts of the field
+ * evaluation of planes k0 .. k0+nk-1 (the work slice_field does).  counts is
+ * [host] int64[3]: candidates, useful, pixels.  Synchronises `stream`. */
+lsl_status slice_field_stats(lattice_bins* bins, int32_t k0, int32_t nk,
+                             int64_t* counts, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * slice_contours -- marching squares on the binary images of nk planes
+ * (Sec. 4: rough boundary curves from the binary image).
+ *
+ * field: [nk][H][W] lattice dtype, inside where field >= C.  Cell (i,j),
+ * i < W-1, j < H-1, has corners (i,j), (i+1,j), (i+1,j+1), (i,j+1) with bits
+ * b0..b3 and case b0 | b1<<1 | b2<<2 | b3<<3.  Segments join edge midpoints,
+ * in grid units (pixel (i,j) at (i,j)), with the inside on the left; the two
+ * saddle cases keep the inside corners apart.  Cells are emitted row by row
+ * (j outer, i inner), a cell's segments in a fixed table order.
+ *
+ * segs: [capacity][4] float32 (x0, y0, x1, y1).  offsets: [nk + 1] int64,
+ * offsets[k] = first segment of plane k, offsets[nk] = total.  case_codes:
+ * optional [nk][H-1][W-1] uint8.  *total [host] receives the total.
+ * Synchronises `stream` (reads the total).  If total > capacity no segment
+ * is written, offsets and case codes are, and LSL_ECAPACITY is returned.
+ * ------------------------------------------------------------------------- */
+lsl_status slice_contours(const lattice_bins* bins, int32_t nk,
+                          const void* field, float* segs, int64_t capacity,
+                          int64_t* offsets, uint8_t* case_codes, int64_t* total,
+                          void* stream);
+
+/* ---------------------------------------------------------------------------
+ * slice_field_backward -- gradient of a loss of the sliced field.
+ *
+ * Given grad_field = dL/dg at the pixels of planes k0 .. k0+nk-1
+ * ([nk][H][W], lattice dtype), computes dL/dr_j = sum_p dL/dg(p) I_j(p) and
+ * dL/dv for every node by the chain rule through Eq. (6)-(7); the
+ * radius-tuning step of Sec. 5.3 adjusts exactly these weights.  Per-pixel
+ * fields are recomputed, not stored.  Reductions run in a fixed order
+ * (results are bitwise repeatable).
+ *
+ * grad_weight: [n_edges] lattice dtype (absent or unbinned struts get 0).
+ * grad_nodes: [n_nodes][3] lattice dtype.  Either may be NULL.
+ * accumulate: 0 overwrites the outputs, 1 adds to them.  Stream-ordered.
+ * ------------------------------------------------------------------------- */
+lsl_status slice_field_backward(lattice_bins* bins, int32_t k0, int32_t nk,
+                                const void* grad_field, void* grad_weight,
+                                void* grad_nodes, int32_t accumulate,
+                                void* stream);
+
+/* ---------------------------------------------------------------------------
+ * slice_batch -- planes k0 .. k0+nk-1 end to end (field, binary image,
+ * contours) with one persistent field launch per slab group: work items
+ * (slab, tile) are taken from a device queue in descending cost order, so
+ * planes with very different strut counts share the GPU evenly (Sec. 6.4:
+ * slicing time follows the number of struts meeting a plane).  Each group's
+ * launch sequence is captured once into a HIP graph and replayed.
+ *
+ * field: optional [nk][H][W]; when NULL the field lives in library scratch
+ * (one group at a time).  bits, segs, offsets, case_codes: as in
+ * slice_field / slice_contours.  Synchronises `stream` once at the end.
+ * LSL_ECAPACITY as in slice_contours (segments beyond capacity are not
+ * written; offsets are).
+ * ------------------------------------------------------------------------- */
+lsl_status slice_batch(lattice_bins* bins, int32_t k0, int32_t nk, void* field,
+                       uint32_t* bits, float* segs, int64_t capacity,
+                       int64_t* offsets, int64_t* total, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * slice_autotune -- choose tile and slab sizes by timing the field on
+ * sampled planes of this lattice and grid.  params is [host] in/out:
+ * nonzero fields are kept, zero fields are filled.  cache_path (optional,
+ * [host] C string) is a JSON file of earlier choices keyed by problem shape;
+ * a hit skips the timing.  Synchronises `stream`.  The field values do not
+ * depend on the choice (the same struts reach each pixel in the same order).
+ * ------------------------------------------------------------------------- */
+lsl_status slice_autotune(const lsl_lattice* lattice, const lsl_grid* grid,
+                          lsl_bin_params* params, const char* cache_path,
+                          void* stream);
+
+/* Static text for a status code. */
+const char* lsl_status_string(lsl_status s);
+/* Message of the calling thread's last failed call ("" if none). */
+const char* lsl_last_error(void);
+/* Library version string. */
+const char* lsl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSL_H */

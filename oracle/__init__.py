@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY.  This package is a plain, slow, float64 restatement
 of what the slicing path computes, written from the paper (Liu et al.,
 "Memory-Efficient Modeling and Slicing of Large-Scale Adaptive Lattice
-Structures", Secs. 2-3).  Only the test suite, the smoke check and the
+Structures", Secs. 3-4).  Only the test suite, the smoke check and the
 benchmark's CPU-baseline leg may import it.  It shares no code with the
 native library and imports nothing from it.
 
@@ -12,7 +12,7 @@ Modules
   slicer    -- slice heights, active set (Eq. 8), the Steps 1-6 sweep,
                per-slice field and the inside test
   binning   -- the (slab, tile, strut) bin set the native binning must equal
-  contours  -- marching squares on the binary slice image (Sec. 3)
+  contours  -- marching squares on the binary slice image (Sec. 4)
   gradient  -- derivatives of a pixel-weighted field sum with respect to
                strut weights and node positions
 

@@ -2,8 +2,8 @@
 
 Test infrastructure (see the package docstring).
 
-Sec. 2.2: only struts within distance R of p contribute to the field at p.
-Sec. 3: a strut's swept sphere of radius R bounds the region it reaches, and
+Sec. 3.2: only struts within distance R of p contribute to the field at p.
+Sec. 4: a strut's swept sphere of radius R bounds the region it reaches, and
 the edge list is kept sorted by the z of each edge's lower end.  The binning
 turns both facts into integer sets, evaluated in float64 with exactly the
 operation order written here (no fused multiply-add), so that any

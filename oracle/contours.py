@@ -1,4 +1,4 @@
-"""Marching squares on the binary slice image (Sec. 3: rough boundary curves
+"""Marching squares on the binary slice image (Sec. 4: rough boundary curves
 from the binary image).
 
 Test infrastructure (see the package docstring).

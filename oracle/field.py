@@ -26,7 +26,7 @@ def kernel(dist, R: float):
 def strut_integral(P, vs, ve, R: float) -> np.ndarray:
     """Integral of the kernel over the edge (vs, ve) for each point of P.
 
-    Sec. 2.2, Eq. (6)-(7).  For a query point p, the line of the edge meets
+    Sec. 3.2, Eq. (6)-(7).  For a query point p, the line of the edge meets
     the sphere of radius R around p at p1 and p2 (p1 before p2 in the
     direction vs -> ve); s1, s2 are the parameters of the edge ends along the
     chord x(s) = (1 - s) p1 + s p2, clipped to [0, 1]; with l = |p2 - p1| and
@@ -40,24 +40,24 @@ def strut_integral(P, vs, ve, R: float) -> np.ndarray:
     when the line misses the open ball (no chord), when the edge has zero
     length, or when the edge lies outside the chord (s2 <= s1).
 
-    P: [..., 3] points; vs, ve: [3].  Returns float64 [...].
+    P, vs, ve: [..., 3] arrays broadcast against each other (many points
+    and one strut, or one point and many struts).  Returns float64 [...].
     """
     P = np.asarray(P, dtype=np.float64)
     vs = np.asarray(vs, dtype=np.float64)
     ve = np.asarray(ve, dtype=np.float64)
-    shape = P.shape[:-1]
-    P = P.reshape(-1, 3)
+    shape = np.broadcast_shapes(P.shape, vs.shape, ve.shape)[:-1]
+    P, vs, ve = (np.broadcast_to(x, shape + (3,)).reshape(-1, 3) for x in (P, vs, ve))
     d = ve - vs
-    L2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2]
-    if L2 == 0.0:
-        return np.zeros(shape)
-    u = d / np.sqrt(L2)
+    L2 = _dot3(d, d)
+    live = L2 > 0.0                       # zero-length struts add nothing
+    u = d / np.sqrt(np.where(live, L2, 1.0))[:, None]
     # foot of p on the line, and squared distance of p from the line
     w = P - vs
-    t0 = _dot3(w, u[None, :])
+    t0 = _dot3(w, u)
     perp = w - t0[:, None] * u
     dperp2 = _dot3(perp, perp)
-    hit = dperp2 < R * R
+    hit = live & (dperp2 < R * R)
     h = np.sqrt(np.where(hit, R * R - dperp2, 0.0))
     foot = vs + t0[:, None] * u
     p1 = foot - h[:, None] * u
@@ -130,3 +130,15 @@ def line_integral_quadrature(p, vs, ve, R: float, epsabs=1e-13, epsrel=1e-11):
         v, _ = quad(f, lo, hi, epsabs=epsabs, epsrel=epsrel, limit=200)
         total += v
     return total
+
+
+def field_at_point(p, nodes, edges, weight, R: float, struts=None) -> float:
+    """g at one point p: every strut's integral at p (one array operation
+    over the struts) times its weight, summed in ascending strut id."""
+    nodes = np.asarray(nodes, dtype=np.float64)
+    ids = np.arange(len(edges)) if struts is None else np.asarray(struts)
+    A = nodes[edges[ids, 0]]
+    B = nodes[edges[ids, 1]]
+    I = strut_integral(np.asarray(p, dtype=np.float64)[None, :], A, B, R)
+    terms = np.asarray(weight, dtype=np.float64)[ids] * I
+    return float(np.cumsum(terms)[-1]) if len(terms) else 0.0

@@ -2,7 +2,7 @@
 
 Test infrastructure (see the package docstring).
 
-Sec. 4.4 tunes strut weights r_i (and the framework moves nodes) to match a
+Sec. 5.3 tunes strut weights r_i (and the framework moves nodes) to match a
 target density, which needs the derivative of a loss of the sliced field.
 For a loss L(g) over sample points p with G(p) = dL/dg(p), the chain rule
 gives
@@ -112,3 +112,38 @@ def soft_occupancy_loss(g, target, C: float, tau: float) -> float:
     g = np.asarray(g, dtype=np.float64)
     s = 1.0 / (1.0 + np.exp(-(g - C) / tau))
     return float(np.sum((s - target) ** 2))
+
+
+def slice_vjp(nodes, edges, weight, R: float, grid, ks, G):
+    """field_vjp over the pixel centres of planes ks with G [len(ks), H, W]:
+    each active strut (Eq. 8) is evaluated over the window of pixels its
+    support can reach (outside it every term and partial is exactly zero)."""
+    from .slicer import active_set, strut_z_range, _pixel_window
+    nodes64 = np.asarray(nodes, dtype=np.float64)
+    w = np.asarray(weight, dtype=np.float64)
+    gw = np.zeros(len(edges))
+    gn = np.zeros((len(nodes64), 3))
+    zlo, zhi = strut_z_range(nodes64, edges)
+    xs, ys = grid.pixel_x(), grid.pixel_y()
+    for kk, k in enumerate(ks):
+        z = float(grid.slice_z(k))
+        Gk = np.asarray(G[kk], dtype=np.float64)
+        for i in active_set(zlo, zhi, R, z):
+            if w[i] == 0.0:
+                continue
+            ia, ib = int(edges[i, 0]), int(edges[i, 1])
+            a, b = nodes64[ia], nodes64[ib]
+            ix0, ix1 = _pixel_window(min(a[0], b[0]) - R, max(a[0], b[0]) + R,
+                                     grid.x0, grid.dx, grid.W)
+            iy0, iy1 = _pixel_window(min(a[1], b[1]) - R, max(a[1], b[1]) + R,
+                                     grid.y0, grid.dy, grid.H)
+            if ix0 > ix1 or iy0 > iy1:
+                continue
+            X, Y = np.meshgrid(xs[ix0:ix1 + 1], ys[iy0:iy1 + 1], indexing="xy")
+            P = np.stack([X, Y, np.full_like(X, z)], axis=-1).reshape(-1, 3)
+            g = Gk[iy0:iy1 + 1, ix0:ix1 + 1].reshape(-1)
+            I, dA, dB = strut_partials(P, a, b, R)
+            gw[i] += np.dot(g, I)
+            gn[ia] += w[i] * (g @ dA)
+            gn[ib] += w[i] * (g @ dB)
+    return gw, gn

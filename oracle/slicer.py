@@ -1,4 +1,4 @@
-"""The streaming slicer of Sec. 3, in float64.
+"""The streaming slicer of Sec. 4, in float64.
 
 Test infrastructure (see the package docstring).
 

@@ -1,0 +1,197 @@
+"""Python binding of liblsl with the ABI's names.  Torch supplies device
+memory and the current stream; every step of the slicing path runs in the
+native library's kernels."""
+from __future__ import annotations
+
+import ctypes
+from ctypes import byref, c_int32, c_int64, c_void_p
+
+import torch
+
+from . import _native as N
+
+_DTYPES = {torch.float32: N.LSL_F32, torch.float64: N.LSL_F64}
+
+
+def _stream(stream=None) -> c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> c_void_p:
+    return c_void_p(0 if t is None else t.data_ptr())
+
+
+def _grid_struct(grid) -> N.LslGrid:
+    g = N.LslGrid()
+    for f in ("x0", "y0", "dx", "dy", "z0", "dz"):
+        setattr(g, f, float(getattr(grid, f)))
+    g.W, g.H, g.n_slices = int(grid.W), int(grid.H), int(grid.n_slices)
+    return g
+
+
+def _lattice_struct(nodes, edges, weight, R, C) -> N.LslLattice:
+    if nodes.dtype not in _DTYPES:
+        raise TypeError("nodes must be float32 or float64")
+    for t, name in ((nodes, "nodes"), (edges, "edges"), (weight, "weight")):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous CUDA tensor")
+    if weight.dtype != nodes.dtype:
+        raise TypeError("weight must have the dtype of nodes")
+    if edges.dtype != torch.int32:
+        raise TypeError("edges must be int32")
+    if nodes.dim() != 2 or nodes.shape[1] != 3 or edges.dim() != 2 or edges.shape[1] != 2:
+        raise ValueError("nodes must be [N,3] and edges [E,2]")
+    if weight.shape != (edges.shape[0],):
+        raise ValueError("weight must be [E]")
+    L = N.LslLattice()
+    L.n_nodes, L.n_edges = nodes.shape[0], edges.shape[0]
+    L.dtype = _DTYPES[nodes.dtype]
+    L.nodes, L.edges, L.weight = nodes.data_ptr(), edges.data_ptr(), weight.data_ptr()
+    L.R, L.C = float(R), float(C)
+    return L
+
+
+class Bins:
+    """Owner of a lattice_bins handle."""
+
+    def __init__(self, handle: int, dtype, grid, R: float, C: float, n_nodes: int,
+                 n_edges: int):
+        self.handle = c_void_p(handle)
+        self.dtype = dtype
+        self.grid = grid
+        self.R, self.C = R, C
+        self.n_nodes, self.n_edges = n_nodes, n_edges
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            N.lib().lattice_bins_free(h)
+            self.handle = None
+
+    def info(self) -> dict:
+        i = N.LslBinsInfo()
+        N.check(N.lib().lattice_bins_info(self.handle, byref(i)), "lattice_bins_info")
+        return {f: getattr(i, f) for f, _ in N.LslBinsInfo._fields_}
+
+    def group(self, g: int):
+        s0, s1, p = c_int32(), c_int32(), c_int64()
+        N.check(N.lib().lattice_bins_group(self.handle, g, byref(s0), byref(s1), byref(p)),
+                "lattice_bins_group")
+        return s0.value, s1.value, p.value
+
+    def export(self, g: int):
+        """(offsets int64 [n_buckets+1], ids int32 [pairs]) of group g."""
+        s0, s1, pairs = self.group(g)
+        info = self.info()
+        nb = (s1 - s0 + 1) * info["tiles_x"] * info["tiles_y"]
+        dev = torch.device("cuda")
+        off = torch.empty(nb + 1, dtype=torch.int64, device=dev)
+        ids = torch.empty(max(pairs, 1), dtype=torch.int32, device=dev)
+        N.check(N.lib().lattice_bins_export(self.handle, g, _ptr(off), _ptr(ids), _stream()),
+                "lattice_bins_export")
+        return off, ids[:pairs]
+
+    def order(self):
+        n = self.info()["n_binned"]
+        out = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+        N.check(N.lib().lattice_bins_order(self.handle, _ptr(out), _stream()), "lattice_bins_order")
+        return out[:n]
+
+
+def lattice_bin(nodes, edges, weight, R: float, C: float, grid, *, tile: int = 0,
+                slab: int = 0, max_pairs: int = 0, stream=None) -> Bins:
+    L = _lattice_struct(nodes, edges, weight, R, C)
+    g = _grid_struct(grid)
+    p = N.LslBinParams(int(tile), int(slab), int(max_pairs))
+    h = c_void_p()
+    N.check(N.lib().lattice_bin(byref(L), byref(g), byref(p), byref(h), _stream(stream)),
+            "lattice_bin")
+    return Bins(h.value, nodes.dtype, grid, float(R), float(C), nodes.shape[0], edges.shape[0])
+
+
+def slice_field(bins: Bins, k0: int, nk: int, out=None, bits: bool | torch.Tensor = False,
+                stream=None):
+    g = bins.grid
+    if out is None:
+        out = torch.empty((nk, g.H, g.W), dtype=bins.dtype, device="cuda")
+    bt = None
+    if isinstance(bits, torch.Tensor):
+        bt = bits
+    elif bits:
+        bt = torch.empty((nk, g.H, (g.W + 31) // 32), dtype=torch.int32, device="cuda")
+    N.check(N.lib().slice_field(bins.handle, int(k0), int(nk), _ptr(out), _ptr(bt),
+                                _stream(stream)), "slice_field")
+    return (out, bt) if bt is not None else out
+
+
+def slice_field_stats(bins: Bins, k0: int, nk: int, stream=None) -> dict:
+    c = (c_int64 * 3)()
+    N.check(N.lib().slice_field_stats(bins.handle, int(k0), int(nk), c, _stream(stream)),
+            "slice_field_stats")
+    return {"candidates": c[0], "useful": c[1], "pixels": c[2]}
+
+
+def slice_contours(bins: Bins, field, capacity: int | None = None, case_codes: bool = False,
+                   stream=None):
+    """Marching squares of planes field[nk,H,W] -> (segs float32 [n,4],
+    offsets int64 [nk+1], case codes uint8 [nk,H-1,W-1] or None)."""
+    nk = field.shape[0]
+    g = bins.grid
+    off = torch.empty(nk + 1, dtype=torch.int64, device="cuda")
+    codes = torch.empty((nk, g.H - 1, g.W - 1), dtype=torch.uint8, device="cuda") \
+        if case_codes else None
+    total = c_int64()
+    L = N.lib()
+    if capacity is None:
+        st = L.slice_contours(bins.handle, nk, _ptr(field), c_void_p(0), 0, _ptr(off),
+                              _ptr(codes), byref(total), _stream(stream))
+        if st not in (N.LSL_OK, N.LSL_ECAPACITY):
+            N.check(st, "slice_contours")
+        capacity = total.value
+    segs = torch.empty((max(capacity, 1), 4), dtype=torch.float32, device="cuda")
+    N.check(L.slice_contours(bins.handle, nk, _ptr(field), _ptr(segs), int(capacity), _ptr(off),
+                             _ptr(codes), byref(total), _stream(stream)), "slice_contours")
+    return segs[:total.value], off, codes
+
+
+def slice_field_backward(bins: Bins, k0: int, nk: int, grad_field, grad_weight=None,
+                         grad_nodes=None, accumulate: bool = False, stream=None):
+    if grad_weight is None:
+        grad_weight = torch.empty(bins.n_edges, dtype=bins.dtype, device="cuda")
+    if grad_nodes is None:
+        grad_nodes = torch.empty((bins.n_nodes, 3), dtype=bins.dtype, device="cuda")
+    if not grad_field.is_contiguous() or grad_field.dtype != bins.dtype:
+        raise ValueError("grad_field must be contiguous with the lattice dtype")
+    N.check(N.lib().slice_field_backward(bins.handle, int(k0), int(nk), _ptr(grad_field),
+                                         _ptr(grad_weight), _ptr(grad_nodes),
+                                         1 if accumulate else 0, _stream(stream)),
+            "slice_field_backward")
+    return grad_weight, grad_nodes
+
+
+def slice_batch(bins: Bins, k0: int, nk: int, field=None, bits=None, capacity: int = 0,
+                segs=None, offsets=None, stream=None):
+    """Persistent, graph-captured slicing of planes [k0, k0+nk): returns
+    (status, total segments, segs, offsets)."""
+    if offsets is None:
+        offsets = torch.empty(nk + 1, dtype=torch.int64, device="cuda")
+    if segs is None and capacity > 0:
+        segs = torch.empty((capacity, 4), dtype=torch.float32, device="cuda")
+    total = c_int64()
+    st = N.lib().slice_batch(bins.handle, int(k0), int(nk), _ptr(field), _ptr(bits), _ptr(segs),
+                             int(capacity), _ptr(offsets), byref(total), _stream(stream))
+    if st not in (N.LSL_OK, N.LSL_ECAPACITY):
+        N.check(st, "slice_batch")
+    return st, total.value, segs, offsets
+
+
+def slice_autotune(nodes, edges, weight, R: float, C: float, grid, cache_path: str | None = None,
+                   tile: int = 0, slab: int = 0, stream=None) -> dict:
+    L = _lattice_struct(nodes, edges, weight, R, C)
+    g = _grid_struct(grid)
+    p = N.LslBinParams(int(tile), int(slab), 0)
+    path = cache_path.encode() if cache_path else None
+    N.check(N.lib().slice_autotune(byref(L), byref(g), byref(p), path, _stream(stream)),
+            "slice_autotune")
+    return {"tile": p.tile, "slab": p.slab}

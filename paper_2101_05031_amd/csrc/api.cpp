@@ -1,0 +1,1009 @@
+// C ABI of liblsl: handle management, argument validation, slab-group
+// planning and the entry points declared in include/lsl.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace lsl {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+const char* last_error() { return g_err.c_str(); }
+
+}  // namespace lsl
+
+using namespace lsl;
+
+namespace {
+
+struct Group {
+    int32_t sa, sb;
+    uint64_t pairs;
+    uint32_t n_active;
+    uint32_t n_buckets;
+};
+
+}  // namespace
+
+struct lattice_bins {
+    int dtype = LSL_F32;
+    int64_t n_nodes = 0, n_edges = 0;
+    uint32_t n_binned = 0;
+    double R = 0, C = 0;
+    lsl_grid grid{};
+    double inv_dx = 0, inv_dy = 0, inv_dz = 0;
+    int32_t tile = 16, slab = 8, ntx = 0, nty = 0, n_slabs = 0;
+    int64_t max_pairs = 0;
+
+    std::vector<uint64_t> pairs_slab;   // pairs of each slab
+    std::vector<uint32_t> win_end;      // # struts whose first slab <= s
+    std::vector<uint32_t> gone;         // # struts whose last slab < s
+    std::vector<Group> groups;
+    int cur_group = -1;
+    int cur_buf = 0;
+    uint64_t total_pairs = 0, max_group_pairs = 0;
+
+    // per-strut arrays in edge-list order
+    void* rec = nullptr;
+    uint32_t* perm = nullptr;
+    SRange* ranges = nullptr;
+    void* w = nullptr;
+    int2* ends = nullptr;
+
+    // resident group
+    uint32_t* active[2] = {nullptr, nullptr};
+    uint32_t* eoff = nullptr;
+    uint32_t* offsets = nullptr;
+    uint32_t* ids = nullptr;
+    uint32_t* inv = nullptr;
+    uint32_t* owner = nullptr;
+    uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
+    uint32_t* tmp = nullptr;
+    uint32_t* blk = nullptr;
+    size_t cap_active = 0, cap_pairs = 0, cap_buckets = 0;
+
+    // backward
+    void* partial = nullptr;
+    double* acc = nullptr;
+    uint32_t* node_off = nullptr;
+    uint32_t* node_inc = nullptr;
+
+    // misc
+    unsigned long long* stats = nullptr;
+    unsigned long long* ctmp = nullptr;
+    size_t ctmp_elems = 0;
+    uint32_t* queue_buf = nullptr;     // persistent path: keys/vals/alternates + counter
+    size_t queue_cap = 0;
+    void* batch_field = nullptr;
+    size_t batch_field_bytes = 0;
+    std::vector<std::pair<void*, size_t>> allocs;
+    int64_t dev_bytes = 0, peak_bytes = 0;
+
+    // persistent path: captured graphs keyed by their launch arguments
+    struct GraphEntry {
+        std::vector<unsigned char> key;
+        hipGraphExec_t exec;
+        hipEvent_t e0, e1;          // around the persistent field kernel (may be null)
+    };
+    double last_field_ms = -1.0;
+    std::vector<GraphEntry> graphs;
+
+    ~lattice_bins() {
+        hipDeviceSynchronize();
+        drop_graphs();
+        for (auto& a : allocs) hipFree(a.first);
+    }
+
+    lsl_status alloc(void** p, size_t bytes) {
+        *p = nullptr;
+        if (bytes == 0) bytes = 16;
+        bytes = (bytes + 255) & ~size_t(255);
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) {
+            hipGetLastError();
+            *p = nullptr;
+            set_error("device allocation of " + std::to_string(bytes) + " bytes failed: " +
+                      hipGetErrorString(e));
+            return LSL_ENOMEM;
+        }
+        allocs.emplace_back(*p, bytes);
+        dev_bytes += (int64_t)bytes;
+        peak_bytes = std::max(peak_bytes, dev_bytes);
+        return LSL_OK;
+    }
+    template <typename T>
+    lsl_status alloc_t(T** p, size_t n) {
+        return alloc((void**)p, n * sizeof(T));
+    }
+    void release(void* p) {
+        if (!p) return;
+        for (size_t i = 0; i < allocs.size(); ++i)
+            if (allocs[i].first == p) {
+                hipFree(p);
+                dev_bytes -= (int64_t)allocs[i].second;
+                allocs.erase(allocs.begin() + (long)i);
+                return;
+            }
+    }
+    size_t esize() const { return dtype == LSL_F64 ? 8 : 4; }
+    void drop_graphs() {
+        for (auto& g : graphs) {
+            hipGraphExecDestroy(g.exec);
+            if (g.e0) hipEventDestroy(g.e0);
+            if (g.e1) hipEventDestroy(g.e1);
+        }
+        graphs.clear();
+    }
+};
+
+namespace {
+
+#define LSL_CHECK(cond, msg)        \
+    do {                            \
+        if (!(cond)) {              \
+            set_error(msg);         \
+            return LSL_EINVAL;      \
+        }                           \
+    } while (0)
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
+
+lsl_status check_lattice(const lsl_lattice* L) {
+    LSL_CHECK(L != nullptr, "lattice is NULL");
+    LSL_CHECK(L->dtype == LSL_F32 || L->dtype == LSL_F64, "lattice dtype must be LSL_F32 or LSL_F64");
+    LSL_CHECK(L->n_nodes >= 1, "n_nodes must be >= 1");
+    LSL_CHECK(L->n_edges >= 0, "n_edges must be >= 0");
+    LSL_CHECK(L->n_edges < (int64_t)0x7fffffff, "n_edges must be < 2^31");
+    LSL_CHECK(L->n_nodes < (int64_t)0x7fffffff, "n_nodes must be < 2^31");
+    LSL_CHECK(L->nodes != nullptr, "nodes is NULL");
+    LSL_CHECK(L->n_edges == 0 || L->edges != nullptr, "edges is NULL");
+    LSL_CHECK(L->n_edges == 0 || L->weight != nullptr, "weight is NULL");
+    LSL_CHECK(finite_pos(L->R), "R must be finite and > 0");
+    LSL_CHECK(finite_pos(L->C), "C must be finite and > 0");
+    return LSL_OK;
+}
+
+lsl_status check_grid(const lsl_grid* g) {
+    LSL_CHECK(g != nullptr, "grid is NULL");
+    LSL_CHECK(std::isfinite(g->x0) && std::isfinite(g->y0) && std::isfinite(g->z0),
+              "grid origin must be finite");
+    LSL_CHECK(finite_pos(g->dx) && finite_pos(g->dy) && finite_pos(g->dz),
+              "grid steps must be finite and > 0");
+    LSL_CHECK(g->W >= 2 && g->H >= 2, "grid W and H must be >= 2");
+    LSL_CHECK(g->W <= 65536 && g->H <= 65536, "grid W and H must be <= 65536");
+    LSL_CHECK(g->n_slices >= 1, "grid n_slices must be >= 1");
+    return LSL_OK;
+}
+
+lsl_status check_params(const lsl_bin_params* p, int32_t* tile, int32_t* slab, int64_t* mp) {
+    *tile = 16;
+    *slab = 8;
+    *mp = (int64_t)1 << 30;
+    if (!p) return LSL_OK;
+    if (p->tile) *tile = p->tile;
+    if (p->slab) *slab = p->slab;
+    if (p->max_pairs) *mp = p->max_pairs;
+    LSL_CHECK(*tile == 8 || *tile == 16 || *tile == 32 || *tile == 64,
+              "tile must be 8, 16, 32 or 64");
+    LSL_CHECK(*slab >= 1 && *slab <= 16, "slab must be in 1..16");
+    LSL_CHECK(*mp >= 1 && *mp <= (int64_t)0x7fffffff, "max_pairs must be in [1, 2^31)");
+    return LSL_OK;
+}
+
+hipStream_t S(void* s) { return (hipStream_t)s; }
+
+lsl_status plan_groups(lattice_bins* b, const std::vector<uint32_t>& cnt_lo,
+                       const std::vector<uint32_t>& cnt_hi,
+                       const std::vector<unsigned long long>& diff) {
+    const int ns = b->n_slabs;
+    b->pairs_slab.assign(ns, 0);
+    b->win_end.assign(ns, 0);
+    b->gone.assign(ns, 0);
+    uint64_t run = 0;
+    uint64_t lo = 0, hi = 0;
+    for (int s = 0; s < ns; ++s) {
+        run += diff[s];
+        b->pairs_slab[s] = run;
+        lo += cnt_lo[s];
+        b->win_end[s] = (uint32_t)lo;
+        b->gone[s] = (uint32_t)hi;
+        hi += cnt_hi[s];
+    }
+    b->groups.clear();
+    b->total_pairs = 0;
+    b->max_group_pairs = 0;
+    const uint64_t per_slab_buckets = (uint64_t)b->ntx * (uint64_t)b->nty;
+    int s = 0;
+    while (s < ns) {
+        Group g;
+        g.sa = s;
+        uint64_t p = b->pairs_slab[s];
+        int e = s;
+        while (e + 1 < ns && p + b->pairs_slab[e + 1] <= (uint64_t)b->max_pairs &&
+               (uint64_t)(e + 2 - s) * per_slab_buckets < 0x7fffffffull)
+            p += b->pairs_slab[++e];
+        g.sb = e;
+        g.pairs = p;
+        if (p >= 0xfffffff0ull) {
+            set_error("one slab holds more than 2^32 (slab, tile, strut) pairs; use larger tiles "
+                      "or thinner slabs");
+            return LSL_ENOMEM;
+        }
+        const uint64_t nbk = (uint64_t)(e - s + 1) * per_slab_buckets;
+        if (nbk >= 0x7fffffffull) {
+            set_error("too many tiles per slab");
+            return LSL_EINVAL;
+        }
+        g.n_buckets = (uint32_t)nbk;
+        g.n_active = b->win_end[e] - b->gone[s];
+        b->groups.push_back(g);
+        b->total_pairs += p;
+        b->max_group_pairs = std::max<uint64_t>(b->max_group_pairs, p);
+        s = e + 1;
+    }
+    return LSL_OK;
+}
+
+lsl_status ensure_group(lattice_bins* b, int g, hipStream_t st) {
+    if (g == b->cur_group) return LSL_OK;
+    const Group& G = b->groups[g];
+    GroupBuffers gb{};
+    gb.ranges = b->ranges;
+    const bool incremental = b->cur_group >= 0 && b->cur_group == g - 1;
+    if (incremental) {
+        const Group& P = b->groups[g - 1];
+        gb.prev_active = b->active[b->cur_buf];
+        gb.n_prev = P.n_active;
+        gb.range_lo = b->win_end[P.sb];
+    } else {
+        gb.prev_active = nullptr;
+        gb.n_prev = 0;
+        gb.range_lo = 0;
+    }
+    gb.range_hi = b->win_end[G.sb];
+    const int out = incremental ? 1 - b->cur_buf : 0;
+    gb.active = b->active[out];
+    gb.n_active = G.n_active;
+    gb.sa = G.sa;
+    gb.sb = G.sb;
+    gb.ntx = b->ntx;
+    gb.nty = b->nty;
+    gb.n_pairs = (uint32_t)G.pairs;
+    gb.n_buckets = G.n_buckets;
+    gb.eoff = b->eoff;
+    gb.offsets = b->offsets;
+    gb.ids = b->ids;
+    gb.inv = b->inv;
+    gb.owner = b->owner;
+    gb.k0 = b->k0;
+    gb.v0 = b->v0;
+    gb.k1 = b->k1;
+    gb.v1 = b->v1;
+    gb.tmp = b->tmp;
+    gb.blk = b->blk;
+    b->cur_group = -1;   // invalid until the launches below are enqueued
+    LSL_TRY(bin_group(gb, st));
+    b->cur_group = g;
+    b->cur_buf = out;
+    return LSL_OK;
+}
+
+FieldArgs field_args(const lattice_bins* b, int32_t k0, int32_t nk, void* field) {
+    FieldArgs a{};
+    a.rec = b->rec;
+    a.offsets = b->offsets;
+    a.ids = b->ids;
+    a.n_binned = b->n_binned;
+    a.ntx = b->ntx;
+    a.nty = b->nty;
+    a.tile = b->tile;
+    a.slab = b->slab;
+    a.k0 = k0;
+    a.nk = nk;
+    a.W = b->grid.W;
+    a.H = b->grid.H;
+    a.x0 = b->grid.x0;
+    a.y0 = b->grid.y0;
+    a.dx = b->grid.dx;
+    a.dy = b->grid.dy;
+    a.z0 = b->grid.z0;
+    a.dz = b->grid.dz;
+    a.R = b->R;
+    a.field = field;
+    return a;
+}
+
+// Calls fn(group index, first slab, last slab) for every group meeting the
+// slabs of planes [k0, k0+nk).
+template <typename Fn>
+lsl_status for_groups(lattice_bins* b, int32_t k0, int32_t nk, Fn fn) {
+    const int s_first = k0 / b->slab, s_last = (k0 + nk - 1) / b->slab;
+    for (size_t g = 0; g < b->groups.size(); ++g) {
+        const Group& G = b->groups[g];
+        if (G.sb < s_first || G.sa > s_last) continue;
+        LSL_TRY(fn((int)g, std::max(G.sa, s_first), std::min(G.sb, s_last)));
+    }
+    return LSL_OK;
+}
+
+lsl_status check_range(const lattice_bins* b, int32_t k0, int32_t nk) {
+    LSL_CHECK(b != nullptr, "bins handle is NULL");
+    LSL_CHECK(k0 >= 0 && nk >= 1 && (int64_t)k0 + nk <= b->grid.n_slices,
+              "plane range must lie in [0, n_slices)");
+    return LSL_OK;
+}
+
+__global__ void k_u32_to_i64(const uint32_t* in, int64_t* out, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (int64_t)in[i];
+}
+
+__global__ void k_ids_to_edges(const uint32_t* ids, const uint32_t* perm, int32_t* out, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (int32_t)perm[ids[i]];
+}
+
+__global__ void k_copy_i32(const uint32_t* in, int32_t* out, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (int32_t)in[i];
+}
+
+unsigned nblk(size_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* lsl_status_string(lsl_status s) {
+    switch (s) {
+        case LSL_OK: return "ok";
+        case LSL_EINVAL: return "invalid argument";
+        case LSL_ENOMEM: return "out of device memory";
+        case LSL_ECAPACITY: return "output capacity exceeded";
+        case LSL_EDEVICE: return "device error";
+        case LSL_EINTERNAL: return "internal error";
+        default: return "unknown status";
+    }
+}
+
+const char* lsl_last_error(void) { return lsl::last_error(); }
+
+const char* lsl_version(void) { return "liblsl 0.1 (gfx950)"; }
+
+lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_params* P,
+                       lattice_bins** out, void* stream) {
+    set_error("");
+    LSL_CHECK(out != nullptr, "out is NULL");
+    *out = nullptr;
+    LSL_TRY(check_lattice(L));
+    LSL_TRY(check_grid(G));
+    int32_t tile, slab;
+    int64_t mp;
+    LSL_TRY(check_params(P, &tile, &slab, &mp));
+    hipStream_t st = S(stream);
+
+    lattice_bins* b = new lattice_bins();
+    b->dtype = L->dtype;
+    b->n_nodes = L->n_nodes;
+    b->n_edges = L->n_edges;
+    b->R = L->R;
+    b->C = L->C;
+    b->grid = *G;
+    b->inv_dx = 1.0 / G->dx;
+    b->inv_dy = 1.0 / G->dy;
+    b->inv_dz = 1.0 / G->dz;
+    b->tile = tile;
+    b->slab = slab;
+    b->max_pairs = mp;
+    b->ntx = (G->W + tile - 1) / tile;
+    b->nty = (G->H + tile - 1) / tile;
+    b->n_slabs = (G->n_slices + slab - 1) / slab;
+    const size_t E = (size_t)L->n_edges;
+    const int ns = b->n_slabs;
+
+    auto fail = [&](lsl_status s) {
+        delete b;
+        return s;
+    };
+    lsl_status s;
+
+    // ---- prep: ranges, sort keys, plan histograms
+    uint32_t *klo = nullptr, *khi = nullptr, *vals = nullptr, *ka = nullptr, *va = nullptr;
+    uint32_t *cnt = nullptr, *stmp = nullptr;
+    SRange* rid = nullptr;
+    unsigned long long* diff = nullptr;
+    const size_t En = std::max<size_t>(E, 1);
+    if ((s = b->alloc_t(&klo, En)) || (s = b->alloc_t(&vals, En)) || (s = b->alloc_t(&ka, En)) ||
+        (s = b->alloc_t(&va, En)) || (s = b->alloc_t(&rid, En)) ||
+        (s = b->alloc_t(&cnt, 2 * (size_t)ns + 4)) || (s = b->alloc_t(&diff, (size_t)ns + 1)) ||
+        (s = b->alloc_t(&stmp, radix_tmp_elems(En))))
+        return fail(s);
+    if (L->dtype == LSL_F64 && (s = b->alloc_t(&khi, En))) return fail(s);
+    uint32_t* cnt_lo = cnt;
+    uint32_t* cnt_hi = cnt + ns;
+    uint32_t* counters = cnt + 2 * ns;   // [0] n_binned, [1] err
+    if ((s = fill_u32(cnt, 0u, 2 * (size_t)ns + 4, st)) ||
+        (s = fill_bytes0(diff, ((size_t)ns + 1) * 8, st)))
+        return fail(s);
+    PrepArgs pa{};
+    pa.nodes = L->nodes;
+    pa.edges = L->edges;
+    pa.weight = L->weight;
+    pa.n_nodes = L->n_nodes;
+    pa.n_edges = L->n_edges;
+    pa.R = L->R;
+    pa.x0 = G->x0;
+    pa.y0 = G->y0;
+    pa.z0 = G->z0;
+    pa.inv_dx = b->inv_dx;
+    pa.inv_dy = b->inv_dy;
+    pa.inv_dz = b->inv_dz;
+    pa.W = G->W;
+    pa.H = G->H;
+    pa.S = G->n_slices;
+    pa.tile = tile;
+    pa.slab = slab;
+    pa.n_slabs = ns;
+    pa.key_lo = klo;
+    pa.key_hi = khi;
+    pa.vals = vals;
+    pa.ranges = rid;
+    pa.cnt_lo = cnt_lo;
+    pa.cnt_hi = cnt_hi;
+    pa.pair_diff = diff;
+    pa.n_binned = counters;
+    pa.err = counters + 1;
+    if ((s = launch_prep(L->dtype, pa, st))) return fail(s);
+
+    // edge list: stable sort by the lower end's z (64-bit keys in two passes)
+    int which = 0;
+    uint32_t* perm_src = vals;
+    if (E > 0) {
+        if ((s = radix_sort_pairs(klo, vals, ka, va, E, 32, stmp, &which, st))) return fail(s);
+        uint32_t* sv = which ? va : vals;
+        if (L->dtype == LSL_F64) {
+            uint32_t* sk = which ? ka : klo;        // low words, sorted (unused now)
+            uint32_t* hk = which ? klo : ka;        // free buffer for gathered high words
+            uint32_t* hv = which ? vals : va;       // free buffer for the carried values
+            if ((s = launch_gather_u32(khi, sv, hk, E, st))) return fail(s);
+            (void)sk;
+            int w2 = 0;
+            if ((s = radix_sort_pairs(hk, sv, khi, hv, E, 32, stmp, &w2, st))) return fail(s);
+            sv = w2 ? hv : sv;
+        }
+        perm_src = sv;
+    }
+
+    // read the plan back
+    std::vector<uint32_t> h_cnt(2 * (size_t)ns + 4);
+    std::vector<unsigned long long> h_diff((size_t)ns + 1);
+    hipError_t he = hipMemcpyAsync(h_cnt.data(), cnt, h_cnt.size() * 4, hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess)
+        he = hipMemcpyAsync(h_diff.data(), diff, h_diff.size() * 8, hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) {
+        set_error(std::string("lattice_bin: ") + hipGetErrorString(he));
+        return fail(LSL_EDEVICE);
+    }
+    const uint32_t err = h_cnt[2 * ns + 1];
+    if (err) {
+        std::string m = "lattice_bin:";
+        if (err & 1u) m += " edge index out of range;";
+        if (err & 2u) m += " negative or non-finite weight;";
+        if (err & 4u) m += " non-finite node position;";
+        set_error(m);
+        return fail(LSL_EINVAL);
+    }
+    b->n_binned = h_cnt[2 * ns];
+    std::vector<uint32_t> vlo(h_cnt.begin(), h_cnt.begin() + ns);
+    std::vector<uint32_t> vhi(h_cnt.begin() + ns, h_cnt.begin() + 2 * ns);
+    if ((s = plan_groups(b, vlo, vhi, h_diff))) return fail(s);
+
+    // ---- per-strut arrays in edge-list order
+    const size_t nb = std::max<size_t>(b->n_binned, 1);
+    if ((s = b->alloc(&b->rec, nb * (L->dtype == LSL_F64 ? sizeof(StrutRec<double>)
+                                                         : sizeof(StrutRec<float>)))) ||
+        (s = b->alloc_t(&b->perm, nb)) || (s = b->alloc_t(&b->ranges, nb)) ||
+        (s = b->alloc(&b->w, nb * b->esize())) || (s = b->alloc_t(&b->ends, nb)))
+        return fail(s);
+    if (b->n_binned) {
+        he = hipMemcpyAsync(b->perm, perm_src, (size_t)b->n_binned * 4, hipMemcpyDeviceToDevice, st);
+        if (he != hipSuccess) {
+            set_error(std::string("lattice_bin: ") + hipGetErrorString(he));
+            return fail(LSL_EDEVICE);
+        }
+        GatherArgs ga{};
+        ga.nodes = L->nodes;
+        ga.edges = L->edges;
+        ga.weight = L->weight;
+        ga.perm = b->perm;
+        ga.ranges_by_id = rid;
+        ga.n_binned = b->n_binned;
+        ga.R = L->R;
+        ga.rec = b->rec;
+        ga.ranges = b->ranges;
+        ga.w = b->w;
+        ga.ends = b->ends;
+        if ((s = launch_gather(L->dtype, ga, st))) return fail(s);
+    }
+    he = hipStreamSynchronize(st);
+    if (he != hipSuccess) {
+        set_error(std::string("lattice_bin: ") + hipGetErrorString(he));
+        return fail(LSL_EDEVICE);
+    }
+    for (void* p : {(void*)klo, (void*)khi, (void*)vals, (void*)ka, (void*)va, (void*)rid,
+                    (void*)cnt, (void*)diff, (void*)stmp})
+        b->release(p);
+
+    // ---- resident-group buffers sized for the largest group
+    size_t max_act = 1, max_pairs = 1, max_bk = 1, max_cand = 1;
+    for (size_t g = 0; g < b->groups.size(); ++g) {
+        const Group& Gr = b->groups[g];
+        max_act = std::max<size_t>(max_act, Gr.n_active);
+        max_pairs = std::max<size_t>(max_pairs, Gr.pairs);
+        max_bk = std::max<size_t>(max_bk, Gr.n_buckets);
+        max_cand = std::max<size_t>(max_cand, b->win_end[Gr.sb]);
+    }
+    b->cap_active = max_act;
+    b->cap_pairs = max_pairs;
+    b->cap_buckets = max_bk;
+    if ((s = b->alloc_t(&b->active[0], max_act)) || (s = b->alloc_t(&b->active[1], max_act)) ||
+        (s = b->alloc_t(&b->eoff, max_act + 1)) || (s = b->alloc_t(&b->offsets, max_bk + 1)) ||
+        (s = b->alloc_t(&b->ids, max_pairs)) || (s = b->alloc_t(&b->inv, max_pairs)) ||
+        (s = b->alloc_t(&b->owner, max_pairs)) || (s = b->alloc_t(&b->k0, max_pairs)) ||
+        (s = b->alloc_t(&b->v0, max_pairs)) || (s = b->alloc_t(&b->k1, max_pairs)) ||
+        (s = b->alloc_t(&b->v1, max_pairs)) ||
+        (s = b->alloc_t(&b->tmp, group_tmp_elems(max_pairs, max_act, max_cand))) ||
+        (s = b->alloc_t(&b->blk, max_cand / 2048 + 2)) || (s = b->alloc_t(&b->stats, 4)))
+        return fail(s);
+    if (!b->groups.empty() && (s = ensure_group(b, 0, st))) return fail(s);
+    *out = b;
+    return LSL_OK;
+}
+
+lsl_status lattice_bins_free(lattice_bins* b) {
+    delete b;
+    return LSL_OK;
+}
+
+lsl_status lattice_bins_info(const lattice_bins* b, lsl_bins_info* o) {
+    LSL_CHECK(b != nullptr && o != nullptr, "NULL argument");
+    o->n_edges = b->n_edges;
+    o->n_nodes = b->n_nodes;
+    o->n_binned = b->n_binned;
+    o->total_pairs = (int64_t)b->total_pairs;
+    o->max_group_pairs = (int64_t)b->max_group_pairs;
+    o->device_bytes = b->dev_bytes;
+    o->peak_device_bytes = b->peak_bytes;
+    o->dtype = b->dtype;
+    o->tile = b->tile;
+    o->slab = b->slab;
+    o->tiles_x = b->ntx;
+    o->tiles_y = b->nty;
+    o->n_slabs = b->n_slabs;
+    o->n_groups = (int32_t)b->groups.size();
+    o->current_group = b->cur_group;
+    o->last_field_ms = b->last_field_ms;
+    return LSL_OK;
+}
+
+lsl_status lattice_bins_group(const lattice_bins* b, int32_t g, int32_t* s0, int32_t* s1,
+                              int64_t* pairs) {
+    LSL_CHECK(b != nullptr, "bins handle is NULL");
+    LSL_CHECK(g >= 0 && g < (int32_t)b->groups.size(), "group index out of range");
+    if (s0) *s0 = b->groups[g].sa;
+    if (s1) *s1 = b->groups[g].sb;
+    if (pairs) *pairs = (int64_t)b->groups[g].pairs;
+    return LSL_OK;
+}
+
+lsl_status lattice_bins_export(lattice_bins* b, int32_t g, int64_t* offsets, int32_t* ids,
+                               void* stream) {
+    LSL_CHECK(b != nullptr, "bins handle is NULL");
+    LSL_CHECK(g >= 0 && g < (int32_t)b->groups.size(), "group index out of range");
+    hipStream_t st = S(stream);
+    LSL_TRY(ensure_group(b, g, st));
+    const Group& G = b->groups[g];
+    if (offsets) k_u32_to_i64<<<nblk(G.n_buckets + 1), 256, 0, st>>>(b->offsets, offsets, G.n_buckets + 1);
+    if (ids && G.pairs) k_ids_to_edges<<<nblk(G.pairs), 256, 0, st>>>(b->ids, b->perm, ids, G.pairs);
+    LSL_HIP(hipGetLastError());
+    return LSL_OK;
+}
+
+lsl_status lattice_bins_order(const lattice_bins* b, int32_t* order, void* stream) {
+    LSL_CHECK(b != nullptr && order != nullptr, "NULL argument");
+    if (b->n_binned)
+        k_copy_i32<<<nblk(b->n_binned), 256, 0, S(stream)>>>(b->perm, order, b->n_binned);
+    LSL_HIP(hipGetLastError());
+    return LSL_OK;
+}
+
+lsl_status slice_field(lattice_bins* b, int32_t k0, int32_t nk, void* field, uint32_t* bits,
+                       void* stream) {
+    set_error("");
+    LSL_TRY(check_range(b, k0, nk));
+    LSL_CHECK(field != nullptr, "field is NULL");
+    hipStream_t st = S(stream);
+    const size_t plane = (size_t)b->grid.W * (size_t)b->grid.H;
+    if (b->n_binned == 0 || b->groups.empty()) {
+        LSL_TRY(fill_bytes0(field, (size_t)nk * plane * b->esize(), st));
+    } else {
+        // planes whose slabs have no group get zeros: the plan covers all slabs
+        LSL_TRY(for_groups(b, k0, nk, [&](int g, int s_lo, int s_hi) -> lsl_status {
+            LSL_TRY(ensure_group(b, g, st));
+            FieldArgs a = field_args(b, k0, nk, field);
+            a.n_pairs = (uint32_t)b->groups[g].pairs;
+            a.group_s0 = b->groups[g].sa;
+            a.s_lo = s_lo;
+            a.s_hi = s_hi;
+            return launch_field(b->dtype, a, false, st);
+        }));
+    }
+    if (bits) LSL_TRY(launch_bits(b->dtype, field, nk, b->grid.W, b->grid.H, b->C, bits, st));
+    return LSL_OK;
+}
+
+lsl_status slice_field_stats(lattice_bins* b, int32_t k0, int32_t nk, int64_t* counts,
+                             void* stream) {
+    set_error("");
+    LSL_TRY(check_range(b, k0, nk));
+    LSL_CHECK(counts != nullptr, "counts is NULL");
+    hipStream_t st = S(stream);
+    LSL_TRY(fill_bytes0(b->stats, 4 * 8, st));
+    if (b->n_binned && !b->groups.empty()) {
+        LSL_TRY(for_groups(b, k0, nk, [&](int g, int s_lo, int s_hi) -> lsl_status {
+            LSL_TRY(ensure_group(b, g, st));
+            FieldArgs a = field_args(b, k0, nk, nullptr);
+            a.n_pairs = (uint32_t)b->groups[g].pairs;
+            a.group_s0 = b->groups[g].sa;
+            a.s_lo = s_lo;
+            a.s_hi = s_hi;
+            a.stats = b->stats;
+            return launch_field(b->dtype, a, true, st);
+        }));
+    }
+    unsigned long long h[4] = {0, 0, 0, 0};
+    LSL_HIP(hipMemcpyAsync(h, b->stats, sizeof(h), hipMemcpyDeviceToHost, st));
+    LSL_HIP(hipStreamSynchronize(st));
+    counts[0] = (int64_t)h[0];
+    counts[1] = (int64_t)h[1];
+    counts[2] = (int64_t)h[2];
+    if (b->n_binned == 0) counts[2] = (int64_t)nk * b->grid.W * b->grid.H;
+    return LSL_OK;
+}
+
+lsl_status slice_contours(const lattice_bins* cb, int32_t nk, const void* field, float* segs,
+                          int64_t capacity, int64_t* offsets, uint8_t* case_codes, int64_t* total,
+                          void* stream) {
+    set_error("");
+    LSL_CHECK(cb != nullptr, "bins handle is NULL");
+    LSL_CHECK(nk >= 1, "nk must be >= 1");
+    LSL_CHECK(field != nullptr && offsets != nullptr, "field and offsets are required");
+    LSL_CHECK(capacity >= 0, "capacity must be >= 0");
+    LSL_CHECK(capacity == 0 || segs != nullptr, "segs is NULL");
+    lattice_bins* b = const_cast<lattice_bins*>(cb);   // scratch only
+    hipStream_t st = S(stream);
+    const size_t need = contour_tmp_elems(nk, b->grid.W, b->grid.H);
+    if (need > b->ctmp_elems) {
+        LSL_HIP(hipStreamSynchronize(st));
+        b->release(b->ctmp);
+        b->ctmp = nullptr;
+        b->ctmp_elems = 0;
+        LSL_TRY(b->alloc_t(&b->ctmp, need));
+        b->ctmp_elems = need;
+    }
+    LSL_TRY(launch_contours_count(b->dtype, field, nk, b->grid.W, b->grid.H, b->C, offsets,
+                                  case_codes, b->ctmp, nullptr, st));
+    int64_t tot = 0;
+    LSL_HIP(hipMemcpyAsync(&tot, offsets + nk, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    LSL_HIP(hipStreamSynchronize(st));
+    if (total) *total = tot;
+    if (tot > capacity) {
+        set_error("slice_contours: " + std::to_string(tot) + " segments exceed capacity " +
+                  std::to_string(capacity));
+        return LSL_ECAPACITY;
+    }
+    if (tot > 0)
+        LSL_TRY(launch_contours_emit(b->dtype, field, nk, b->grid.W, b->grid.H, b->C, b->ctmp,
+                                     nullptr, segs, capacity, st));
+    return LSL_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Node -> (strut, end) incidence list in edge-list order, built once.
+lsl_status ensure_node_csr(lattice_bins* b, hipStream_t st) {
+    if (b->node_off) return LSL_OK;
+    const size_t n2 = 2 * (size_t)std::max<uint32_t>(b->n_binned, 1);
+    uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr, *tmp = nullptr;
+    lsl_status s;
+    if ((s = b->alloc_t(&k0, n2)) || (s = b->alloc_t(&v0, n2)) || (s = b->alloc_t(&k1, n2)) ||
+        (s = b->alloc_t(&v1, n2)) || (s = b->alloc_t(&tmp, radix_tmp_elems(n2))) ||
+        (s = b->alloc_t(&b->node_off, (size_t)b->n_nodes + 1)) ||
+        (s = b->alloc_t(&b->node_inc, n2)))
+        return s;
+    const size_t n = 2 * (size_t)b->n_binned;
+    LSL_TRY(launch_node_keys(b->ends, b->n_binned, k0, v0, st));
+    int bits = 0;
+    while (bits < 32 && (1ull << bits) < (uint64_t)b->n_nodes) ++bits;
+    int which = 0;
+    LSL_TRY(radix_sort_pairs(k0, v0, k1, v1, n, bits, tmp, &which, st));
+    const uint32_t* ks = which ? k1 : k0;
+    const uint32_t* vs = which ? v1 : v0;
+    LSL_TRY(launch_node_offsets(ks, n, b->n_nodes, b->node_off, st));
+    if (n) LSL_HIP(hipMemcpyAsync(b->node_inc, vs, n * 4, hipMemcpyDeviceToDevice, st));
+    LSL_HIP(hipStreamSynchronize(st));
+    for (void* p : {(void*)k0, (void*)v0, (void*)k1, (void*)v1, (void*)tmp}) b->release(p);
+    return LSL_OK;
+}
+
+BackArgs back_args(const lattice_bins* b, int g, int32_t k0, int32_t nk, int s_lo, int s_hi,
+                   const void* grad) {
+    BackArgs a{};
+    a.rec = b->rec;
+    a.offsets = b->offsets;
+    a.ids = b->ids;
+    a.n_binned = b->n_binned;
+    a.n_pairs = (uint32_t)b->groups[g].pairs;
+    a.ntx = b->ntx;
+    a.nty = b->nty;
+    a.tile = b->tile;
+    a.slab = b->slab;
+    a.group_s0 = b->groups[g].sa;
+    a.s_lo = s_lo;
+    a.s_hi = s_hi;
+    a.k0 = k0;
+    a.nk = nk;
+    a.W = b->grid.W;
+    a.H = b->grid.H;
+    a.x0 = b->grid.x0;
+    a.y0 = b->grid.y0;
+    a.dx = b->grid.dx;
+    a.dy = b->grid.dy;
+    a.z0 = b->grid.z0;
+    a.dz = b->grid.dz;
+    a.R = b->R;
+    a.grad = grad;
+    a.partial = b->partial;
+    return a;
+}
+
+struct BatchKey {
+    int32_t g, k0, nk, first;
+    void *field, *bits, *segs, *offsets;
+    int64_t capacity;
+};
+
+// Enqueues one group's part of slice_batch on `st`: queue build, persistent
+// field launch, binary image and contours (positions continue from *base).
+lsl_status batch_group_work(lattice_bins* b, int g, int32_t k0, int32_t nk, int s_lo, int s_hi,
+                            void* field, uint32_t* bits, float* segs, int64_t capacity,
+                            int64_t* offsets, hipEvent_t e0, hipEvent_t e1, hipStream_t st) {
+    const int kg0 = std::max(k0, s_lo * b->slab);
+    const int kg1 = std::min(k0 + nk, (s_hi + 1) * b->slab);
+    const int nkg = kg1 - kg0;
+    const size_t plane = (size_t)b->grid.W * (size_t)b->grid.H;
+    // field of this group's planes: the caller's array or library scratch
+    void* fbase = field ? (void*)((char*)field + (size_t)(kg0 - k0) * plane * b->esize())
+                        : b->batch_field;
+    FieldArgs a = field_args(b, kg0, nkg, fbase);
+    a.n_pairs = (uint32_t)b->groups[g].pairs;
+    a.group_s0 = b->groups[g].sa;
+    a.s_lo = s_lo;
+    a.s_hi = s_hi;
+    const uint32_t n_items = (uint32_t)((s_hi - s_lo + 1) * b->ntx * b->nty);
+    uint32_t* qk = b->queue_buf;
+    uint32_t* qv = qk + b->queue_cap;
+    uint32_t* qk2 = qv + b->queue_cap;
+    uint32_t* qv2 = qk2 + b->queue_cap;
+    uint32_t* counter = qv2 + b->queue_cap;
+    uint32_t* qtmp = counter + 64;
+    const uint32_t* queue = nullptr;
+    LSL_TRY(launch_queue_build(a, qk, qv, qk2, qv2, n_items, qtmp, &queue, st));
+    BatchArgs ba{};
+    ba.f = a;
+    ba.queue = queue;
+    ba.n_items = n_items;
+    ba.counter = counter;
+    const int nblocks = persistent_blocks(b->dtype, b->slab);
+    LSL_TRY(fill_u32(counter, 0u, 1, st));
+    if (e0) LSL_HIP(hipEventRecord(e0, st));
+    LSL_TRY(launch_persistent(b->dtype, ba, nblocks, st));
+    if (e1) LSL_HIP(hipEventRecord(e1, st));
+    const size_t words = (size_t)(b->grid.W + 31) / 32;
+    if (bits)
+        LSL_TRY(launch_bits(b->dtype, fbase, nkg, b->grid.W, b->grid.H, b->C,
+                            bits + (size_t)(kg0 - k0) * (size_t)b->grid.H * words, st));
+    unsigned long long* base = (unsigned long long*)(counter + 32);
+    LSL_TRY(launch_contours_count(b->dtype, fbase, nkg, b->grid.W, b->grid.H, b->C,
+                                  offsets + (kg0 - k0), nullptr, b->ctmp, base, st));
+    LSL_TRY(launch_contours_emit(b->dtype, fbase, nkg, b->grid.W, b->grid.H, b->C, b->ctmp, base,
+                                 segs, capacity, st));
+    return LSL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lsl_status slice_field_backward(lattice_bins* b, int32_t k0, int32_t nk, const void* grad_field,
+                                void* grad_weight, void* grad_nodes, int32_t accumulate,
+                                void* stream) {
+    set_error("");
+    LSL_TRY(check_range(b, k0, nk));
+    LSL_CHECK(grad_field != nullptr, "grad_field is NULL");
+    hipStream_t st = S(stream);
+    if (!b->acc) LSL_TRY(b->alloc_t(&b->acc, (size_t)std::max<uint32_t>(b->n_binned, 1) * 7));
+    if (!b->partial) LSL_TRY(b->alloc(&b->partial, b->cap_pairs * 10 * b->esize()));
+    LSL_TRY(ensure_node_csr(b, st));
+    LSL_TRY(fill_bytes0(b->acc, (size_t)std::max<uint32_t>(b->n_binned, 1) * 7 * 8, st));
+    if (b->n_binned && !b->groups.empty()) {
+        LSL_TRY(for_groups(b, k0, nk, [&](int g, int s_lo, int s_hi) -> lsl_status {
+            LSL_TRY(ensure_group(b, g, st));
+            const Group& G = b->groups[g];
+            if (G.pairs == 0) return LSL_OK;
+            BackArgs a = back_args(b, g, k0, nk, s_lo, s_hi, grad_field);
+            LSL_TRY(launch_backward(b->dtype, a, st));
+            ReduceArgs r{};
+            r.partial = b->partial;
+            r.active = b->active[b->cur_buf];
+            r.n_active = G.n_active;
+            r.eoff = b->eoff;
+            r.inv = b->inv;
+            r.rec = b->rec;
+            r.w = b->w;
+            r.R = b->R;
+            r.acc = b->acc;
+            return launch_reduce(b->dtype, r, b->ranges, G.sa, s_lo, s_hi, (uint32_t)G.pairs,
+                                 b->n_binned, st);
+        }));
+    }
+    ScatterArgs sc{};
+    sc.acc = b->acc;
+    sc.perm = b->perm;
+    sc.n_binned = b->n_binned;
+    sc.n_edges = b->n_edges;
+    sc.n_nodes = b->n_nodes;
+    sc.node_off = b->node_off;
+    sc.node_inc = b->node_inc;
+    sc.grad_weight = grad_weight;
+    sc.grad_nodes = grad_nodes;
+    sc.accumulate = accumulate;
+    return launch_scatter(b->dtype, sc, st);
+}
+
+lsl_status slice_batch(lattice_bins* b, int32_t k0, int32_t nk, void* field, uint32_t* bits,
+                       float* segs, int64_t capacity, int64_t* offsets, int64_t* total,
+                       void* stream) {
+    set_error("");
+    LSL_TRY(check_range(b, k0, nk));
+    LSL_CHECK(offsets != nullptr, "offsets is NULL");
+    LSL_CHECK(capacity >= 0 && (capacity == 0 || segs != nullptr), "bad segment buffer");
+    hipStream_t st = S(stream);
+    const size_t plane = (size_t)b->grid.W * (size_t)b->grid.H;
+    // scratch sized for the largest group
+    size_t max_items = 1, max_planes = 1;
+    for (auto& G : b->groups) {
+        max_items = std::max<size_t>(max_items, (size_t)(G.sb - G.sa + 1) * b->ntx * b->nty);
+        max_planes = std::max<size_t>(max_planes, (size_t)(G.sb - G.sa + 1) * b->slab);
+    }
+    max_planes = std::min<size_t>(max_planes, (size_t)nk);
+    if (b->queue_cap < max_items) {
+        LSL_HIP(hipStreamSynchronize(st));
+        b->release(b->queue_buf);
+        b->queue_buf = nullptr;
+        b->queue_cap = 0;
+        LSL_TRY(b->alloc_t(&b->queue_buf, 4 * max_items + 64 + radix_tmp_elems(max_items)));
+        b->queue_cap = max_items;
+        b->drop_graphs();
+    }
+    const size_t ct = contour_tmp_elems((int32_t)max_planes, b->grid.W, b->grid.H);
+    if (b->ctmp_elems < ct) {
+        LSL_HIP(hipStreamSynchronize(st));
+        b->release(b->ctmp);
+        b->ctmp = nullptr;
+        b->ctmp_elems = 0;
+        LSL_TRY(b->alloc_t(&b->ctmp, ct));
+        b->ctmp_elems = ct;
+        b->drop_graphs();
+    }
+    if (!field && b->batch_field_bytes < max_planes * plane * b->esize()) {
+        LSL_HIP(hipStreamSynchronize(st));
+        b->release(b->batch_field);
+        b->batch_field = nullptr;
+        b->batch_field_bytes = 0;
+        LSL_TRY(b->alloc(&b->batch_field, max_planes * plane * b->esize()));
+        b->batch_field_bytes = max_planes * plane * b->esize();
+        b->drop_graphs();
+    }
+    uint32_t* counter = b->queue_buf + 4 * b->queue_cap;
+    unsigned long long* base = (unsigned long long*)(counter + 32);
+    LSL_TRY(fill_bytes0(base, 8, st));
+    if (b->n_binned == 0 || b->groups.empty()) {
+        if (field) LSL_TRY(fill_bytes0(field, (size_t)nk * plane * b->esize(), st));
+    }
+    hipStream_t cap = nullptr;
+    LSL_TRY(for_groups(b, k0, nk, [&](int g, int s_lo, int s_hi) -> lsl_status {
+        LSL_TRY(ensure_group(b, g, st));
+        BatchKey key{g, k0, nk, 0, field, bits, segs, offsets, capacity};
+        std::vector<unsigned char> kb((unsigned char*)&key, (unsigned char*)&key + sizeof(key));
+        hipGraphExec_t exec = nullptr;
+        for (auto& ge : b->graphs)
+            if (ge.key == kb) exec = ge.exec;
+        if (!exec) {
+            if (!cap) LSL_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            // capture with timing events first; without them if that fails
+            for (int attempt = 0; attempt < 2 && !exec; ++attempt) {
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (attempt == 0) {
+                    LSL_HIP(hipEventCreate(&e0));
+                    LSL_HIP(hipEventCreate(&e1));
+                }
+                LSL_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+                lsl_status ws = batch_group_work(b, g, k0, nk, s_lo, s_hi, field, bits, segs,
+                                                 capacity, offsets, e0, e1, cap);
+                hipGraph_t graph = nullptr;
+                hipError_t ce = hipStreamEndCapture(cap, &graph);
+                hipError_t ie = hipErrorUnknown;
+                if (ws == LSL_OK && ce == hipSuccess && graph)
+                    ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                if (graph) hipGraphDestroy(graph);
+                if (ie != hipSuccess) {
+                    exec = nullptr;
+                    hipGetLastError();
+                    if (e0) hipEventDestroy(e0);
+                    if (e1) hipEventDestroy(e1);
+                    if (attempt == 1) {
+                        if (ws != LSL_OK) return ws;
+                        set_error(std::string("slice_batch: graph capture failed: ") +
+                                  hipGetErrorString(ce != hipSuccess ? ce : ie));
+                        return LSL_EDEVICE;
+                    }
+                    continue;
+                }
+                b->graphs.push_back({kb, exec, e0, e1});
+            }
+        }
+        LSL_HIP(hipGraphLaunch(exec, st));
+        return LSL_OK;
+    }));
+    if (cap) hipStreamDestroy(cap);
+    unsigned long long tot = 0;
+    LSL_HIP(hipMemcpyAsync(&tot, base, 8, hipMemcpyDeviceToHost, st));
+    LSL_HIP(hipStreamSynchronize(st));
+    // field time of this call: the launched graphs' event pairs
+    b->last_field_ms = 0.0;
+    LSL_TRY(for_groups(b, k0, nk, [&](int g, int, int) -> lsl_status {
+        BatchKey key{g, k0, nk, 0, field, bits, segs, offsets, capacity};
+        std::vector<unsigned char> kb((unsigned char*)&key, (unsigned char*)&key + sizeof(key));
+        for (auto& ge : b->graphs)
+            if (ge.key == kb) {
+                float ms = 0.0f;
+                if (ge.e0 && hipEventElapsedTime(&ms, ge.e0, ge.e1) == hipSuccess)
+                    b->last_field_ms += ms;
+                else
+                    b->last_field_ms = -1e30;
+            }
+        return LSL_OK;
+    }));
+    if (b->last_field_ms < 0) b->last_field_ms = -1.0;
+    if (total) *total = (int64_t)tot;
+    if ((int64_t)tot > capacity) {
+        set_error("slice_batch: " + std::to_string(tot) + " segments exceed capacity " +
+                  std::to_string(capacity));
+        return LSL_ECAPACITY;
+    }
+    return LSL_OK;
+}
+
+}  // extern "C"

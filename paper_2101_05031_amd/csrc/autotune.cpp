@@ -1,0 +1,167 @@
+// slice_autotune: picks the tile edge and slab depth for a lattice and grid
+// by binning with each candidate and timing the field on a few sampled plane
+// windows.  The field does not depend on the choice (every pixel sees the
+// same struts in the same order), so only speed is compared.  Results are
+// cached in a small JSON file keyed by the problem's shape.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+using namespace lsl;
+
+namespace {
+
+std::string shape_key(const lsl_lattice* L, const lsl_grid* G) {
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), "E%lld_N%lld_d%d_W%d_H%d_S%d_R%.6g_dx%.6g_dy%.6g_dz%.6g",
+                  (long long)L->n_edges, (long long)L->n_nodes, L->dtype, G->W, G->H, G->n_slices,
+                  L->R, G->dx, G->dy, G->dz);
+    return buf;
+}
+
+// Reads {"key": {"tile": t, "slab": s}, ...}; returns false if key is absent.
+bool cache_lookup(const char* path, const std::string& key, int* tile, int* slab) {
+    std::ifstream f(path);
+    if (!f) return false;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string s = ss.str();
+    const std::string q = "\"" + key + "\"";
+    size_t p = s.find(q);
+    if (p == std::string::npos) return false;
+    size_t e = s.find('}', p);
+    if (e == std::string::npos) return false;
+    const std::string obj = s.substr(p, e - p);
+    size_t pt = obj.find("\"tile\""), ps = obj.find("\"slab\"");
+    if (pt == std::string::npos || ps == std::string::npos) return false;
+    int t = 0, sl = 0;
+    if (std::sscanf(obj.c_str() + obj.find(':', pt) + 1, "%d", &t) != 1) return false;
+    if (std::sscanf(obj.c_str() + obj.find(':', ps) + 1, "%d", &sl) != 1) return false;
+    *tile = t;
+    *slab = sl;
+    return true;
+}
+
+void cache_store(const char* path, const std::string& key, int tile, int slab) {
+    std::string s;
+    {
+        std::ifstream f(path);
+        if (f) {
+            std::stringstream ss;
+            ss << f.rdbuf();
+            s = ss.str();
+        }
+    }
+    const std::string entry = "\"" + key + "\": {\"tile\": " + std::to_string(tile) +
+                              ", \"slab\": " + std::to_string(slab) + "}";
+    size_t close = s.rfind('}');
+    if (s.empty() || close == std::string::npos || s.find('{') == std::string::npos) {
+        s = "{\n  " + entry + "\n}\n";
+    } else {
+        const bool empty = s.find('"') == std::string::npos;
+        s = s.substr(0, close);
+        while (!s.empty() && (s.back() == '\n' || s.back() == ' ')) s.pop_back();
+        s += (empty ? "\n  " : ",\n  ") + entry + "\n}\n";
+    }
+    std::ofstream o(path);
+    o << s;
+}
+
+}  // namespace
+
+extern "C" lsl_status slice_autotune(const lsl_lattice* L, const lsl_grid* G,
+                                     lsl_bin_params* P, const char* cache_path, void* stream) {
+    set_error("");
+    if (!L || !G || !P) {
+        set_error("slice_autotune: NULL argument");
+        return LSL_EINVAL;
+    }
+    const std::string key = shape_key(L, G);
+    if (cache_path) {
+        int t = 0, s = 0;
+        if (cache_lookup(cache_path, key, &t, &s)) {
+            if (!P->tile) P->tile = t;
+            if (!P->slab) P->slab = s;
+            return LSL_OK;
+        }
+    }
+    std::vector<int> tiles = P->tile ? std::vector<int>{P->tile} : std::vector<int>{16, 32};
+    std::vector<int> slabs = P->slab ? std::vector<int>{P->slab} : std::vector<int>{4, 8, 16};
+    const int win = std::min(16, G->n_slices);
+    const int nwin = G->n_slices >= 3 * win ? 3 : 1;
+    std::vector<int> starts;
+    for (int w = 0; w < nwin; ++w)
+        starts.push_back(nwin == 1 ? 0 : (int)((int64_t)(G->n_slices - win) * (2 * w + 1) / (2 * nwin)) / 16 * 16);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t es = L->dtype == LSL_F64 ? 8 : 4;
+    void* field = nullptr;
+    hipError_t he = hipMalloc(&field, (size_t)win * G->W * G->H * es);
+    if (he != hipSuccess) {
+        hipGetLastError();
+        set_error("slice_autotune: cannot allocate the sample field");
+        return LSL_ENOMEM;
+    }
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    double best = 1e300;
+    int bt = tiles[0], bs = slabs[0];
+    lsl_status result = LSL_OK;
+    for (int t : tiles) {
+        for (int s : slabs) {
+            lsl_bin_params bp{t, s, P->max_pairs};
+            lattice_bins* b = nullptr;
+            const auto c0 = std::chrono::steady_clock::now();
+            lsl_status rs = lattice_bin(L, G, &bp, &b, stream);
+            const double bin_s =
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - c0).count();
+            if (rs != LSL_OK) {
+                if (rs == LSL_ENOMEM) continue;    // candidate does not fit
+                result = rs;
+                break;
+            }
+            double field_s = 0;
+            for (int k0 : starts) {
+                float best_ms = 1e30f;
+                for (int rep = 0; rep < 2; ++rep) {
+                    hipEventRecord(e0, st);
+                    rs = slice_field(b, k0, win, field, nullptr, stream);
+                    hipEventRecord(e1, st);
+                    hipEventSynchronize(e1);
+                    float ms = 0;
+                    hipEventElapsedTime(&ms, e0, e1);
+                    if (rs == LSL_OK) best_ms = std::min(best_ms, ms);
+                }
+                field_s += best_ms * 1e-3;
+            }
+            lattice_bins_free(b);
+            if (rs != LSL_OK) {
+                result = rs;
+                break;
+            }
+            const double score = field_s / (nwin * win) * G->n_slices + bin_s;
+            if (score < best) {
+                best = score;
+                bt = t;
+                bs = s;
+            }
+        }
+        if (result != LSL_OK) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(field);
+    if (result != LSL_OK) return result;
+    P->tile = bt;
+    P->slab = bs;
+    if (cache_path) cache_store(cache_path, key, bt, bs);
+    return LSL_OK;
+}

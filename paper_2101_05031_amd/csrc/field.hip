@@ -1,0 +1,124 @@
+// Field evaluation (Eq. 6 with the closed form of Eq. 7, Sec. 4 Step 4).
+//
+// One wave owns an 8x8 pixel block of one tile and one slab of planes; the
+// four waves of a workgroup take the four 8x8 blocks of a 16x16 tile (or
+// four of the blocks of a larger tile).  The wave walks its tile's bucket
+// list (edge-list order) 64 struts at a time.  Per strut and plane it stages,
+// in float64, the foot F of the block centre c on the strut's line:
+//
+//   tc = (c - a).u,  m = a + tc u - c  (m is orthogonal to u),
+//
+// and drops the strut for that plane when the exact distance from c to the
+// segment is at least R + r_block (no pixel of the block can then be within
+// R).  The surviving struts are compacted into LDS with a ballot/mbcnt
+// prefix.  For a pixel p = c + d (d in the plane, |d| <= r_block) the
+// arclength coordinates of the strut ends with origin at the foot of p are
+//
+//   alpha = -tc - d.u,   beta = (L - tc) - d.u,
+//   H = R^2 - dist(p, line)^2 = (R^2 - |m|^2) + 2 m.d - |d|^2 + (d.u)^2,
+//
+// all formed from small quantities, and the term is
+//
+//   r/R^4 * integral over [clamp(alpha), clamp(beta)] of (H - t^2)^2 dt
+//     = r/R^4 * (cb - ca) * (H^2 - 2/3 H S1 + S2/5),
+//   S1 = ca^2 + ca cb + cb^2,  S2 = (ca^2 + cb^2) S1 - (ca cb)^2,
+//   ca, cb = alpha, beta clamped to [-sqrt(H), sqrt(H)].
+//
+// Terms outside the support come out as exact zeros (cb - ca = 0).  float32
+// sums are compensated: s' = s + t, e += t - (s' - s); a zero term leaves
+// both unchanged, so the result does not depend on which zero terms a list
+// holds.
+#include "field_block.hpp"
+
+namespace lsl {
+namespace {
+
+template <typename T, int SZ, bool STATS>
+__global__ __launch_bounds__(256) void k_field(FieldArgs a, uint32_t n_items) {
+    __shared__ Stage<T> stage[4][kWave];
+    const int wv = threadIdx.x >> 6;
+    const uint32_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t item = blk * 4u + (uint32_t)wv;
+    if (item >= n_items) return;
+    // item -> (slab, tile, 8x8 block): blocks of a tile are consecutive
+    const int nsub = a.tile / kBlockPix;
+    uint32_t t = item;
+    const int sub = (int)(t % (uint32_t)(nsub * nsub));
+    t /= (uint32_t)(nsub * nsub);
+    const int tx = (int)(t % (uint32_t)a.ntx);
+    t /= (uint32_t)a.ntx;
+    const int ty = (int)(t % (uint32_t)a.nty);
+    t /= (uint32_t)a.nty;
+    fieldk::field_block<T, SZ, STATS>(a, a.s_lo + (int)t, tx, ty, sub, stage[wv]);
+}
+
+// Binary image: one wave per 64 pixels of a row; the ballot is the bit mask.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bits(const T* field, int32_t nk, int32_t W, int32_t H,
+                                              T C, uint32_t* bits) {
+    const int lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int chunks = (W + 63) / 64;
+    const int words = (W + 31) / 32;
+    const uint64_t rows = (uint64_t)nk * (uint64_t)H;
+    if (wave >= rows * (uint64_t)chunks) return;
+    const uint64_t row = wave / (uint64_t)chunks;
+    const int c = (int)(wave % (uint64_t)chunks);
+    const int i = c * 64 + lane;
+    const bool in = i < W && field[row * (uint64_t)W + (uint64_t)i] >= C;
+    const uint64_t m = ballot64(in);
+    uint32_t* out = bits + row * (uint64_t)words;
+    if (lane == 0) out[2 * c] = (uint32_t)m;
+    if (lane == 1 && 2 * c + 1 < words) out[2 * c + 1] = (uint32_t)(m >> 32);
+}
+
+template <typename T, int SZ>
+lsl_status launch_t(const FieldArgs& a, bool stats, uint32_t n_items, hipStream_t st) {
+    const unsigned blocks = (n_items + 3u) / 4u;
+    if (stats)
+        k_field<T, SZ, true><<<blocks, 256, 0, st>>>(a, n_items);
+    else
+        k_field<T, SZ, false><<<blocks, 256, 0, st>>>(a, n_items);
+    LSL_HIP(hipGetLastError());
+    return LSL_OK;
+}
+
+template <typename T>
+lsl_status launch_dt(const FieldArgs& a, bool stats, uint32_t n_items, hipStream_t st) {
+    if (a.slab <= 1) return launch_t<T, 1>(a, stats, n_items, st);
+    if (a.slab <= 2) return launch_t<T, 2>(a, stats, n_items, st);
+    if (a.slab <= 4) return launch_t<T, 4>(a, stats, n_items, st);
+    if (a.slab <= 8) return launch_t<T, 8>(a, stats, n_items, st);
+    return launch_t<T, 16>(a, stats, n_items, st);
+}
+
+}  // namespace
+
+lsl_status launch_field(int dtype, const FieldArgs& a, bool stats, hipStream_t st) {
+    const int nsub = a.tile / kBlockPix;
+    const uint64_t n_items = (uint64_t)(a.s_hi - a.s_lo + 1) * (uint64_t)a.ntx * (uint64_t)a.nty *
+                             (uint64_t)(nsub * nsub);
+    if (n_items == 0 || a.nk <= 0) return LSL_OK;
+    if (n_items > 0xfffffff0ull) {
+        set_error("slice_field: too many work items in one launch");
+        return LSL_EINTERNAL;
+    }
+    if (dtype == LSL_F32) return launch_dt<float>(a, stats, (uint32_t)n_items, st);
+    return launch_dt<double>(a, stats, (uint32_t)n_items, st);
+}
+
+lsl_status launch_bits(int dtype, const void* field, int32_t nk, int32_t W, int32_t H, double C,
+                       uint32_t* bits, hipStream_t st) {
+    const uint64_t waves = (uint64_t)nk * (uint64_t)H * (uint64_t)((W + 63) / 64);
+    if (waves == 0) return LSL_OK;
+    const uint64_t blocks = (waves + 3) / 4;
+    if (dtype == LSL_F32)
+        k_bits<float><<<(unsigned)blocks, 256, 0, st>>>((const float*)field, nk, W, H, (float)C,
+                                                        bits);
+    else
+        k_bits<double><<<(unsigned)blocks, 256, 0, st>>>((const double*)field, nk, W, H, C, bits);
+    LSL_HIP(hipGetLastError());
+    return LSL_OK;
+}
+
+}  // namespace lsl

@@ -1,0 +1,185 @@
+// Per-block field evaluation shared by the plain and the persistent field
+// kernels (see field.hip for the method).
+#pragma once
+
+#include "kernels.hpp"
+
+namespace lsl {
+namespace fieldk {
+
+template <typename T>
+struct Num;
+
+template <>
+struct Num<float> {
+    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float clamp_(float v, float lo, float hi) {
+        return __builtin_amdgcn_fmed3f(v, lo, hi);
+    }
+    static __device__ __forceinline__ float fma_(float a, float b, float c) {
+        return __builtin_fmaf(a, b, c);
+    }
+    static __device__ __forceinline__ float max_(float a, float b) { return __builtin_fmaxf(a, b); }
+};
+
+template <>
+struct Num<double> {
+    static __device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
+    static __device__ __forceinline__ double clamp_(double v, double lo, double hi) {
+        return __builtin_fmin(__builtin_fmax(v, lo), hi);
+    }
+    static __device__ __forceinline__ double fma_(double a, double b, double c) {
+        return __builtin_fma(a, b, c);
+    }
+    static __device__ __forceinline__ double max_(double a, double b) { return __builtin_fmax(a, b); }
+};
+
+// One (pixel, strut) term of the field, added to the compensated sum (s, c).
+template <typename T>
+__device__ __forceinline__ T eval_term(const Stage<T>& e, T dX, T dY, T d2) {
+    using N = Num<T>;
+    const T du = N::fma_(dX, e.ux, dY * e.uy);                 // d.u
+    const T al = e.ntc - du;                                     // alpha
+    const T be = e.nbtc - du;                                    // beta
+    const T H = N::fma_(du, du, N::fma_(e.mx2, dX, N::fma_(e.my2, dY, e.H0 - d2)));
+    const T h = N::sqrt_(N::max_(H, T(0)));
+    const T ca = N::clamp_(al, -h, h);
+    const T cb = N::clamp_(be, -h, h);
+    const T D = cb - ca;
+    const T x2 = ca * ca, y2 = cb * cb, xy = ca * cb;
+    const T q2 = x2 + y2;
+    const T S1 = q2 + xy;
+    const T S2 = N::fma_(q2, S1, -(xy * xy));
+    const T u = N::fma_(T(-2.0 / 3.0), S1, H);
+    const T Q = N::fma_(H, u, T(0.2) * S2);
+    return (e.wq * D) * Q;
+}
+
+template <typename T>
+__device__ __forceinline__ void comp_add(T t, T& s, T& c) {
+    const T sn = s + t;
+    c += t - (sn - s);
+    s = sn;
+}
+
+// One wave evaluates the 8x8 block `sub` of tile (tx, ty) over the planes of
+// `slab` that lie in [k0, k0+nk); `stage` is the wave's 64-entry LDS area.
+template <typename T, int SZ, bool STATS>
+__device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx, int ty, int sub,
+                                            Stage<T>* stage) {
+    const int lane = lane_id();
+    const uint32_t n_binned = a.n_binned, n_pairs = a.n_pairs;
+    const int nsub = a.tile / kBlockPix;
+    const int i0 = tx * a.tile + (sub % nsub) * kBlockPix;
+    const int j0 = ty * a.tile + (sub / nsub) * kBlockPix;
+    if (i0 >= a.W || j0 >= a.H) return;
+    int kb = slab * a.slab, ke = kb + a.slab;
+    if (kb < a.k0) kb = a.k0;
+    if (ke > a.k0 + a.nk) ke = a.k0 + a.nk;
+    const int nvalid = ke - kb;
+
+    const uint32_t bucket = ((uint32_t)(slab - a.group_s0) * (uint32_t)a.nty + (uint32_t)ty) *
+                                (uint32_t)a.ntx + (uint32_t)tx;
+    uint32_t beg = a.offsets[bucket], end = a.offsets[bucket + 1];
+    if (end > n_pairs) end = n_pairs;
+    if (beg > end) beg = end;
+
+    const int lx = lane & 7, ly = lane >> 3;
+    const int pi = i0 + lx, pj = j0 + ly;
+    const bool pix = pi < a.W && pj < a.H;
+    const double cx = a.x0 + ((double)i0 + 4.0) * a.dx;     // centre of the 8x8 centres
+    const double cy = a.y0 + ((double)j0 + 4.0) * a.dy;
+    const T dX = (T)(((double)lx - 3.5) * a.dx);
+    const T dY = (T)(((double)ly - 3.5) * a.dy);
+    const T d2 = dX * dX + dY * dY;
+    const double rb = 3.5 * sqrt(a.dx * a.dx + a.dy * a.dy);
+    const double thr = (a.R + rb) * (1.0 + 1e-7);
+    const double thr2 = thr * thr;
+    const double R2 = a.R * a.R;
+    const uint64_t lt = lanes_below(lane);
+
+    T acc_s[SZ], acc_c[SZ];
+#pragma unroll
+    for (int k = 0; k < SZ; ++k) acc_s[k] = acc_c[k] = T(0);
+    unsigned long long n_cand = 0, n_useful = 0;
+
+    const StrutRec<T>* recs = (const StrutRec<T>*)a.rec;
+    for (uint32_t cbase = beg; cbase < end; cbase += kWave) {
+        const uint32_t idx = cbase + (uint32_t)lane;
+        bool valid = idx < end;
+        uint32_t p = valid ? a.ids[idx] : 0u;
+        valid = valid && p < n_binned;
+        const StrutRec<T> r = recs[valid ? p : 0u];
+        const double ax = (double)r.ax, ay = (double)r.ay, az = (double)r.az;
+        const Line ln = strut_line(r);
+        const double L = ln.L, ux = ln.ux, uy = ln.uy, uz = ln.uz;
+        const T uxT = (T)ux, uyT = (T)uy;
+        const double wx = cx - ax, wy = cy - ay;
+        const double txy = fma(wx, ux, wy * uy);
+#pragma unroll
+        for (int k = 0; k < SZ; ++k) {
+            if (k < nvalid) {
+                const double z = a.z0 + ((double)(kb + k) + 0.5) * a.dz;
+                const double wz = z - az;
+                const double tc = fma(wz, uz, txy);
+                const double mx = fma(tc, ux, -wx), my = fma(tc, uy, -wy), mz = fma(tc, uz, -wz);
+                const double m2 = fma(mx, mx, fma(my, my, mz * mz));
+                const double ex = tc < 0.0 ? -tc : (tc > L ? tc - L : 0.0);
+                const bool pass = valid && fma(ex, ex, m2) < thr2;
+                const uint64_t mask = ballot64(pass);
+                if (mask == 0ull) continue;
+                if (pass) {
+                    Stage<T> s;
+                    s.mx2 = (T)(2.0 * mx);
+                    s.my2 = (T)(2.0 * my);
+                    s.ux = uxT;
+                    s.uy = uyT;
+                    s.ntc = (T)(-tc);
+                    s.nbtc = (T)(L - tc);
+                    s.H0 = (T)(R2 - m2);
+                    s.wq = r.wq;
+                    stage[__popcll(mask & lt)] = s;
+                }
+                __builtin_amdgcn_wave_barrier();
+                const int n = __popcll(mask);
+                T s_ = acc_s[k], c_ = acc_c[k];
+                for (int j = 0; j < n; ++j) {
+                    const T term = eval_term<T>(stage[j], dX, dY, d2);
+                    comp_add(term, s_, c_);
+                    if (STATS) n_useful += term > T(0) ? 1ull : 0ull;
+                }
+                if (STATS) n_cand += pix ? (unsigned long long)n : 0ull;
+                acc_s[k] = s_;
+                acc_c[k] = c_;
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+    }
+
+    if (STATS) {
+        if (!pix) n_useful = 0;
+        for (int d = 32; d >= 1; d >>= 1) {
+            n_cand += __shfl_xor(n_cand, d, kWave);
+            n_useful += __shfl_xor(n_useful, d, kWave);
+        }
+        const unsigned long long npx = (unsigned long long)__popcll(ballot64(pix)) * nvalid;
+        if (lane == 0) {
+            atomicAdd(&a.stats[0], n_cand);
+            atomicAdd(&a.stats[1], n_useful);
+            atomicAdd(&a.stats[2], npx);
+        }
+        return;
+    }
+    if (pix) {
+        T* out = (T*)a.field;
+#pragma unroll
+        for (int k = 0; k < SZ; ++k)
+            if (k < nvalid)
+                out[((size_t)(kb + k - a.k0) * (size_t)a.H + (size_t)pj) * (size_t)a.W + (size_t)pi] =
+                    acc_s[k] + acc_c[k];
+    }
+}
+
+
+}  // namespace fieldk
+}  // namespace lsl

@@ -1,0 +1,170 @@
+// Launcher interfaces between the C-ABI host code and the kernel files.
+#pragma once
+
+#include "common.hpp"
+
+namespace lsl {
+
+// ----------------------------------------------------------------- prep.hip
+struct PrepArgs {
+    const void* nodes;
+    const int32_t* edges;
+    const void* weight;
+    int64_t n_nodes, n_edges;
+    double R;
+    double x0, y0, z0, inv_dx, inv_dy, inv_dz;
+    int32_t W, H, S;
+    int32_t tile, slab, n_slabs;
+    // outputs, indexed by edge id
+    uint32_t* key_lo;
+    uint32_t* key_hi;                 // float64 lattices only
+    uint32_t* vals;                   // edge ids
+    SRange* ranges;
+    // plan histograms
+    uint32_t* cnt_lo;                 // [n_slabs] struts whose first slab is s
+    uint32_t* cnt_hi;                 // [n_slabs] struts whose last slab is s
+    unsigned long long* pair_diff;    // [n_slabs + 1] difference array of pairs
+    uint32_t* n_binned;
+    uint32_t* err;                    // bit 0 index, 1 weight, 2 node
+};
+lsl_status launch_prep(int dtype, const PrepArgs& a, hipStream_t st);
+
+struct GatherArgs {
+    const void* nodes;
+    const int32_t* edges;
+    const void* weight;
+    const uint32_t* perm;             // [n_binned] sorted position -> edge id
+    const SRange* ranges_by_id;
+    int64_t n_binned;
+    double R;
+    void* rec;                        // StrutRec<T> [n_binned]
+    SRange* ranges;                   // [n_binned]
+    void* w;                          // T [n_binned]
+    int2* ends;                       // [n_binned]
+};
+lsl_status launch_gather(int dtype, const GatherArgs& a, hipStream_t st);
+lsl_status launch_gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t* dst,
+                             size_t n, hipStream_t st);
+
+// ------------------------------------------------------------------ bin.hip
+struct GroupBuffers {
+    // inputs
+    const SRange* ranges;             // [n_binned]
+    // active lists (double buffered by the caller)
+    const uint32_t* prev_active;      // may be null
+    uint32_t n_prev;
+    uint32_t range_lo, range_hi;      // sorted positions [lo, hi) to consider
+    uint32_t* active;                 // out [n_active]
+    uint32_t n_active;
+    int32_t sa, sb;                   // slabs of the group
+    int32_t ntx, nty;
+    uint32_t n_pairs;
+    uint32_t n_buckets;
+    // outputs
+    uint32_t* eoff;                   // [n_active + 1]
+    uint32_t* offsets;                // [n_buckets + 1]
+    uint32_t* ids;                    // [n_pairs] sorted positions
+    uint32_t* inv;                    // [n_pairs] emission -> bucket position
+    uint32_t* owner;                  // [n_pairs] scratch
+    uint32_t* k0; uint32_t* v0; uint32_t* k1; uint32_t* v1;   // [n_pairs] scratch
+    uint32_t* tmp;                    // scan / sort scratch
+    uint32_t* blk;                    // compaction block counts
+};
+size_t group_tmp_elems(size_t n_pairs, size_t n_active, size_t n_cand);
+lsl_status bin_group(const GroupBuffers& g, hipStream_t st);
+
+// ---------------------------------------------------------------- field.hip
+struct FieldArgs {
+    const void* rec;
+    const uint32_t* offsets;
+    const uint32_t* ids;
+    uint32_t n_binned, n_pairs;       // bounds of rec[] and ids[]
+    int32_t ntx, nty, tile, slab;
+    int32_t group_s0;                 // first slab of the resident group
+    int32_t s_lo, s_hi;               // slabs to evaluate (absolute)
+    int32_t k0, nk;                   // planes written: [k0, k0+nk)
+    int32_t W, H;
+    double x0, y0, dx, dy, z0, dz, R;
+    void* field;                      // [nk][H][W]
+    unsigned long long* stats;        // [3] (stats kernels only)
+};
+lsl_status launch_field(int dtype, const FieldArgs& a, bool stats, hipStream_t st);
+lsl_status launch_bits(int dtype, const void* field, int32_t nk, int32_t W, int32_t H,
+                       double C, uint32_t* bits, hipStream_t st);
+
+// ------------------------------------------------------------- contours.hip
+size_t contour_tmp_elems(int32_t nk, int32_t W, int32_t H);
+// base (optional, device): running segment count added to this call's
+// offsets and positions; the emit pass advances it by this call's total.
+lsl_status launch_contours_count(int dtype, const void* field, int32_t nk, int32_t W,
+                                 int32_t H, double C, int64_t* offsets, uint8_t* codes,
+                                 unsigned long long* tmp, const unsigned long long* base,
+                                 hipStream_t st);
+lsl_status launch_contours_emit(int dtype, const void* field, int32_t nk, int32_t W,
+                                int32_t H, double C, const unsigned long long* tmp,
+                                unsigned long long* base, float* segs, int64_t capacity,
+                                hipStream_t st);
+
+// ------------------------------------------------------------- backward.hip
+struct BackArgs {
+    const void* rec;
+    const uint32_t* offsets;
+    const uint32_t* ids;
+    uint32_t n_binned, n_pairs;
+    int32_t ntx, nty, tile, slab;
+    int32_t group_s0;
+    int32_t s_lo, s_hi;
+    int32_t k0, nk;
+    int32_t W, H;
+    double x0, y0, dx, dy, z0, dz, R;
+    const void* grad;                 // [nk][H][W]
+    void* partial;                    // [n_pairs][10] T
+};
+lsl_status launch_backward(int dtype, const BackArgs& a, hipStream_t st);
+
+struct ReduceArgs {
+    const void* partial;              // [n_pairs][10]
+    const uint32_t* active;           // [n_active] sorted positions
+    uint32_t n_active;
+    const uint32_t* eoff;             // [n_active + 1]
+    const uint32_t* inv;              // emission -> bucket position
+    const void* rec;
+    const void* w;
+    double R;
+    double* acc;                      // [n_binned][7]: dL/dw, dL/da (3), dL/db (3)
+};
+lsl_status launch_reduce(int dtype, const ReduceArgs& a, const SRange* ranges, int32_t sa,
+                         int32_t s_lo, int32_t s_hi, uint32_t n_pairs, uint32_t n_binned,
+                         hipStream_t st);
+
+struct ScatterArgs {
+    const double* acc;                // [n_binned][7]
+    const uint32_t* perm;             // sorted position -> edge id
+    int64_t n_binned, n_edges, n_nodes;
+    const uint32_t* node_off;         // [n_nodes + 1]
+    const uint32_t* node_inc;         // incidences 2p + end
+    void* grad_weight;                // [n_edges] or null
+    void* grad_nodes;                 // [n_nodes][3] or null
+    int32_t accumulate;
+};
+lsl_status launch_scatter(int dtype, const ScatterArgs& a, hipStream_t st);
+lsl_status launch_node_keys(const int2* ends, int64_t n_binned, uint32_t* keys,
+                            uint32_t* vals, hipStream_t st);
+lsl_status launch_node_offsets(const uint32_t* sorted_keys, size_t n, int64_t n_nodes,
+                               uint32_t* node_off, hipStream_t st);
+
+// ---------------------------------------------------------------- batch.hip
+struct BatchArgs {
+    FieldArgs f;
+    const uint32_t* queue;            // items (s_rel, tile) in cost order
+    uint32_t n_items;
+    uint32_t* counter;                // device work counter (zeroed per launch)
+};
+lsl_status launch_queue_build(const FieldArgs& f, uint32_t* keys, uint32_t* vals,
+                              uint32_t* keys_alt, uint32_t* vals_alt, uint32_t n_items,
+                              uint32_t* tmp, const uint32_t** queue_out, hipStream_t st);
+// The caller zeroes a.counter before the launch.
+lsl_status launch_persistent(int dtype, const BatchArgs& a, int n_blocks, hipStream_t st);
+int persistent_blocks(int dtype, int slab);
+
+}  // namespace lsl

@@ -8,20 +8,20 @@ FP64 oracle's tests draw their inputs from here; nothing here imports either.
 The paper's own models (Table 4: Teddy ... Kitten-HR) are not available, so
 lattices of the same kind stand in for them: tetrahedral lattices built from a
 cube grid split into Kuhn simplices (the paper builds its lattices from the
-edges of a tetrahedral mesh, Sec. 4.1) and a uniform BCC cell lattice.
+edges of a tetrahedral mesh, Sec. 5.1) and a uniform BCC cell lattice.
 
 Input recipe (units are mm):
 
 * A strut graph is (nodes [N,3], edges [E,2] int32, weight [E]); an edge is
-  (v_s, v_e, r) as in Sec. 2.1.
+  (v_s, v_e, r) as in Sec. 3.1.
 * Physical strut radii rho are mapped to the paper's per-edge weight r of
   Eq. (6) with :func:`weight_for_radius`: the weight that puts the iso-surface
   g = C of an isolated, infinitely long strut at distance rho from its axis.
-  The paper only says the map is monotone (Sec. 2.2); this choice is an input
+  The paper only says the map is monotone (Sec. 3.2); this choice is an input
   convention, not part of the method.
 * The kernel support is R = 1.5 x the largest radius the recipe can produce
-  (Sec. 2.2 uses 1.5 x the maximal radius), and the iso-value is C = 1.
-* Slices sit at z0 + (k + 1/2) dz with z0 the lowest node (Sec. 3, Step 1).
+  (Sec. 3.2 uses 1.5 x the maximal radius), and the iso-value is C = 1.
+* Slices sit at z0 + (k + 1/2) dz with z0 the lowest node (Sec. 4, Step 1).
 * Pixels are square; the grid covers the lattice's xy bounding box grown by R
   plus two pixels on each side, so that every contour closes inside the image.
 """

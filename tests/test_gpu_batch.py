@@ -1,0 +1,107 @@
+"""GPU checks of the persistent, graph-captured batched path and of the
+autotuner."""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import contours as OC
+from oracle import slicer as OS
+from paper_2101_05031_amd import _native as N
+from paper_2101_05031_amd import api, synth
+
+from gpu_util import assert_field_close, bin_lattice, to_dev, unpack_bits
+
+pytestmark = pytest.mark.gpu
+
+
+def uneven_case():
+    """8-blob radii with voids: planes and tiles carry very uneven work."""
+    lat = synth.kuhn_lattice(8, 30.0, seed=3, radius="blobs", r_min=0.1, r_span=0.5,
+                             void_below=0.15)
+    grid = synth.grid_for(lat, 259, 247, 40, dz=0.7)
+    return lat, grid
+
+
+@pytest.mark.parametrize("max_pairs", [0, 20000])
+def test_batch_equals_plain_path(max_pairs):
+    """Persistent + graph path: field bitwise equal to slice_field, bits and
+    segments equal to slice_contours, over one or several slab groups; the
+    graph replays give the same result."""
+    lat, grid = uneven_case()
+    assert (lat.weight == 0).any()
+    b = bin_lattice(lat, grid, max_pairs=max_pairs)
+    S = grid.n_slices
+    ref = api.slice_field(b, 0, S)
+    rsegs, roff, _ = api.slice_contours(b, ref)
+    cap = len(rsegs) + 16
+    for rep in range(3):
+        field = torch.empty_like(ref)
+        bits = torch.empty((S, grid.H, (grid.W + 31) // 32), dtype=torch.int32, device="cuda")
+        segs = torch.empty((cap, 4), dtype=torch.float32, device="cuda")
+        offs = torch.empty(S + 1, dtype=torch.int64, device="cuda")
+        st, total, _, _ = api.slice_batch(b, 0, S, field=field, bits=bits, capacity=cap,
+                                          segs=segs, offsets=offs)
+        assert st == N.LSL_OK and total == len(rsegs)
+        assert torch.equal(field.view(torch.int32), ref.view(torch.int32))
+        assert np.array_equal(unpack_bits(bits, grid.W), ref.cpu().numpy() >= lat.C)
+        assert torch.equal(offs, roff)
+        assert torch.equal(segs[:total], rsegs)
+    info = b.info()
+    assert info["last_field_ms"] > 0
+
+
+def test_batch_without_field_buffer_and_capacity():
+    lat, grid = uneven_case()
+    b = bin_lattice(lat, grid, max_pairs=15000)
+    S = grid.n_slices
+    ref = api.slice_field(b, 3, S - 3)
+    rsegs, roff, _ = api.slice_contours(b, ref)
+    cap = len(rsegs)
+    st, total, segs, offs = api.slice_batch(b, 3, S - 3, capacity=cap)
+    assert st == N.LSL_OK and total == cap
+    assert torch.equal(segs[:total], rsegs)
+    assert torch.equal(offs, roff)
+    st, total, _, offs2 = api.slice_batch(b, 3, S - 3, capacity=cap - 5,
+                                          segs=torch.empty((cap - 5, 4), device="cuda"))
+    assert st == N.LSL_ECAPACITY and total == cap
+    assert torch.equal(offs2, roff)
+
+
+def test_batch_matches_oracle_on_uneven_planes():
+    lat, grid = uneven_case()
+    b = bin_lattice(lat, grid)
+    S = grid.n_slices
+    field = torch.empty((S, grid.H, grid.W), dtype=torch.float32, device="cuda")
+    st, total, segs, offs = api.slice_batch(b, 0, S, field=field, capacity=10**6)
+    fh = field.cpu().numpy()
+    ks = [0, 7, 19, 33, 39]
+    ref = np.stack([OS.slice_field(lat.nodes, lat.edges, lat.weight, lat.R, grid, k) for k in ks])
+    assert_field_close(fh[ks], ref, lat.C, 1e-5, "batch")
+    segs = segs.cpu().numpy().astype(np.float64)
+    offs = offs.cpu().numpy()
+    for k in ks:
+        assert np.array_equal(segs[offs[k]:offs[k + 1]], OC.segments(fh[k] >= lat.C))
+
+
+def test_autotune_choice_and_cache(tmp_path):
+    lat, grid = uneven_case()
+    n, e, w = to_dev(lat)
+    path = str(tmp_path / "tune.json")
+    p = api.slice_autotune(n, e, w, lat.R, lat.C, grid, cache_path=path)
+    assert p["tile"] in (16, 32) and p["slab"] in (4, 8, 16)
+    data = json.load(open(path))
+    assert len(data) == 1
+    # a cache hit returns the stored choice
+    p2 = api.slice_autotune(n, e, w, lat.R, lat.C, grid, cache_path=path)
+    assert p2 == p
+    # a fixed field is kept
+    p3 = api.slice_autotune(n, e, w, lat.R, lat.C, grid, slab=4)
+    assert p3["slab"] == 4
+    # the choice does not change the field
+    b0 = bin_lattice(lat, grid)
+    b1 = bin_lattice(lat, grid, tile=p["tile"], slab=p["slab"])
+    f0 = api.slice_field(b0, 0, grid.n_slices)
+    f1 = api.slice_field(b1, 0, grid.n_slices)
+    assert torch.equal(f0.view(torch.int32), f1.view(torch.int32))

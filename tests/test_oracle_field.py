@@ -181,7 +181,7 @@ def test_radius_to_weight_places_iso_surface():
 
 
 def test_smaller_weight_thinner_strut():
-    """Sec. 2.2: decreasing r_i moves the iso-surface towards the edge."""
+    """Sec. 3.2: decreasing r_i moves the iso-surface towards the edge."""
     R = 1.5
     a = np.array([0.0, 0.0, -40.0])
     b = np.array([0.0, 0.0, 40.0])
