@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -89,10 +90,11 @@ struct lattice_bins {
     // persistent path: captured graphs keyed by their launch arguments
     struct GraphEntry {
         std::vector<unsigned char> key;
-        hipGraphExec_t exec;
-        hipEvent_t e0, e1;          // around the persistent field kernel (may be null)
+        hipGraphExec_t exec[3];     // queue build | persistent field | image + contours
+        hipEvent_t e0, e1;          // recorded on the caller's stream around exec[1]
     };
     double last_field_ms = -1.0;
+    bool queue_in_alt = false;      // the sorted work queue is in the alternate buffer
     std::vector<GraphEntry> graphs;
 
     ~lattice_bins() {
@@ -135,7 +137,8 @@ struct lattice_bins {
     size_t esize() const { return dtype == LSL_F64 ? 8 : 4; }
     void drop_graphs() {
         for (auto& g : graphs) {
-            hipGraphExecDestroy(g.exec);
+            for (auto& x : g.exec)
+                if (x) hipGraphExecDestroy(x);
             if (g.e0) hipEventDestroy(g.e0);
             if (g.e1) hipEventDestroy(g.e1);
         }
@@ -784,11 +787,14 @@ struct BatchKey {
     int64_t capacity;
 };
 
-// Enqueues one group's part of slice_batch on `st`: queue build, persistent
-// field launch, binary image and contours (positions continue from *base).
+// Enqueues one phase of a group's part of slice_batch on `st`:
+//   0: work queue (descending cost) and counter reset
+//   1: persistent field kernel
+//   2: binary image and contours (positions continue from the device-side
+//      running total of earlier groups)
 lsl_status batch_group_work(lattice_bins* b, int g, int32_t k0, int32_t nk, int s_lo, int s_hi,
                             void* field, uint32_t* bits, float* segs, int64_t capacity,
-                            int64_t* offsets, hipEvent_t e0, hipEvent_t e1, hipStream_t st) {
+                            int64_t* offsets, int phase, hipStream_t st) {
     const int kg0 = std::max(k0, s_lo * b->slab);
     const int kg1 = std::min(k0 + nk, (s_hi + 1) * b->slab);
     const int nkg = kg1 - kg0;
@@ -808,27 +814,58 @@ lsl_status batch_group_work(lattice_bins* b, int g, int32_t k0, int32_t nk, int 
     uint32_t* qv2 = qk2 + b->queue_cap;
     uint32_t* counter = qv2 + b->queue_cap;
     uint32_t* qtmp = counter + 64;
-    const uint32_t* queue = nullptr;
-    LSL_TRY(launch_queue_build(a, qk, qv, qk2, qv2, n_items, qtmp, &queue, st));
-    BatchArgs ba{};
-    ba.f = a;
-    ba.queue = queue;
-    ba.n_items = n_items;
-    ba.counter = counter;
-    const int nblocks = persistent_blocks(b->dtype, b->slab);
-    LSL_TRY(fill_u32(counter, 0u, 1, st));
-    if (e0) LSL_HIP(hipEventRecord(e0, st));
-    LSL_TRY(launch_persistent(b->dtype, ba, nblocks, st));
-    if (e1) LSL_HIP(hipEventRecord(e1, st));
+    unsigned long long* base = (unsigned long long*)(counter + 32);
+    if (phase == 0) {
+        const uint32_t* queue = nullptr;
+        LSL_TRY(launch_queue_build(a, qk, qv, qk2, qv2, n_items, qtmp, &queue, st));
+        LSL_TRY(fill_u32(counter, 0u, 1, st));
+        b->queue_in_alt = queue != qv;
+        return LSL_OK;
+    }
+    if (phase == 1) {
+        BatchArgs ba{};
+        ba.f = a;
+        ba.queue = b->queue_in_alt ? qv2 : qv;
+        ba.n_items = n_items;
+        ba.counter = counter;
+        return launch_persistent(b->dtype, ba, persistent_blocks(b->dtype, b->slab), st);
+    }
     const size_t words = (size_t)(b->grid.W + 31) / 32;
     if (bits)
         LSL_TRY(launch_bits(b->dtype, fbase, nkg, b->grid.W, b->grid.H, b->C,
                             bits + (size_t)(kg0 - k0) * (size_t)b->grid.H * words, st));
-    unsigned long long* base = (unsigned long long*)(counter + 32);
     LSL_TRY(launch_contours_count(b->dtype, fbase, nkg, b->grid.W, b->grid.H, b->C,
                                   offsets + (kg0 - k0), nullptr, b->ctmp, base, st));
     LSL_TRY(launch_contours_emit(b->dtype, fbase, nkg, b->grid.W, b->grid.H, b->C, b->ctmp, base,
                                  segs, capacity, st));
+    return LSL_OK;
+}
+
+lsl_status capture(hipStream_t cap, hipGraphExec_t* exec, const std::function<lsl_status(hipStream_t)>& fn) {
+    *exec = nullptr;
+    LSL_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    lsl_status ws = fn(cap);
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamEndCapture(cap, &graph);
+    if (ws != LSL_OK) {
+        if (graph) hipGraphDestroy(graph);
+        hipGetLastError();
+        return ws;
+    }
+    if (ce != hipSuccess || !graph) {
+        if (graph) hipGraphDestroy(graph);
+        hipGetLastError();
+        set_error(std::string("slice_batch: graph capture failed: ") + hipGetErrorString(ce));
+        return LSL_EDEVICE;
+    }
+    hipError_t ie = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+        *exec = nullptr;
+        hipGetLastError();
+        set_error(std::string("slice_batch: graph instantiation failed: ") + hipGetErrorString(ie));
+        return LSL_EDEVICE;
+    }
     return LSL_OK;
 }
 
@@ -844,7 +881,7 @@ lsl_status slice_field_backward(lattice_bins* b, int32_t k0, int32_t nk, const v
     LSL_CHECK(grad_field != nullptr, "grad_field is NULL");
     hipStream_t st = S(stream);
     if (!b->acc) LSL_TRY(b->alloc_t(&b->acc, (size_t)std::max<uint32_t>(b->n_binned, 1) * 7));
-    if (!b->partial) LSL_TRY(b->alloc(&b->partial, b->cap_pairs * 10 * b->esize()));
+    if (!b->partial) LSL_TRY(b->alloc(&b->partial, b->cap_pairs * 9 * b->esize()));
     LSL_TRY(ensure_node_csr(b, st));
     LSL_TRY(fill_bytes0(b->acc, (size_t)std::max<uint32_t>(b->n_binned, 1) * 7 * 8, st));
     if (b->n_binned && !b->groups.empty()) {
@@ -937,44 +974,35 @@ lsl_status slice_batch(lattice_bins* b, int32_t k0, int32_t nk, void* field, uin
         LSL_TRY(ensure_group(b, g, st));
         BatchKey key{g, k0, nk, 0, field, bits, segs, offsets, capacity};
         std::vector<unsigned char> kb((unsigned char*)&key, (unsigned char*)&key + sizeof(key));
-        hipGraphExec_t exec = nullptr;
+        lattice_bins::GraphEntry* ent = nullptr;
         for (auto& ge : b->graphs)
-            if (ge.key == kb) exec = ge.exec;
-        if (!exec) {
+            if (ge.key == kb) ent = &ge;
+        if (!ent) {
             if (!cap) LSL_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-            // capture with timing events first; without them if that fails
-            for (int attempt = 0; attempt < 2 && !exec; ++attempt) {
-                hipEvent_t e0 = nullptr, e1 = nullptr;
-                if (attempt == 0) {
-                    LSL_HIP(hipEventCreate(&e0));
-                    LSL_HIP(hipEventCreate(&e1));
+            lattice_bins::GraphEntry ne{};
+            ne.key = kb;
+            for (int ph = 0; ph < 3; ++ph) {
+                lsl_status cs = capture(cap, &ne.exec[ph], [&](hipStream_t cs_st) {
+                    return batch_group_work(b, g, k0, nk, s_lo, s_hi, field, bits, segs,
+                                            capacity, offsets, ph, cs_st);
+                });
+                if (cs != LSL_OK) {
+                    for (auto& x : ne.exec)
+                        if (x) hipGraphExecDestroy(x);
+                    if (cap) hipStreamDestroy(cap);
+                    return cs;
                 }
-                LSL_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-                lsl_status ws = batch_group_work(b, g, k0, nk, s_lo, s_hi, field, bits, segs,
-                                                 capacity, offsets, e0, e1, cap);
-                hipGraph_t graph = nullptr;
-                hipError_t ce = hipStreamEndCapture(cap, &graph);
-                hipError_t ie = hipErrorUnknown;
-                if (ws == LSL_OK && ce == hipSuccess && graph)
-                    ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-                if (graph) hipGraphDestroy(graph);
-                if (ie != hipSuccess) {
-                    exec = nullptr;
-                    hipGetLastError();
-                    if (e0) hipEventDestroy(e0);
-                    if (e1) hipEventDestroy(e1);
-                    if (attempt == 1) {
-                        if (ws != LSL_OK) return ws;
-                        set_error(std::string("slice_batch: graph capture failed: ") +
-                                  hipGetErrorString(ce != hipSuccess ? ce : ie));
-                        return LSL_EDEVICE;
-                    }
-                    continue;
-                }
-                b->graphs.push_back({kb, exec, e0, e1});
             }
+            LSL_HIP(hipEventCreate(&ne.e0));
+            LSL_HIP(hipEventCreate(&ne.e1));
+            b->graphs.push_back(ne);
+            ent = &b->graphs.back();
         }
-        LSL_HIP(hipGraphLaunch(exec, st));
+        LSL_HIP(hipGraphLaunch(ent->exec[0], st));
+        LSL_HIP(hipEventRecord(ent->e0, st));
+        LSL_HIP(hipGraphLaunch(ent->exec[1], st));
+        LSL_HIP(hipEventRecord(ent->e1, st));
+        LSL_HIP(hipGraphLaunch(ent->exec[2], st));
         return LSL_OK;
     }));
     if (cap) hipStreamDestroy(cap);
@@ -989,10 +1017,12 @@ lsl_status slice_batch(lattice_bins* b, int32_t k0, int32_t nk, void* field, uin
         for (auto& ge : b->graphs)
             if (ge.key == kb) {
                 float ms = 0.0f;
-                if (ge.e0 && hipEventElapsedTime(&ms, ge.e0, ge.e1) == hipSuccess)
+                if (hipEventElapsedTime(&ms, ge.e0, ge.e1) == hipSuccess) {
                     b->last_field_ms += ms;
-                else
+                } else {
+                    hipGetLastError();
                     b->last_field_ms = -1e30;
+                }
             }
         return LSL_OK;
     }));

@@ -3,27 +3,38 @@
 // Sec. 5.3 changes exactly the strut weights r).
 //
 // Per pixel p and strut (a, b) with u = (b - a)/L, q = a - p, alpha = q.u,
-// beta = alpha + L, H = R^2 - |q|^2 + alpha^2 and the clamped ends ca, cb:
+// beta = alpha + L, H = R^2 - |q|^2 + alpha^2 (squared half chord), the
+// clamped ends ca, cb and q_perp = q - alpha u (the offset of the line from
+// p, |q_perp| < R):
 //
-//   I      = R^-4 (cb - ca) Q                       (the field term / r)
-//   dI/dalpha = -phi(alpha), dI/dbeta = phi(beta),   phi(t) = R^-4 max(H - t^2, 0)^2
-//   dI/dH  = 2 R^-4 (cb - ca) (H - S1/3)
-//   K      = dI/dalpha + dI/dbeta + 2 alpha dI/dH
-//   dI/db  = K q_perp/L + dI/dbeta u,          q_perp = q - alpha u
-//   dI/da  = K (u - q_perp/L) - dI/dbeta u - 2 dI/dH q
+//   I       = R^-4 (cb - ca) Q                         (the field term / r)
+//   dI/dalpha = -phi(alpha), dI/dbeta = phi(beta),     phi(t) = R^-4 max(H - t^2, 0)^2
+//   J = dI/dH = 2 R^-4 (cb - ca) (H - S1/3)
+//   K = dI/dalpha + dI/dbeta + 2 alpha J
 //
-// so the loss gradient of one strut only needs ten pixel sums:
-//   Aw = sum G I, AK = sum G K, AKa = sum G K alpha, AKq = sum G K q (3),
-//   Ab = sum G phi(beta), AHq = sum G dI/dH q (3),
-// from which dL/dr = Aw, dL/db = r [(AKq - AKa u)/L + Ab u],
-// dL/da = r [AK u - (AKq - AKa u)/L - Ab u - 2 AHq].
+// and, through u = (b - a)/|b - a| and q,
+//
+//   dI/db = phi(beta) u + (K/L) q_perp
+//   dI/da = -phi(alpha) u - (K/L + 2J) q_perp
+//
+// (the alpha-sized parts of K u and 2 J q cancel exactly, so every summed
+// quantity stays of the size of R).  The loss gradient of a strut needs nine
+// pixel sums: Aw = sum G I, Aa = sum G phi(alpha), Ab = sum G phi(beta),
+// AKq = sum G K q_perp (3), AJq = sum G J q_perp (3):
+//
+//   dL/dr = Aw,  dL/db = r [Ab u + AKq / L],  dL/da = -r [Aa u + AKq / L + 2 AJq].
+//
+// Around the 8x8 block centre c, q_perp = m - d + (d.u) u with m = F - c the
+// offset of the foot F of c (uniform per strut and plane) and d = p - c the
+// pixel's offset, so sum G K q_perp = sum G K m - d sum G K + u sum G K (d.u):
+// each pair adds to thirteen registers without forming q_perp.
 //
 // Work split.  One wave takes one (tile, slab) bucket and walks the tile's
 // 8x8 blocks in a fixed order.  For 32 list entries at a time it stages, per
 // block and plane, the same block-centre quantities as the forward pass
-// (m, tc, and q_c = a - c), compacts the struts that reach the block in any
+// (m and tc), compacts the struts that reach the block in any
 // plane of the slab, and then for each such strut loops over only the planes
-// it reaches: every lane adds its pixel's contribution to eleven registers,
+// it reaches: every lane adds its pixel's contribution to thirteen registers,
 // the wave sums them once per (strut, block), and lane 0 adds the sums into
 // the entry's LDS slot.  The slots are written once per bucket entry, so each
 // (slab, tile, strut) pair gets exactly one partial, with no atomics.
@@ -36,10 +47,11 @@ namespace lsl {
 namespace {
 
 constexpr int kChunk = 32;      // bucket entries staged at a time
+constexpr int kParts = 9;       // pixel sums per (strut, bucket)
 
 template <typename T>
 struct alignas(16) BStrut {
-    T ux, uy, pad0, pad1;
+    T ux, uy, uz, pad;
     uint32_t planes;            // bit k: the strut reaches the block in plane k
     uint32_t pos;               // entry index within the chunk
 };
@@ -47,7 +59,7 @@ struct alignas(16) BStrut {
 template <typename T>
 struct alignas(16) BPlane {
     T mx2, my2, ntc, H0;        // as in the forward pass
-    T qx, qy, qz, nbtc;         // q_c = a - c; L - tc
+    T mx, my, mz, nbtc;         // m = F - c; L - tc
 };
 
 template <typename T>
@@ -88,7 +100,7 @@ template <typename T, int SZ>
 __global__ __launch_bounds__(64) void k_backward(BackArgs a, uint32_t n_items) {
     __shared__ BStrut<T> bs[kChunk];
     __shared__ BPlane<T> bp[kChunk][SZ];
-    __shared__ T slot[kChunk][10];
+    __shared__ T slot[kChunk][kParts];
 
     const int lane = lane_id();
     const uint32_t item = xcd_remap(blockIdx.x, gridDim.x);
@@ -125,7 +137,7 @@ __global__ __launch_bounds__(64) void k_backward(BackArgs a, uint32_t n_items) {
 
     for (uint32_t cbase = beg; cbase < end; cbase += kChunk) {
         const int nent = (int)((end - cbase) < (uint32_t)kChunk ? (end - cbase) : (uint32_t)kChunk);
-        for (int q = lane; q < kChunk * 10; q += kWave) (&slot[0][0])[q] = T(0);
+        for (int q = lane; q < kChunk * kParts; q += kWave) (&slot[0][0])[q] = T(0);
         __builtin_amdgcn_wave_barrier();
 
         // this chunk's strut records, one per lane (lanes >= nent idle)
@@ -175,9 +187,9 @@ __global__ __launch_bounds__(64) void k_backward(BackArgs a, uint32_t n_items) {
                         P.my2 = (T)(2.0 * my);
                         P.ntc = (T)(-tc);
                         P.H0 = (T)(R2 - m2);
-                        P.qx = (T)(-wx);          // q_c = a - c
-                        P.qy = (T)(-wy);
-                        P.qz = (T)(-wz);
+                        P.mx = (T)mx;
+                        P.my = (T)my;
+                        P.mz = (T)mz;
                         P.nbtc = (T)(L - tc);
                         bp[lane][k] = P;
                     }
@@ -189,8 +201,8 @@ __global__ __launch_bounds__(64) void k_backward(BackArgs a, uint32_t n_items) {
                 BStrut<T> b;
                 b.ux = (T)ux;
                 b.uy = (T)uy;
-                b.pad0 = T(0);
-                b.pad1 = T(0);
+                b.uz = (T)uz;
+                b.pad = T(0);
                 b.planes = planes;
                 b.pos = (uint32_t)lane;
                 bs[__popcll(mask & lt)] = b;
@@ -199,8 +211,8 @@ __global__ __launch_bounds__(64) void k_backward(BackArgs a, uint32_t n_items) {
             const int n = __popcll(mask);
             for (int j = 0; j < n; ++j) {
                 const BStrut<T> b = bs[j];
-                T Aw = 0, AK = 0, AKa = 0, AKx = 0, AKy = 0, AKz = 0, Ab = 0, AH = 0, AHx = 0,
-                  AHy = 0, AHz = 0;
+                T Aw = 0, Aa = 0, Ab = 0, AK = 0, AKx = 0, AKy = 0, AKz = 0, AKd = 0, AJ = 0,
+                  AJx = 0, AJy = 0, AJz = 0, AJd = 0;
 #pragma unroll
                 for (int k = 0; k < SZ; ++k) {
                     if (k < nvalid && ((b.planes >> k) & 1u)) {
@@ -223,31 +235,33 @@ __global__ __launch_bounds__(64) void k_backward(BackArgs a, uint32_t n_items) {
                         pa = pa > T(0) ? pa * pa : T(0);
                         T pb = dfma(-be, be, H);
                         pb = pb > T(0) ? pb * pb : T(0);
-                        const T IH = dfma(T(-1.0 / 3.0), S1, H) * D;    // (dI/dH) R^4 / 2
-                        const T K = dfma(T(4) * al, IH, pb - pa);        // K R^4
-                        const T gK = g * K;
-                        AK += gK;
-                        AKa = dfma(gK, al, AKa);
-                        AKx = dfma(gK, P.qx, AKx);
-                        AKy = dfma(gK, P.qy, AKy);
-                        AKz = dfma(gK, P.qz, AKz);
+                        Aa = dfma(g, pa, Aa);
                         Ab = dfma(g, pb, Ab);
-                        const T gH = g * IH;
-                        AH += gH;
-                        AHx = dfma(gH, P.qx, AHx);
-                        AHy = dfma(gH, P.qy, AHy);
-                        AHz = dfma(gH, P.qz, AHz);
+                        const T J = T(2) * dfma(T(-1.0 / 3.0), S1, H) * D;   // J R^4
+                        const T K = dfma(T(2) * al, J, pb - pa);               // K R^4
+                        const T gK = g * K, gJ = g * J;
+                        AK += gK;
+                        AKx = dfma(gK, P.mx, AKx);
+                        AKy = dfma(gK, P.my, AKy);
+                        AKz = dfma(gK, P.mz, AKz);
+                        AKd = dfma(gK, du, AKd);
+                        AJ += gJ;
+                        AJx = dfma(gJ, P.mx, AJx);
+                        AJy = dfma(gJ, P.my, AJy);
+                        AJz = dfma(gJ, P.mz, AJz);
+                        AJd = dfma(gJ, du, AJd);
                     }
                 }
-                // q = q_c - d for the lane's pixel (d = (dX, dY, 0))
-                AKx = dfma(-dX, AK, AKx);
-                AKy = dfma(-dY, AK, AKy);
-                AHx = dfma(-dX, AH, AHx);
-                AHy = dfma(-dY, AH, AHy);
-                const T v0 = wave_sum(Aw), v1 = wave_sum(AK), v2 = wave_sum(AKa),
+                // sum G K q_perp = sum G K m - d sum G K + u sum G K (d.u), d = (dX, dY, 0)
+                AKx = dfma(b.ux, AKd, dfma(-dX, AK, AKx));
+                AKy = dfma(b.uy, AKd, dfma(-dY, AK, AKy));
+                AKz = dfma(b.uz, AKd, AKz);
+                AJx = dfma(b.ux, AJd, dfma(-dX, AJ, AJx));
+                AJy = dfma(b.uy, AJd, dfma(-dY, AJ, AJy));
+                AJz = dfma(b.uz, AJd, AJz);
+                const T v0 = wave_sum(Aw), v1 = wave_sum(Aa), v2 = wave_sum(Ab),
                         v3 = wave_sum(AKx), v4 = wave_sum(AKy), v5 = wave_sum(AKz),
-                        v6 = wave_sum(Ab), v7 = wave_sum(AHx), v8 = wave_sum(AHy),
-                        v9 = wave_sum(AHz);
+                        v6 = wave_sum(AJx), v7 = wave_sum(AJy), v8 = wave_sum(AJz);
                 if (lane == 0) {
                     T* sl = slot[b.pos];
                     sl[0] += v0;
@@ -257,17 +271,16 @@ __global__ __launch_bounds__(64) void k_backward(BackArgs a, uint32_t n_items) {
                     sl[4] += v4;
                     sl[5] += v5;
                     sl[6] += v6;
-                    sl[7] += T(2) * v7;       // dI/dH R^4 = 2 IH
-                    sl[8] += T(2) * v8;
-                    sl[9] += T(2) * v9;
+                    sl[7] += v7;
+                    sl[8] += v8;
                 }
                 __builtin_amdgcn_wave_barrier();
             }
             __builtin_amdgcn_wave_barrier();
         }
         __builtin_amdgcn_wave_barrier();
-        for (int q = lane; q < nent * 10; q += kWave)
-            part[(size_t)cbase * 10 + (size_t)q] = (&slot[0][0])[q];
+        for (int q = lane; q < nent * kParts; q += kWave)
+            part[(size_t)cbase * kParts + (size_t)q] = (&slot[0][0])[q];
         __builtin_amdgcn_wave_barrier();
     }
 }
@@ -289,31 +302,27 @@ __global__ void k_reduce(ReduceArgs a, const SRange* ranges, int32_t sa, int32_t
     if (hi < lo) return;
     const uint32_t e0 = a.eoff[i] + (uint32_t)(lo - s0) * nxy;
     const uint32_t e1 = a.eoff[i] + (uint32_t)(hi - s0 + 1) * nxy;
-    double s[10];
-    for (int q = 0; q < 10; ++q) s[q] = 0.0;
+    double s[kParts];
+    for (int q = 0; q < kParts; ++q) s[q] = 0.0;
     const T* part = (const T*)a.partial;
     for (uint32_t e = e0; e < e1; ++e) {
         const uint32_t pos = a.inv[e];
         if (pos >= n_pairs) continue;
-        for (int q = 0; q < 10; ++q) s[q] += (double)part[(size_t)pos * 10 + q];
+        for (int q = 0; q < kParts; ++q) s[q] += (double)part[(size_t)pos * kParts + q];
     }
     const StrutRec<T> r = ((const StrutRec<T>*)a.rec)[p];
     const double w = (double)((const T*)a.w)[p];
     const double R4 = a.R * a.R * a.R * a.R;
     const Line ln = strut_line(r);
-    const double ux = ln.ux, uy = ln.uy, uz = ln.uz, L = ln.L;
+    const double u[3] = {ln.ux, ln.uy, ln.uz};
     const double cw = w / R4;
-    // (AKq - AKa u) / L
-    const double px = (s[3] - s[2] * ux) / L, py = (s[4] - s[2] * uy) / L,
-                 pz = (s[5] - s[2] * uz) / L;
     double* acc = a.acc + (size_t)p * 7;
     acc[0] += s[0] / R4;
-    acc[1] += cw * (s[1] * ux - px - s[6] * ux - 2.0 * s[7]);
-    acc[2] += cw * (s[1] * uy - py - s[6] * uy - 2.0 * s[8]);
-    acc[3] += cw * (s[1] * uz - pz - s[6] * uz - 2.0 * s[9]);
-    acc[4] += cw * (px + s[6] * ux);
-    acc[5] += cw * (py + s[6] * uy);
-    acc[6] += cw * (pz + s[6] * uz);
+    for (int c = 0; c < 3; ++c) {
+        const double kq = s[3 + c] / ln.L;
+        acc[1 + c] -= cw * (s[1] * u[c] + kq + 2.0 * s[6 + c]);     // dL/da
+        acc[4 + c] += cw * (s[2] * u[c] + kq);                       // dL/db
+    }
 }
 
 __global__ void k_node_keys(const int2* ends, int64_t n, uint32_t* keys, uint32_t* vals) {

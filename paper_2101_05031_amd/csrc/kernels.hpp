@@ -118,12 +118,12 @@ struct BackArgs {
     int32_t W, H;
     double x0, y0, dx, dy, z0, dz, R;
     const void* grad;                 // [nk][H][W]
-    void* partial;                    // [n_pairs][10] T
+    void* partial;                    // [n_pairs][9] T
 };
 lsl_status launch_backward(int dtype, const BackArgs& a, hipStream_t st);
 
 struct ReduceArgs {
-    const void* partial;              // [n_pairs][10]
+    const void* partial;              // [n_pairs][9]
     const uint32_t* active;           // [n_active] sorted positions
     uint32_t n_active;
     const uint32_t* eoff;             // [n_active + 1]

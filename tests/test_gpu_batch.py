@@ -18,9 +18,9 @@ pytestmark = pytest.mark.gpu
 
 def uneven_case():
     """8-blob radii with voids: planes and tiles carry very uneven work."""
-    lat = synth.kuhn_lattice(8, 30.0, seed=3, radius="blobs", r_min=0.1, r_span=0.5,
-                             void_below=0.15)
-    grid = synth.grid_for(lat, 259, 247, 40, dz=0.7)
+    lat = synth.kuhn_lattice(10, 100.0, seed=3, radius="blobs", r_min=0.1, r_span=0.5,
+                             void_below=0.3)
+    grid = synth.grid_for(lat, 259, 247, 40, dz=2.6)
     return lat, grid
 
 
