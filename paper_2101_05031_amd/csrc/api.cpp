@@ -80,10 +80,10 @@ struct lattice_bins {
     unsigned long long* stats = nullptr;
     unsigned long long* ctmp = nullptr;
     size_t ctmp_elems = 0;
+    uint32_t* cbits = nullptr;        // binary images: slice_contours, slice_batch
+    size_t cbits_elems = 0;
     uint32_t* queue_buf = nullptr;     // persistent path: keys/vals/alternates + counter
     size_t queue_cap = 0;
-    void* batch_field = nullptr;
-    size_t batch_field_bytes = 0;
     std::vector<std::pair<void*, size_t>> allocs;
     int64_t dev_bytes = 0, peak_bytes = 0;
 
@@ -319,7 +319,9 @@ FieldArgs field_args(const lattice_bins* b, int32_t k0, int32_t nk, void* field)
     a.z0 = b->grid.z0;
     a.dz = b->grid.dz;
     a.R = b->R;
+    a.C = b->C;
     a.field = field;
+    a.bits = nullptr;
     return a;
 }
 
@@ -638,20 +640,21 @@ lsl_status slice_field(lattice_bins* b, int32_t k0, int32_t nk, void* field, uin
     const size_t plane = (size_t)b->grid.W * (size_t)b->grid.H;
     if (b->n_binned == 0 || b->groups.empty()) {
         LSL_TRY(fill_bytes0(field, (size_t)nk * plane * b->esize(), st));
-    } else {
-        // planes whose slabs have no group get zeros: the plan covers all slabs
-        LSL_TRY(for_groups(b, k0, nk, [&](int g, int s_lo, int s_hi) -> lsl_status {
-            LSL_TRY(ensure_group(b, g, st));
-            FieldArgs a = field_args(b, k0, nk, field);
-            a.n_pairs = (uint32_t)b->groups[g].pairs;
-            a.group_s0 = b->groups[g].sa;
-            a.s_lo = s_lo;
-            a.s_hi = s_hi;
-            return launch_field(b->dtype, a, false, st);
-        }));
+        if (bits)
+            LSL_TRY(fill_bytes0(bits, (size_t)nk * b->grid.H * ((b->grid.W + 31) / 32) * 4, st));
+        return LSL_OK;
     }
-    if (bits) LSL_TRY(launch_bits(b->dtype, field, nk, b->grid.W, b->grid.H, b->C, bits, st));
-    return LSL_OK;
+    // the plan covers every slab, so every block of every plane is written
+    return for_groups(b, k0, nk, [&](int g, int s_lo, int s_hi) -> lsl_status {
+        LSL_TRY(ensure_group(b, g, st));
+        FieldArgs a = field_args(b, k0, nk, field);
+        a.bits = bits;
+        a.n_pairs = (uint32_t)b->groups[g].pairs;
+        a.group_s0 = b->groups[g].sa;
+        a.s_lo = s_lo;
+        a.s_hi = s_hi;
+        return launch_field(b->dtype, a, false, st);
+    });
 }
 
 lsl_status slice_field_stats(lattice_bins* b, int32_t k0, int32_t nk, int64_t* counts,
@@ -702,9 +705,22 @@ lsl_status slice_contours(const lattice_bins* cb, int32_t nk, const void* field,
         b->ctmp_elems = 0;
         LSL_TRY(b->alloc_t(&b->ctmp, need));
         b->ctmp_elems = need;
+        b->drop_graphs();
     }
-    LSL_TRY(launch_contours_count(b->dtype, field, nk, b->grid.W, b->grid.H, b->C, offsets,
-                                  case_codes, b->ctmp, nullptr, st));
+    const size_t nbits = (size_t)nk * b->grid.H * ((b->grid.W + 31) / 32);
+    if (nbits > b->cbits_elems) {
+        LSL_HIP(hipStreamSynchronize(st));
+        b->release(b->cbits);
+        b->cbits = nullptr;
+        b->cbits_elems = 0;
+        LSL_TRY(b->alloc_t(&b->cbits, nbits));
+        b->cbits_elems = nbits;
+        b->drop_graphs();
+    }
+    // the binary images, then marching squares on them
+    LSL_TRY(launch_bits(b->dtype, field, nk, b->grid.W, b->grid.H, b->C, b->cbits, st));
+    LSL_TRY(launch_contours_count(b->cbits, nk, b->grid.W, b->grid.H, offsets, case_codes,
+                                  b->ctmp, nullptr, st));
     int64_t tot = 0;
     LSL_HIP(hipMemcpyAsync(&tot, offsets + nk, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     LSL_HIP(hipStreamSynchronize(st));
@@ -715,8 +731,8 @@ lsl_status slice_contours(const lattice_bins* cb, int32_t nk, const void* field,
         return LSL_ECAPACITY;
     }
     if (tot > 0)
-        LSL_TRY(launch_contours_emit(b->dtype, field, nk, b->grid.W, b->grid.H, b->C, b->ctmp,
-                                     nullptr, segs, capacity, st));
+        LSL_TRY(launch_contours_emit(b->cbits, nk, b->grid.W, b->grid.H, b->ctmp, nullptr, segs,
+                                     capacity, st));
     return LSL_OK;
 }
 
@@ -799,10 +815,13 @@ lsl_status batch_group_work(lattice_bins* b, int g, int32_t k0, int32_t nk, int 
     const int kg1 = std::min(k0 + nk, (s_hi + 1) * b->slab);
     const int nkg = kg1 - kg0;
     const size_t plane = (size_t)b->grid.W * (size_t)b->grid.H;
-    // field of this group's planes: the caller's array or library scratch
-    void* fbase = field ? (void*)((char*)field + (size_t)(kg0 - k0) * plane * b->esize())
-                        : b->batch_field;
+    const size_t words = (size_t)(b->grid.W + 31) / 32;
+    // this group's planes: the caller's field (if any) and binary images (the
+    // caller's, or library scratch)
+    void* fbase = field ? (void*)((char*)field + (size_t)(kg0 - k0) * plane * b->esize()) : nullptr;
+    uint32_t* bbase = bits ? bits + (size_t)(kg0 - k0) * (size_t)b->grid.H * words : b->cbits;
     FieldArgs a = field_args(b, kg0, nkg, fbase);
+    a.bits = bbase;
     a.n_pairs = (uint32_t)b->groups[g].pairs;
     a.group_s0 = b->groups[g].sa;
     a.s_lo = s_lo;
@@ -830,14 +849,10 @@ lsl_status batch_group_work(lattice_bins* b, int g, int32_t k0, int32_t nk, int 
         ba.counter = counter;
         return launch_persistent(b->dtype, ba, persistent_blocks(b->dtype, b->slab), st);
     }
-    const size_t words = (size_t)(b->grid.W + 31) / 32;
-    if (bits)
-        LSL_TRY(launch_bits(b->dtype, fbase, nkg, b->grid.W, b->grid.H, b->C,
-                            bits + (size_t)(kg0 - k0) * (size_t)b->grid.H * words, st));
-    LSL_TRY(launch_contours_count(b->dtype, fbase, nkg, b->grid.W, b->grid.H, b->C,
-                                  offsets + (kg0 - k0), nullptr, b->ctmp, base, st));
-    LSL_TRY(launch_contours_emit(b->dtype, fbase, nkg, b->grid.W, b->grid.H, b->C, b->ctmp, base,
-                                 segs, capacity, st));
+    LSL_TRY(launch_contours_count(bbase, nkg, b->grid.W, b->grid.H, offsets + (kg0 - k0),
+                                  nullptr, b->ctmp, base, st));
+    LSL_TRY(launch_contours_emit(bbase, nkg, b->grid.W, b->grid.H, b->ctmp, base, segs, capacity,
+                                 st));
     return LSL_OK;
 }
 
@@ -954,13 +969,14 @@ lsl_status slice_batch(lattice_bins* b, int32_t k0, int32_t nk, void* field, uin
         b->ctmp_elems = ct;
         b->drop_graphs();
     }
-    if (!field && b->batch_field_bytes < max_planes * plane * b->esize()) {
+    const size_t nbits = max_planes * (size_t)b->grid.H * ((b->grid.W + 31) / 32);
+    if (!bits && b->cbits_elems < nbits) {
         LSL_HIP(hipStreamSynchronize(st));
-        b->release(b->batch_field);
-        b->batch_field = nullptr;
-        b->batch_field_bytes = 0;
-        LSL_TRY(b->alloc(&b->batch_field, max_planes * plane * b->esize()));
-        b->batch_field_bytes = max_planes * plane * b->esize();
+        b->release(b->cbits);
+        b->cbits = nullptr;
+        b->cbits_elems = 0;
+        LSL_TRY(b->alloc_t(&b->cbits, nbits));
+        b->cbits_elems = nbits;
         b->drop_graphs();
     }
     uint32_t* counter = b->queue_buf + 4 * b->queue_cap;

@@ -35,7 +35,7 @@
 // (m and tc), compacts the struts that reach the block in any
 // plane of the slab, and then for each such strut loops over only the planes
 // it reaches: every lane adds its pixel's contribution to thirteen registers,
-// the wave sums them once per (strut, block), and lane 0 adds the sums into
+// the wave sums them once per (strut, block), and one lane adds the sums into
 // the entry's LDS slot.  The slots are written once per bucket entry, so each
 // (slab, tile, strut) pair gets exactly one partial, with no atomics.
 // The per-strut sums then run over the pairs of each strut in emission order
@@ -81,6 +81,15 @@ __device__ __forceinline__ double dclamp<double>(double v, double h) {
 }
 
 template <typename T>
+__device__ __forceinline__ T dmax(T a, T b) {
+    return __builtin_fmax(a, b);
+}
+template <>
+__device__ __forceinline__ float dmax<float>(float a, float b) {
+    return __builtin_fmaxf(a, b);
+}
+
+template <typename T>
 __device__ __forceinline__ T dfma(T a, T b, T c) {
     return __builtin_fma(a, b, c);
 }
@@ -89,8 +98,27 @@ __device__ __forceinline__ float dfma<float>(float a, float b, float c) {
     return __builtin_fmaf(a, b, c);
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
+// Sum over the wave, complete in lane 63 (kSumLane).  float: DPP row
+// operations only (quad swaps, half-row and row mirrors, then the row
+// broadcasts of lanes 15 and 31 into the following rows), no LDS traffic.
+constexpr int kSumLane = 63;
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_take(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+    v += dpp_take<0xB1, 0xF>(v);     // quad_perm [1,0,3,2]
+    v += dpp_take<0x4E, 0xF>(v);     // quad_perm [2,3,0,1]
+    v += dpp_take<0x141, 0xF>(v);    // row_half_mirror
+    v += dpp_take<0x140, 0xF>(v);    // row_mirror: every lane holds its row's sum
+    v += dpp_take<0x142, 0xA>(v);    // row_bcast:15 into rows 1 and 3
+    v += dpp_take<0x143, 0xC>(v);    // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
     return v;
@@ -211,11 +239,12 @@ __global__ __launch_bounds__(64) void k_backward(BackArgs a, uint32_t n_items) {
             const int n = __popcll(mask);
             for (int j = 0; j < n; ++j) {
                 const BStrut<T> b = bs[j];
+                const uint32_t planes_s = __builtin_amdgcn_readfirstlane(b.planes);
                 T Aw = 0, Aa = 0, Ab = 0, AK = 0, AKx = 0, AKy = 0, AKz = 0, AKd = 0, AJ = 0,
                   AJx = 0, AJy = 0, AJz = 0, AJd = 0;
 #pragma unroll
                 for (int k = 0; k < SZ; ++k) {
-                    if (k < nvalid && ((b.planes >> k) & 1u)) {
+                    if (k < nvalid && ((planes_s >> k) & 1u)) {
                         const BPlane<T> P = bp[b.pos][k];
                         const T g = G[k];
                         const T du = dfma(dX, b.ux, dY * b.uy);
@@ -231,10 +260,10 @@ __global__ __launch_bounds__(64) void k_backward(BackArgs a, uint32_t n_items) {
                         const T S2 = dfma(q2, S1, -(xy * xy));
                         const T Q = dfma(H, dfma(T(-2.0 / 3.0), S1, H), T(0.2) * S2);
                         Aw = dfma(g * D, Q, Aw);
-                        T pa = dfma(-al, al, H);
-                        pa = pa > T(0) ? pa * pa : T(0);
-                        T pb = dfma(-be, be, H);
-                        pb = pb > T(0) ? pb * pb : T(0);
+                        T pa = dmax<T>(dfma(-al, al, H), T(0));
+                        pa = pa * pa;
+                        T pb = dmax<T>(dfma(-be, be, H), T(0));
+                        pb = pb * pb;
                         Aa = dfma(g, pa, Aa);
                         Ab = dfma(g, pb, Ab);
                         const T J = T(2) * dfma(T(-1.0 / 3.0), S1, H) * D;   // J R^4
@@ -262,7 +291,7 @@ __global__ __launch_bounds__(64) void k_backward(BackArgs a, uint32_t n_items) {
                 const T v0 = wave_sum(Aw), v1 = wave_sum(Aa), v2 = wave_sum(Ab),
                         v3 = wave_sum(AKx), v4 = wave_sum(AKy), v5 = wave_sum(AKz),
                         v6 = wave_sum(AJx), v7 = wave_sum(AJy), v8 = wave_sum(AJz);
-                if (lane == 0) {
+                if (lane == kSumLane) {
                     T* sl = slot[b.pos];
                     sl[0] += v0;
                     sl[1] += v1;

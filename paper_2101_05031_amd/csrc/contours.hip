@@ -1,6 +1,7 @@
 // Marching squares on the binary slice images (Sec. 4: rough boundary
-// curves from the binary image), in two passes so that segments come out in
-// row-major cell order with no atomics on the output:
+// curves from the binary image), read as bit images (one bit per pixel), in
+// two passes so that segments come out in row-major cell order with no
+// atomics on the output:
 //
 //   count: case code and segment count (0, 1 or 2) per cell; per-block totals
 //   scan : exclusive prefix over (plane, block) totals -> per-plane offsets
@@ -9,7 +10,7 @@
 //          write each cell's segments at its offset.
 //
 // Cell (i, j) has corners (i,j), (i+1,j), (i+1,j+1), (i,j+1) -> bits b0..b3
-// (inside where field >= C).  Segment ends are edge midpoints in grid units;
+// (the image's bits).  Segment ends are edge midpoints in grid units;
 // the inside lies on the left of each segment; the saddles 5 and 10 keep the
 // two inside corners apart.
 #include "kernels.hpp"
@@ -44,29 +45,33 @@ __constant__ int8_t kSeg[16][2][4] = {
     {{0, 0, 0, 0}, {0, 0, 0, 0}},
 };
 
-template <typename T>
-__device__ __forceinline__ int cell_case(const T* f, int32_t W, int i, int j, T C) {
-    const size_t r0 = (size_t)j * (size_t)W + (size_t)i;
-    const size_t r1 = r0 + (size_t)W;
-    return (f[r0] >= C ? 1 : 0) | (f[r0 + 1] >= C ? 2 : 0) | (f[r1 + 1] >= C ? 4 : 0) |
-           (f[r1] >= C ? 8 : 0);
+__device__ __forceinline__ uint32_t bit_at(const uint32_t* row, int i) {
+    return (row[i >> 5] >> (i & 31)) & 1u;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kMThreads) void k_ms_count(const T* field, int32_t W, int32_t H,
-                                                        T C, uint32_t bps, uint8_t* codes,
+// case code of cell (i, j) of one binary image with `words` words per row
+__device__ __forceinline__ int cell_case(const uint32_t* img, size_t words, int i, int j) {
+    const uint32_t* r0 = img + (size_t)j * words;
+    const uint32_t* r1 = r0 + words;
+    return (int)(bit_at(r0, i) | (bit_at(r0, i + 1) << 1) | (bit_at(r1, i + 1) << 2) |
+                 (bit_at(r1, i) << 3));
+}
+
+__global__ __launch_bounds__(kMThreads) void k_ms_count(const uint32_t* bits, int32_t W,
+                                                        int32_t H, uint32_t bps, uint8_t* codes,
                                                         unsigned long long* blk) {
     __shared__ uint32_t sm[4];
     const uint32_t k = blockIdx.x / bps, b = blockIdx.x % bps;
     const uint32_t cw = (uint32_t)(W - 1);
     const uint64_t cps = (uint64_t)cw * (uint64_t)(H - 1);
-    const T* f = field + (size_t)k * (size_t)W * (size_t)H;
+    const size_t words = (size_t)(W + 31) / 32;
+    const uint32_t* f = bits + (size_t)k * (size_t)H * words;
     uint32_t cnt = 0;
     for (int r = 0; r < kMRounds; ++r) {
         const uint64_t c = (uint64_t)b * kMTile + (uint64_t)r * kMThreads + threadIdx.x;
         if (c < cps) {
             const int j = (int)(c / cw), i = (int)(c % cw);
-            const int cs = cell_case(f, W, i, j, C);
+            const int cs = cell_case(f, words, i, j);
             cnt += (uint32_t)kSegCount[cs];
             if (codes) codes[(size_t)k * cps + c] = (uint8_t)cs;
         }
@@ -89,8 +94,7 @@ __global__ void k_ms_advance(unsigned long long* base, const unsigned long long*
     if (threadIdx.x == 0 && blockIdx.x == 0) *base += blk[nb];
 }
 
-template <typename T>
-__global__ __launch_bounds__(kMThreads) void k_ms_emit(const T* field, int32_t W, int32_t H, T C,
+__global__ __launch_bounds__(kMThreads) void k_ms_emit(const uint32_t* bits, int32_t W, int32_t H,
                                                        uint32_t bps,
                                                        const unsigned long long* blk,
                                                        const unsigned long long* base,
@@ -100,7 +104,8 @@ __global__ __launch_bounds__(kMThreads) void k_ms_emit(const T* field, int32_t W
     const uint32_t k = blockIdx.x / bps, b = blockIdx.x % bps;
     const uint32_t cw = (uint32_t)(W - 1);
     const uint64_t cps = (uint64_t)cw * (uint64_t)(H - 1);
-    const T* f = field + (size_t)k * (size_t)W * (size_t)H;
+    const size_t words = (size_t)(W + 31) / 32;
+    const uint32_t* f = bits + (size_t)k * (size_t)H * words;
     uint64_t run = blk[blockIdx.x] + (base ? *base : 0ull);
     const uint64_t lt = lanes_below(lane);
     for (int r = 0; r < kMRounds; ++r) {
@@ -109,7 +114,7 @@ __global__ __launch_bounds__(kMThreads) void k_ms_emit(const T* field, int32_t W
         if (c < cps) {
             j = (int)(c / cw);
             i = (int)(c % cw);
-            cs = cell_case(f, W, i, j, C);
+            cs = cell_case(f, words, i, j);
         }
         const int n = kSegCount[cs];
         const uint64_t m0 = ballot64(n & 1), m1 = ballot64(n >> 1);
@@ -147,10 +152,9 @@ size_t contour_tmp_elems(int32_t nk, int32_t W, int32_t H) {
     return n + scan_tmp_elems(n);
 }
 
-lsl_status launch_contours_count(int dtype, const void* field, int32_t nk, int32_t W, int32_t H,
-                                 double C, int64_t* offsets, uint8_t* codes,
-                                 unsigned long long* tmp, const unsigned long long* base,
-                                 hipStream_t st) {
+lsl_status launch_contours_count(const uint32_t* bits, int32_t nk, int32_t W, int32_t H,
+                                 int64_t* offsets, uint8_t* codes, unsigned long long* tmp,
+                                 const unsigned long long* base, hipStream_t st) {
     const uint32_t bps = blocks_per_slice(W, H);
     const size_t nb = (size_t)nk * bps;
     if (nb > 0x7fffffffull) {
@@ -159,12 +163,7 @@ lsl_status launch_contours_count(int dtype, const void* field, int32_t nk, int32
     }
     unsigned long long* blk = tmp;
     unsigned long long* stmp = tmp + nb + 1;
-    if (dtype == LSL_F32)
-        k_ms_count<float><<<(unsigned)nb, kMThreads, 0, st>>>((const float*)field, W, H, (float)C,
-                                                              bps, codes, blk);
-    else
-        k_ms_count<double><<<(unsigned)nb, kMThreads, 0, st>>>((const double*)field, W, H, C, bps,
-                                                               codes, blk);
+    k_ms_count<<<(unsigned)nb, kMThreads, 0, st>>>(bits, W, H, bps, codes, blk);
     LSL_HIP(hipGetLastError());
     // exclusive scan over nb + 1 entries: the last one receives the total
     LSL_TRY(fill_bytes0(blk + nb, 8, st));
@@ -175,19 +174,13 @@ lsl_status launch_contours_count(int dtype, const void* field, int32_t nk, int32
     return LSL_OK;
 }
 
-lsl_status launch_contours_emit(int dtype, const void* field, int32_t nk, int32_t W, int32_t H,
-                                double C, const unsigned long long* tmp,
-                                unsigned long long* base, float* segs, int64_t capacity,
-                                hipStream_t st) {
+lsl_status launch_contours_emit(const uint32_t* bits, int32_t nk, int32_t W, int32_t H,
+                                const unsigned long long* tmp, unsigned long long* base,
+                                float* segs, int64_t capacity, hipStream_t st) {
     const uint32_t bps = blocks_per_slice(W, H);
     const size_t nb = (size_t)nk * bps;
-    if (dtype == LSL_F32)
-        k_ms_emit<float><<<(unsigned)nb, kMThreads, 0, st>>>((const float*)field, W, H, (float)C,
-                                                             bps, tmp, base, (float4*)segs,
-                                                             capacity);
-    else
-        k_ms_emit<double><<<(unsigned)nb, kMThreads, 0, st>>>((const double*)field, W, H, C, bps,
-                                                              tmp, base, (float4*)segs, capacity);
+    k_ms_emit<<<(unsigned)nb, kMThreads, 0, st>>>(bits, W, H, bps, tmp, base, (float4*)segs,
+                                                  capacity);
     if (base) k_ms_advance<<<1, 64, 0, st>>>(base, tmp, nb);
     LSL_HIP(hipGetLastError());
     return LSL_OK;

@@ -52,24 +52,30 @@ __global__ __launch_bounds__(256) void k_field(FieldArgs a, uint32_t n_items) {
     fieldk::field_block<T, SZ, STATS>(a, a.s_lo + (int)t, tx, ty, sub, stage[wv]);
 }
 
-// Binary image: one wave per 64 pixels of a row; the ballot is the bit mask.
+// Binary image of a field: one wave packs 512 pixels of a row, 64 at a time
+// with coalesced loads; each ballot is two words of the bit row.
 template <typename T>
 __global__ __launch_bounds__(256) void k_bits(const T* field, int32_t nk, int32_t W, int32_t H,
                                               T C, uint32_t* bits) {
     const int lane = lane_id();
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int chunks = (W + 63) / 64;
+    const int chunks = (W + 511) / 512;
     const int words = (W + 31) / 32;
     const uint64_t rows = (uint64_t)nk * (uint64_t)H;
     if (wave >= rows * (uint64_t)chunks) return;
     const uint64_t row = wave / (uint64_t)chunks;
     const int c = (int)(wave % (uint64_t)chunks);
-    const int i = c * 64 + lane;
-    const bool in = i < W && field[row * (uint64_t)W + (uint64_t)i] >= C;
-    const uint64_t m = ballot64(in);
+    const T* f = field + row * (uint64_t)W;
     uint32_t* out = bits + row * (uint64_t)words;
-    if (lane == 0) out[2 * c] = (uint32_t)m;
-    if (lane == 1 && 2 * c + 1 < words) out[2 * c + 1] = (uint32_t)(m >> 32);
+    uint32_t mine = 0;                   // lane q < 16 keeps word c*16 + q
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int i = c * 512 + r * 64 + lane;
+        const uint64_t m = ballot64(i < W && f[i] >= C);
+        if (lane == 2 * r) mine = (uint32_t)m;
+        if (lane == 2 * r + 1) mine = (uint32_t)(m >> 32);
+    }
+    if (lane < 16 && c * 16 + lane < words) out[c * 16 + lane] = mine;
 }
 
 template <typename T, int SZ>
@@ -109,7 +115,7 @@ lsl_status launch_field(int dtype, const FieldArgs& a, bool stats, hipStream_t s
 
 lsl_status launch_bits(int dtype, const void* field, int32_t nk, int32_t W, int32_t H, double C,
                        uint32_t* bits, hipStream_t st) {
-    const uint64_t waves = (uint64_t)nk * (uint64_t)H * (uint64_t)((W + 63) / 64);
+    const uint64_t waves = (uint64_t)nk * (uint64_t)H * (uint64_t)((W + 511) / 512);
     if (waves == 0) return LSL_OK;
     const uint64_t blocks = (waves + 3) / 4;
     if (dtype == LSL_F32)

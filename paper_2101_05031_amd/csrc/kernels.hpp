@@ -85,7 +85,9 @@ struct FieldArgs {
     int32_t k0, nk;                   // planes written: [k0, k0+nk)
     int32_t W, H;
     double x0, y0, dx, dy, z0, dz, R;
-    void* field;                      // [nk][H][W]
+    void* field;                      // [nk][H][W] or null (not written)
+    uint32_t* bits;                   // [nk][H][ceil(W/32)] or null: field >= C
+    double C;
     unsigned long long* stats;        // [3] (stats kernels only)
 };
 lsl_status launch_field(int dtype, const FieldArgs& a, bool stats, hipStream_t st);
@@ -94,16 +96,15 @@ lsl_status launch_bits(int dtype, const void* field, int32_t nk, int32_t W, int3
 
 // ------------------------------------------------------------- contours.hip
 size_t contour_tmp_elems(int32_t nk, int32_t W, int32_t H);
+// Marching squares on binary images bits [nk][H][ceil(W/32)].
 // base (optional, device): running segment count added to this call's
 // offsets and positions; the emit pass advances it by this call's total.
-lsl_status launch_contours_count(int dtype, const void* field, int32_t nk, int32_t W,
-                                 int32_t H, double C, int64_t* offsets, uint8_t* codes,
-                                 unsigned long long* tmp, const unsigned long long* base,
-                                 hipStream_t st);
-lsl_status launch_contours_emit(int dtype, const void* field, int32_t nk, int32_t W,
-                                int32_t H, double C, const unsigned long long* tmp,
-                                unsigned long long* base, float* segs, int64_t capacity,
-                                hipStream_t st);
+lsl_status launch_contours_count(const uint32_t* bits, int32_t nk, int32_t W, int32_t H,
+                                 int64_t* offsets, uint8_t* codes, unsigned long long* tmp,
+                                 const unsigned long long* base, hipStream_t st);
+lsl_status launch_contours_emit(const uint32_t* bits, int32_t nk, int32_t W, int32_t H,
+                                const unsigned long long* tmp, unsigned long long* base,
+                                float* segs, int64_t capacity, hipStream_t st);
 
 // ------------------------------------------------------------- backward.hip
 struct BackArgs {

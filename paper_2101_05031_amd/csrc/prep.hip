@@ -39,35 +39,27 @@ __device__ __forceinline__ uint64_t double_key(double z) {
     return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
 }
 
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-    return v;
-}
-
-// Adds `cnt` of each distinct bin value held by the lanes in `mask` with one
-// atomic per value (lanes of a wave are usually in the same slab).
-__device__ __forceinline__ void wave_hist_add(bool take, int32_t bin, unsigned long long amount,
-                                              uint32_t* cnt, unsigned long long* acc,
-                                              int acc_off, bool negate) {
-    const int lane = lane_id();
-    uint64_t todo = ballot64(take);
-    while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const int32_t v = __shfl(bin, leader, kWave);
-        const bool mine = take && bin == v && ((todo >> lane) & 1ull);
-        const uint64_t peers = ballot64(mine);
-        const unsigned long long s = wave_sum_u64(mine ? amount : 0ull);
-        if (lane == leader) {
-            atomicAdd(&cnt[v], (uint32_t)__popcll(peers));
-            atomicAdd(&acc[v + acc_off], negate ? (0ull - s) : s);
-        }
-        todo &= ~peers;
-    }
-}
+// Plan histograms live in LDS per block when the slab count allows it.
+constexpr int kLdsSlabs = 2048;
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
+    __shared__ uint32_t h_lo[kLdsSlabs], h_hi[kLdsSlabs];
+    __shared__ unsigned long long h_pairs[kLdsSlabs + 1];
+    __shared__ uint32_t h_n;
+    const bool lds = a.n_slabs <= kLdsSlabs;
+    if (lds) {
+        for (int i = threadIdx.x; i < a.n_slabs; i += blockDim.x) {
+            h_lo[i] = 0u;
+            h_hi[i] = 0u;
+            h_pairs[i] = 0ull;
+        }
+        if (threadIdx.x == 0) {
+            h_pairs[a.n_slabs] = 0ull;
+            h_n = 0u;
+        }
+        __syncthreads();
+    }
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = e < a.n_edges;
     bool binned = false;
@@ -129,11 +121,33 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
         a.vals[e] = (uint32_t)e;
         a.ranges[e] = rg;
     }
-    // plan histograms: one atomic per distinct slab per wave
-    wave_hist_add(binned, rg.s0, ntile, a.cnt_lo, a.pair_diff, 0, false);
-    wave_hist_add(binned, rg.s1, ntile, a.cnt_hi, a.pair_diff, 1, true);
-    const uint64_t nb = ballot64(binned);
-    if (lane_id() == 0 && nb) atomicAdd(a.n_binned, (uint32_t)__popcll(nb));
+    // plan histograms: struts starting / ending in each slab, and a
+    // difference array of (slab, tile) pairs
+    if (lds) {
+        if (binned) {
+            atomicAdd(&h_lo[rg.s0], 1u);
+            atomicAdd(&h_hi[rg.s1], 1u);
+            atomicAdd(&h_pairs[rg.s0], ntile);
+            atomicAdd(&h_pairs[rg.s1 + 1], 0ull - ntile);
+            atomicAdd(&h_n, 1u);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < a.n_slabs; i += blockDim.x) {
+            if (h_lo[i]) atomicAdd(&a.cnt_lo[i], h_lo[i]);
+            if (h_hi[i]) atomicAdd(&a.cnt_hi[i], h_hi[i]);
+            if (h_pairs[i]) atomicAdd(&a.pair_diff[i], h_pairs[i]);
+        }
+        if (threadIdx.x == 0) {
+            if (h_pairs[a.n_slabs]) atomicAdd(&a.pair_diff[a.n_slabs], h_pairs[a.n_slabs]);
+            if (h_n) atomicAdd(a.n_binned, h_n);
+        }
+    } else if (binned) {
+        atomicAdd(&a.cnt_lo[rg.s0], 1u);
+        atomicAdd(&a.cnt_hi[rg.s1], 1u);
+        atomicAdd(&a.pair_diff[rg.s0], ntile);
+        atomicAdd(&a.pair_diff[rg.s1 + 1], 0ull - ntile);
+        atomicAdd(a.n_binned, 1u);
+    }
 }
 
 template <typename T>
