@@ -63,7 +63,7 @@ struct lattice_bins {
     uint32_t* eoff = nullptr;
     uint32_t* offsets = nullptr;
     uint32_t* ids = nullptr;
-    uint32_t* inv = nullptr;
+    uint32_t* emi = nullptr;
     uint32_t* owner = nullptr;
     uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
     uint32_t* tmp = nullptr;
@@ -283,7 +283,7 @@ lsl_status ensure_group(lattice_bins* b, int g, hipStream_t st) {
     gb.eoff = b->eoff;
     gb.offsets = b->offsets;
     gb.ids = b->ids;
-    gb.inv = b->inv;
+    gb.emi = b->emi;
     gb.owner = b->owner;
     gb.k0 = b->k0;
     gb.v0 = b->v0;
@@ -322,6 +322,7 @@ FieldArgs field_args(const lattice_bins* b, int32_t k0, int32_t nk, void* field)
     a.C = b->C;
     a.field = field;
     a.bits = nullptr;
+    a.bits_blk = nullptr;
     return a;
 }
 
@@ -361,6 +362,11 @@ __global__ void k_copy_i32(const uint32_t* in, int32_t* out, size_t n) {
 }
 
 unsigned nblk(size_t n) { return (unsigned)((n + 255) / 256); }
+
+// 32-bit words of a block-major binary image of nk planes
+size_t blk_words(const lattice_bins* b, int32_t nk) {
+    return 2 * (size_t)nk * (size_t)((b->grid.H + 7) / 8) * (size_t)((b->grid.W + 7) / 8);
+}
 
 }  // namespace
 
@@ -562,7 +568,7 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
     b->cap_buckets = max_bk;
     if ((s = b->alloc_t(&b->active[0], max_act)) || (s = b->alloc_t(&b->active[1], max_act)) ||
         (s = b->alloc_t(&b->eoff, max_act + 1)) || (s = b->alloc_t(&b->offsets, max_bk + 1)) ||
-        (s = b->alloc_t(&b->ids, max_pairs)) || (s = b->alloc_t(&b->inv, max_pairs)) ||
+        (s = b->alloc_t(&b->ids, max_pairs)) || (s = b->alloc_t(&b->emi, max_pairs)) ||
         (s = b->alloc_t(&b->owner, max_pairs)) || (s = b->alloc_t(&b->k0, max_pairs)) ||
         (s = b->alloc_t(&b->v0, max_pairs)) || (s = b->alloc_t(&b->k1, max_pairs)) ||
         (s = b->alloc_t(&b->v1, max_pairs)) ||
@@ -707,7 +713,7 @@ lsl_status slice_contours(const lattice_bins* cb, int32_t nk, const void* field,
         b->ctmp_elems = need;
         b->drop_graphs();
     }
-    const size_t nbits = (size_t)nk * b->grid.H * ((b->grid.W + 31) / 32);
+    const size_t nbits = blk_words(b, nk);
     if (nbits > b->cbits_elems) {
         LSL_HIP(hipStreamSynchronize(st));
         b->release(b->cbits);
@@ -717,9 +723,10 @@ lsl_status slice_contours(const lattice_bins* cb, int32_t nk, const void* field,
         b->cbits_elems = nbits;
         b->drop_graphs();
     }
-    // the binary images, then marching squares on them
-    LSL_TRY(launch_bits(b->dtype, field, nk, b->grid.W, b->grid.H, b->C, b->cbits, st));
-    LSL_TRY(launch_contours_count(b->cbits, nk, b->grid.W, b->grid.H, offsets, case_codes,
+    // the binary images (block-major), then marching squares on them
+    LSL_TRY(launch_bits_blk(b->dtype, field, nk, b->grid.W, b->grid.H, b->C,
+                            (uint64_t*)b->cbits, st));
+    LSL_TRY(launch_contours_count(b->cbits, true, nk, b->grid.W, b->grid.H, offsets, case_codes,
                                   b->ctmp, nullptr, st));
     int64_t tot = 0;
     LSL_HIP(hipMemcpyAsync(&tot, offsets + nk, sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -731,8 +738,8 @@ lsl_status slice_contours(const lattice_bins* cb, int32_t nk, const void* field,
         return LSL_ECAPACITY;
     }
     if (tot > 0)
-        LSL_TRY(launch_contours_emit(b->cbits, nk, b->grid.W, b->grid.H, b->ctmp, nullptr, segs,
-                                     capacity, st));
+        LSL_TRY(launch_contours_emit(b->cbits, true, nk, b->grid.W, b->grid.H, b->ctmp, nullptr,
+                                     segs, capacity, st));
     return LSL_OK;
 }
 
@@ -792,6 +799,7 @@ BackArgs back_args(const lattice_bins* b, int g, int32_t k0, int32_t nk, int s_l
     a.z0 = b->grid.z0;
     a.dz = b->grid.dz;
     a.R = b->R;
+    a.emi = b->emi;
     a.grad = grad;
     a.partial = b->partial;
     return a;
@@ -819,9 +827,12 @@ lsl_status batch_group_work(lattice_bins* b, int g, int32_t k0, int32_t nk, int 
     // this group's planes: the caller's field (if any) and binary images (the
     // caller's, or library scratch)
     void* fbase = field ? (void*)((char*)field + (size_t)(kg0 - k0) * plane * b->esize()) : nullptr;
-    uint32_t* bbase = bits ? bits + (size_t)(kg0 - k0) * (size_t)b->grid.H * words : b->cbits;
+    // caller's bits: row-major; otherwise library scratch, block-major
+    uint32_t* bbase = bits ? bits + (size_t)(kg0 - k0) * (size_t)b->grid.H * words : nullptr;
     FieldArgs a = field_args(b, kg0, nkg, fbase);
     a.bits = bbase;
+    a.bits_blk = bits ? nullptr : (uint64_t*)b->cbits;
+    const void* img = bits ? (const void*)bbase : (const void*)b->cbits;
     a.n_pairs = (uint32_t)b->groups[g].pairs;
     a.group_s0 = b->groups[g].sa;
     a.s_lo = s_lo;
@@ -849,10 +860,10 @@ lsl_status batch_group_work(lattice_bins* b, int g, int32_t k0, int32_t nk, int 
         ba.counter = counter;
         return launch_persistent(b->dtype, ba, persistent_blocks(b->dtype, b->slab), st);
     }
-    LSL_TRY(launch_contours_count(bbase, nkg, b->grid.W, b->grid.H, offsets + (kg0 - k0),
+    LSL_TRY(launch_contours_count(img, !bits, nkg, b->grid.W, b->grid.H, offsets + (kg0 - k0),
                                   nullptr, b->ctmp, base, st));
-    LSL_TRY(launch_contours_emit(bbase, nkg, b->grid.W, b->grid.H, b->ctmp, base, segs, capacity,
-                                 st));
+    LSL_TRY(launch_contours_emit(img, !bits, nkg, b->grid.W, b->grid.H, b->ctmp, base, segs,
+                                 capacity, st));
     return LSL_OK;
 }
 
@@ -911,7 +922,6 @@ lsl_status slice_field_backward(lattice_bins* b, int32_t k0, int32_t nk, const v
             r.active = b->active[b->cur_buf];
             r.n_active = G.n_active;
             r.eoff = b->eoff;
-            r.inv = b->inv;
             r.rec = b->rec;
             r.w = b->w;
             r.R = b->R;
@@ -969,7 +979,7 @@ lsl_status slice_batch(lattice_bins* b, int32_t k0, int32_t nk, void* field, uin
         b->ctmp_elems = ct;
         b->drop_graphs();
     }
-    const size_t nbits = max_planes * (size_t)b->grid.H * ((b->grid.W + 31) / 32);
+    const size_t nbits = blk_words(b, (int32_t)max_planes);
     if (!bits && b->cbits_elems < nbits) {
         LSL_HIP(hipStreamSynchronize(st));
         b->release(b->cbits);

@@ -36,9 +36,10 @@
 // plane of the slab, and then for each such strut loops over only the planes
 // it reaches: every lane adds its pixel's contribution to thirteen registers,
 // the wave sums them once per (strut, block), and one lane adds the sums into
-// the entry's LDS slot.  The slots are written once per bucket entry, so each
-// (slab, tile, strut) pair gets exactly one partial, with no atomics.
-// The per-strut sums then run over the pairs of each strut in emission order
+// the entry's LDS slot.  The slots are written once per bucket entry, at the
+// entry's emission index, so each (slab, tile, strut) pair gets exactly one
+// partial, with no atomics, and a strut's pairs lie side by side.  The
+// per-strut sums then run over each strut's pairs in emission order
 // (slab, tile), and the nodes gather their struts' gradients through a node
 // -> strut incidence list.  Every reduction has a fixed order.
 #include "kernels.hpp"
@@ -49,17 +50,11 @@ namespace {
 constexpr int kChunk = 32;      // bucket entries staged at a time
 constexpr int kParts = 9;       // pixel sums per (strut, bucket)
 
+// per (strut, plane): m = F - c, H0 = R^2 - |m|^2, and the ends -tc, L - tc
 template <typename T>
-struct alignas(16) BStrut {
-    T ux, uy, uz, pad;
-    uint32_t planes;            // bit k: the strut reaches the block in plane k
-    uint32_t pos;               // entry index within the chunk
-};
-
-template <typename T>
-struct alignas(16) BPlane {
-    T mx2, my2, ntc, H0;        // as in the forward pass
-    T mx, my, mz, nbtc;         // m = F - c; L - tc
+struct alignas(8) BPlane {
+    T mx, my, mz, H0;
+    T ntc, nbtc;
 };
 
 template <typename T>
@@ -98,14 +93,54 @@ __device__ __forceinline__ float dfma<float>(float a, float b, float c) {
     return __builtin_fmaf(a, b, c);
 }
 
-// Sum over the wave, complete in lane 63 (kSumLane).  float: DPP row
-// operations only (quad swaps, half-row and row mirrors, then the row
-// broadcasts of lanes 15 and 31 into the following rows), no LDS traffic.
+// Wave sums of the nine per-lane partials, added into one LDS slot row.
+//
+// float: a reduce-scatter.  v_permlane32_swap exchanges the upper half-wave
+// of one register with the lower half-wave of another, so one swap and one
+// add fold two values into one register (lanes 0-31 hold half sums of the
+// first, lanes 32-63 of the second); v_permlane16_swap does the same for odd
+// and even rows.  After the two folds, a row rotate by 8 pairs the half-rows,
+// and three DPP steps finish each 8-lane group.  Lane group g = lane / 8
+// then holds the total of value kScatter[g]; the ninth value takes a plain
+// DPP reduction into lane 63.  The nine owner lanes add their totals to the
+// slot, each at its own address, in a fixed order of operations.
 constexpr int kSumLane = 63;
 
 template <int CTRL, int ROWS>
 __device__ __forceinline__ float dpp_take(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
+}
+
+__device__ __forceinline__ float fold32(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                    false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float fold16(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                    false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// value index whose total lane group g (= lane / 8) holds after reduce8
+__device__ __forceinline__ int scatter_index(int lane) {
+    const int g = lane >> 3, row = g >> 1;
+    return 4 * (g & 1) + (((row & 1) << 1) | (row >> 1));
+}
+
+__device__ __forceinline__ float reduce8(float v0, float v1, float v2, float v3, float v4,
+                                         float v5, float v6, float v7, int lane) {
+    const float w0 = fold32(v0, v1), w1 = fold32(v2, v3), w2 = fold32(v4, v5),
+                w3 = fold32(v6, v7);
+    const float x0 = fold16(w0, w1), x1 = fold16(w2, w3);   // rows: values 0 2 1 3 | 4 6 5 7
+    const float t0 = x0 + dpp_take<0x128, 0xF>(x0);          // row_ror:8
+    const float t1 = x1 + dpp_take<0x128, 0xF>(x1);
+    float y = (lane & 8) ? t1 : t0;
+    y += dpp_take<0xB1, 0xF>(y);     // quad_perm [1,0,3,2]
+    y += dpp_take<0x4E, 0xF>(y);     // quad_perm [2,3,0,1]
+    y += dpp_take<0x141, 0xF>(y);    // row_half_mirror: every lane holds its group's total
+    return y;
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -118,15 +153,37 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
+__device__ __forceinline__ void deposit(float* sl, const float (&v)[9], int lane, int own) {
+    const float y = reduce8(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], lane);
+    const float z = wave_sum(v[8]);
+    if (own >= 0) sl[own] += own == 8 ? z : y;
+}
+
+__device__ __forceinline__ void deposit(double* sl, const double (&v)[9], int lane, int) {
+    double t[9];
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-    return v;
+    for (int q = 0; q < 9; ++q) {
+        double x = v[q];
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, kWave);
+        t[q] = x;
+    }
+    if (lane == kSumLane)
+#pragma unroll
+        for (int q = 0; q < 9; ++q) sl[q] += t[q];
+}
+
+// The slot entry this lane adds to in deposit (float), or -1.
+__device__ __forceinline__ int deposit_owner(int lane) {
+    if (lane == kSumLane) return 8;
+    return (lane & 7) == 0 ? scatter_index(lane) : -1;
 }
 
 template <typename T, int SZ>
-__global__ __launch_bounds__(64) void k_backward(BackArgs a, uint32_t n_items) {
-    __shared__ BStrut<T> bs[kChunk];
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_backward(BackArgs a, uint32_t n_items) {
+    // compacted list of the struts that reach the current block
+    __shared__ T bs_ux[kChunk], bs_uy[kChunk], bs_uz[kChunk];
+    __shared__ uint32_t bs_planes[kChunk], bs_pos[kChunk];
     __shared__ BPlane<T> bp[kChunk][SZ];
     __shared__ T slot[kChunk][kParts];
 
@@ -154,11 +211,13 @@ __global__ __launch_bounds__(64) void k_backward(BackArgs a, uint32_t n_items) {
     const T dX = (T)(((double)lx - 3.5) * a.dx);
     const T dY = (T)(((double)ly - 3.5) * a.dy);
     const T d2 = dX * dX + dY * dY;
+    const T dX2 = dX + dX, dY2 = dY + dY;
     const double rb = 3.5 * sqrt(a.dx * a.dx + a.dy * a.dy);
     const double thr = (a.R + rb) * (1.0 + 1e-7);
     const double thr2 = thr * thr;
     const double R2 = a.R * a.R;
     const uint64_t lt = lanes_below(lane);
+    const int own = deposit_owner(lane);
     const StrutRec<T>* recs = (const StrutRec<T>*)a.rec;
     const T* grad = (const T*)a.grad;
     T* part = (T*)a.partial;
@@ -211,13 +270,11 @@ __global__ __launch_bounds__(64) void k_backward(BackArgs a, uint32_t n_items) {
                     if (valid && fma(ex, ex, m2) < thr2) {
                         planes |= 1u << k;
                         BPlane<T> P;
-                        P.mx2 = (T)(2.0 * mx);
-                        P.my2 = (T)(2.0 * my);
-                        P.ntc = (T)(-tc);
-                        P.H0 = (T)(R2 - m2);
                         P.mx = (T)mx;
                         P.my = (T)my;
                         P.mz = (T)mz;
+                        P.H0 = (T)(R2 - m2);
+                        P.ntc = (T)(-tc);
                         P.nbtc = (T)(L - tc);
                         bp[lane][k] = P;
                     }
@@ -226,32 +283,33 @@ __global__ __launch_bounds__(64) void k_backward(BackArgs a, uint32_t n_items) {
             const uint64_t mask = ballot64(planes != 0u);
             if (mask == 0ull) continue;
             if (planes != 0u) {
-                BStrut<T> b;
-                b.ux = (T)ux;
-                b.uy = (T)uy;
-                b.uz = (T)uz;
-                b.pad = T(0);
-                b.planes = planes;
-                b.pos = (uint32_t)lane;
-                bs[__popcll(mask & lt)] = b;
+                const int q = __popcll(mask & lt);
+                bs_ux[q] = (T)ux;
+                bs_uy[q] = (T)uy;
+                bs_uz[q] = (T)uz;
+                bs_planes[q] = planes;
+                bs_pos[q] = (uint32_t)lane;
             }
             __builtin_amdgcn_wave_barrier();
             const int n = __popcll(mask);
             for (int j = 0; j < n; ++j) {
-                const BStrut<T> b = bs[j];
-                const uint32_t planes_s = __builtin_amdgcn_readfirstlane(b.planes);
+                const T bux = bs_ux[j], buy = bs_uy[j], buz = bs_uz[j];
+                const uint32_t bpos = bs_pos[j];
+                const uint32_t planes_s = __builtin_amdgcn_readfirstlane(bs_planes[j]);
                 T Aw = 0, Aa = 0, Ab = 0, AK = 0, AKx = 0, AKy = 0, AKz = 0, AKd = 0, AJ = 0,
                   AJx = 0, AJy = 0, AJz = 0, AJd = 0;
+                const T du = dfma(dX, bux, dY * buy);         // d.u: the same in every plane
+                const T dd = dfma(du, du, -d2);               // (d.u)^2 - |d|^2
 #pragma unroll
                 for (int k = 0; k < SZ; ++k) {
                     if (k < nvalid && ((planes_s >> k) & 1u)) {
-                        const BPlane<T> P = bp[b.pos][k];
+                        const BPlane<T> P = bp[bpos][k];
                         const T g = G[k];
-                        const T du = dfma(dX, b.ux, dY * b.uy);
                         const T al = P.ntc - du;
                         const T be = P.nbtc - du;
-                        const T H = dfma(du, du, dfma(P.mx2, dX, dfma(P.my2, dY, P.H0 - d2)));
-                        const T h = dsqrt<T>(H > T(0) ? H : T(0));
+                        const T H = dfma(P.mx, dX2, dfma(P.my, dY2, P.H0 + dd));
+                        const T Hc = dmax<T>(H, T(0));
+                        const T h = dsqrt<T>(Hc);
                         const T ca = dclamp<T>(al, h), cb = dclamp<T>(be, h);
                         const T D = cb - ca;
                         const T x2 = ca * ca, y2 = cb * cb, xy = ca * cb;
@@ -260,9 +318,11 @@ __global__ __launch_bounds__(64) void k_backward(BackArgs a, uint32_t n_items) {
                         const T S2 = dfma(q2, S1, -(xy * xy));
                         const T Q = dfma(H, dfma(T(-2.0 / 3.0), S1, H), T(0.2) * S2);
                         Aw = dfma(g * D, Q, Aw);
-                        T pa = dmax<T>(dfma(-al, al, H), T(0));
+                        // phi at the ends: zero outside the chord, where the end
+                        // is clamped to +-h, and off the strut's reach (Hc = 0)
+                        T pa = Hc - x2;
                         pa = pa * pa;
-                        T pb = dmax<T>(dfma(-be, be, H), T(0));
+                        T pb = Hc - y2;
                         pb = pb * pb;
                         Aa = dfma(g, pa, Aa);
                         Ab = dfma(g, pb, Ab);
@@ -282,34 +342,25 @@ __global__ __launch_bounds__(64) void k_backward(BackArgs a, uint32_t n_items) {
                     }
                 }
                 // sum G K q_perp = sum G K m - d sum G K + u sum G K (d.u), d = (dX, dY, 0)
-                AKx = dfma(b.ux, AKd, dfma(-dX, AK, AKx));
-                AKy = dfma(b.uy, AKd, dfma(-dY, AK, AKy));
-                AKz = dfma(b.uz, AKd, AKz);
-                AJx = dfma(b.ux, AJd, dfma(-dX, AJ, AJx));
-                AJy = dfma(b.uy, AJd, dfma(-dY, AJ, AJy));
-                AJz = dfma(b.uz, AJd, AJz);
-                const T v0 = wave_sum(Aw), v1 = wave_sum(Aa), v2 = wave_sum(Ab),
-                        v3 = wave_sum(AKx), v4 = wave_sum(AKy), v5 = wave_sum(AKz),
-                        v6 = wave_sum(AJx), v7 = wave_sum(AJy), v8 = wave_sum(AJz);
-                if (lane == kSumLane) {
-                    T* sl = slot[b.pos];
-                    sl[0] += v0;
-                    sl[1] += v1;
-                    sl[2] += v2;
-                    sl[3] += v3;
-                    sl[4] += v4;
-                    sl[5] += v5;
-                    sl[6] += v6;
-                    sl[7] += v7;
-                    sl[8] += v8;
-                }
+                AKx = dfma(bux, AKd, dfma(-dX, AK, AKx));
+                AKy = dfma(buy, AKd, dfma(-dY, AK, AKy));
+                AKz = dfma(buz, AKd, AKz);
+                AJx = dfma(bux, AJd, dfma(-dX, AJ, AJx));
+                AJy = dfma(buy, AJd, dfma(-dY, AJ, AJy));
+                AJz = dfma(buz, AJd, AJz);
+                const T v[9] = {Aw, Aa, Ab, AKx, AKy, AKz, AJx, AJy, AJz};
+                deposit(slot[bpos], v, lane, own);
                 __builtin_amdgcn_wave_barrier();
             }
             __builtin_amdgcn_wave_barrier();
         }
         __builtin_amdgcn_wave_barrier();
-        for (int q = lane; q < nent * kParts; q += kWave)
-            part[(size_t)cbase * kParts + (size_t)q] = (&slot[0][0])[q];
+        // each entry's sums go to its emission index (the strut's pairs are
+        // then contiguous for the per-strut reduction)
+        for (int q = lane; q < nent * kParts; q += kWave) {
+            const uint32_t e = a.emi[cbase + (uint32_t)(q / kParts)];
+            if (e < a.n_pairs) part[(size_t)e * kParts + (size_t)(q % kParts)] = (&slot[0][0])[q];
+        }
         __builtin_amdgcn_wave_barrier();
     }
 }
@@ -330,15 +381,13 @@ __global__ void k_reduce(ReduceArgs a, const SRange* ranges, int32_t sa, int32_t
     const int32_t hi = s_hi < rg.s1 ? s_hi : rg.s1;
     if (hi < lo) return;
     const uint32_t e0 = a.eoff[i] + (uint32_t)(lo - s0) * nxy;
-    const uint32_t e1 = a.eoff[i] + (uint32_t)(hi - s0 + 1) * nxy;
+    uint32_t e1 = a.eoff[i] + (uint32_t)(hi - s0 + 1) * nxy;
     double s[kParts];
     for (int q = 0; q < kParts; ++q) s[q] = 0.0;
     const T* part = (const T*)a.partial;
-    for (uint32_t e = e0; e < e1; ++e) {
-        const uint32_t pos = a.inv[e];
-        if (pos >= n_pairs) continue;
-        for (int q = 0; q < kParts; ++q) s[q] += (double)part[(size_t)pos * kParts + q];
-    }
+    if (e1 > n_pairs) e1 = n_pairs;
+    for (uint32_t e = e0; e < e1; ++e)
+        for (int q = 0; q < kParts; ++q) s[q] += (double)part[(size_t)e * kParts + q];
     const StrutRec<T> r = ((const StrutRec<T>*)a.rec)[p];
     const double w = (double)((const T*)a.w)[p];
     const double R4 = a.R * a.R * a.R * a.R;

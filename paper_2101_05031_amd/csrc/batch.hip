@@ -34,7 +34,7 @@ __global__ void k_queue_keys(FieldArgs a, uint32_t n_items, uint32_t* keys, uint
 }
 
 template <typename T, int SZ>
-__global__ __launch_bounds__(256) void k_persistent(FieldArgs a, const uint32_t* queue,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_persistent(FieldArgs a, const uint32_t* queue,
                                                     uint32_t n_items, uint32_t* counter) {
     __shared__ Stage<T> stage[4][kWave];
     __shared__ uint32_t s_item;

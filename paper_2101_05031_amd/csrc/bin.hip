@@ -141,13 +141,13 @@ __global__ void k_csr_offsets(const uint32_t* keys, uint32_t n, uint32_t n_bucke
     for (uint32_t b = kprev; b <= k && b <= n_buckets; ++b) offsets[b] = i;
 }
 
-__global__ void k_ids_inv(const uint32_t* sorted_vals, const uint32_t* owner,
-                          const uint32_t* active, uint32_t n, uint32_t* ids, uint32_t* inv) {
+__global__ void k_ids_emi(const uint32_t* sorted_vals, const uint32_t* owner,
+                          const uint32_t* active, uint32_t n, uint32_t* ids, uint32_t* emi) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t e = sorted_vals[i];
     ids[i] = active[owner[e]];
-    inv[e] = i;
+    emi[i] = e;
 }
 
 int bits_for(uint32_t n) {
@@ -195,11 +195,11 @@ lsl_status bin_group(const GroupBuffers& g, hipStream_t st) {
                                  &which, st));
         const uint32_t* ks = which ? g.k1 : g.k0;
         const uint32_t* vs = which ? g.v1 : g.v0;
-        // 5. bucket offsets, strut ids and the emission -> position map
+        // 5. bucket offsets, strut ids and each entry's emission index
         k_csr_offsets<<<(g.n_pairs + 1 + 255) / 256, 256, 0, st>>>(ks, g.n_pairs, g.n_buckets,
                                                                    g.offsets);
-        k_ids_inv<<<(g.n_pairs + 255) / 256, 256, 0, st>>>(vs, g.owner, g.active, g.n_pairs,
-                                                           g.ids, g.inv);
+        k_ids_emi<<<(g.n_pairs + 255) / 256, 256, 0, st>>>(vs, g.owner, g.active, g.n_pairs,
+                                                           g.ids, g.emi);
         LSL_HIP(hipGetLastError());
     } else {
         LSL_TRY(fill_u32(g.offsets, 0u, (size_t)g.n_buckets + 1, st));

@@ -49,29 +49,56 @@ __device__ __forceinline__ uint32_t bit_at(const uint32_t* row, int i) {
     return (row[i >> 5] >> (i & 31)) & 1u;
 }
 
-// case code of cell (i, j) of one binary image with `words` words per row
-__device__ __forceinline__ int cell_case(const uint32_t* img, size_t words, int i, int j) {
-    const uint32_t* r0 = img + (size_t)j * words;
-    const uint32_t* r1 = r0 + words;
-    return (int)(bit_at(r0, i) | (bit_at(r0, i + 1) << 1) | (bit_at(r1, i + 1) << 2) |
-                 (bit_at(r1, i) << 3));
+// One plane of a binary image, row-major (BLK = false: `words` 32-bit words
+// per row) or block-major (BLK = true: `words` 8x8-block words per block row).
+template <bool BLK>
+struct Img {
+    const void* p;
+    size_t words;
+    __device__ __forceinline__ uint32_t at(int i, int j) const {
+        if (BLK) {
+            const uint64_t w = ((const uint64_t*)p)[(size_t)(j >> 3) * words + (size_t)(i >> 3)];
+            return (uint32_t)(w >> (8 * (j & 7) + (i & 7))) & 1u;
+        }
+        return bit_at((const uint32_t*)p + (size_t)j * words, i);
+    }
+};
+
+template <bool BLK>
+__device__ __forceinline__ Img<BLK> plane_img(const void* bits, int32_t W, int32_t H, uint32_t k) {
+    Img<BLK> m;
+    if (BLK) {
+        m.words = (size_t)(W + 7) / 8;
+        m.p = (const uint64_t*)bits + (size_t)k * (size_t)((H + 7) / 8) * m.words;
+    } else {
+        m.words = (size_t)(W + 31) / 32;
+        m.p = (const uint32_t*)bits + (size_t)k * (size_t)H * m.words;
+    }
+    return m;
 }
 
-__global__ __launch_bounds__(kMThreads) void k_ms_count(const uint32_t* bits, int32_t W,
+// case code of cell (i, j)
+template <bool BLK>
+__device__ __forceinline__ int cell_case(const Img<BLK>& m, int i, int j) {
+    return (int)(m.at(i, j) | (m.at(i + 1, j) << 1) | (m.at(i + 1, j + 1) << 2) |
+                 (m.at(i, j + 1) << 3));
+}
+
+template <bool BLK>
+__global__ __launch_bounds__(kMThreads) void k_ms_count(const void* bits, int32_t W,
                                                         int32_t H, uint32_t bps, uint8_t* codes,
                                                         unsigned long long* blk) {
     __shared__ uint32_t sm[4];
     const uint32_t k = blockIdx.x / bps, b = blockIdx.x % bps;
     const uint32_t cw = (uint32_t)(W - 1);
     const uint64_t cps = (uint64_t)cw * (uint64_t)(H - 1);
-    const size_t words = (size_t)(W + 31) / 32;
-    const uint32_t* f = bits + (size_t)k * (size_t)H * words;
+    const Img<BLK> f = plane_img<BLK>(bits, W, H, k);
     uint32_t cnt = 0;
     for (int r = 0; r < kMRounds; ++r) {
         const uint64_t c = (uint64_t)b * kMTile + (uint64_t)r * kMThreads + threadIdx.x;
         if (c < cps) {
             const int j = (int)(c / cw), i = (int)(c % cw);
-            const int cs = cell_case(f, words, i, j);
+            const int cs = cell_case<BLK>(f, i, j);
             cnt += (uint32_t)kSegCount[cs];
             if (codes) codes[(size_t)k * cps + c] = (uint8_t)cs;
         }
@@ -94,7 +121,8 @@ __global__ void k_ms_advance(unsigned long long* base, const unsigned long long*
     if (threadIdx.x == 0 && blockIdx.x == 0) *base += blk[nb];
 }
 
-__global__ __launch_bounds__(kMThreads) void k_ms_emit(const uint32_t* bits, int32_t W, int32_t H,
+template <bool BLK>
+__global__ __launch_bounds__(kMThreads) void k_ms_emit(const void* bits, int32_t W, int32_t H,
                                                        uint32_t bps,
                                                        const unsigned long long* blk,
                                                        const unsigned long long* base,
@@ -104,8 +132,7 @@ __global__ __launch_bounds__(kMThreads) void k_ms_emit(const uint32_t* bits, int
     const uint32_t k = blockIdx.x / bps, b = blockIdx.x % bps;
     const uint32_t cw = (uint32_t)(W - 1);
     const uint64_t cps = (uint64_t)cw * (uint64_t)(H - 1);
-    const size_t words = (size_t)(W + 31) / 32;
-    const uint32_t* f = bits + (size_t)k * (size_t)H * words;
+    const Img<BLK> f = plane_img<BLK>(bits, W, H, k);
     uint64_t run = blk[blockIdx.x] + (base ? *base : 0ull);
     const uint64_t lt = lanes_below(lane);
     for (int r = 0; r < kMRounds; ++r) {
@@ -114,7 +141,7 @@ __global__ __launch_bounds__(kMThreads) void k_ms_emit(const uint32_t* bits, int
         if (c < cps) {
             j = (int)(c / cw);
             i = (int)(c % cw);
-            cs = cell_case(f, words, i, j);
+            cs = cell_case<BLK>(f, i, j);
         }
         const int n = kSegCount[cs];
         const uint64_t m0 = ballot64(n & 1), m1 = ballot64(n >> 1);
@@ -152,7 +179,7 @@ size_t contour_tmp_elems(int32_t nk, int32_t W, int32_t H) {
     return n + scan_tmp_elems(n);
 }
 
-lsl_status launch_contours_count(const uint32_t* bits, int32_t nk, int32_t W, int32_t H,
+lsl_status launch_contours_count(const void* bits, bool blkl, int32_t nk, int32_t W, int32_t H,
                                  int64_t* offsets, uint8_t* codes, unsigned long long* tmp,
                                  const unsigned long long* base, hipStream_t st) {
     const uint32_t bps = blocks_per_slice(W, H);
@@ -163,7 +190,10 @@ lsl_status launch_contours_count(const uint32_t* bits, int32_t nk, int32_t W, in
     }
     unsigned long long* blk = tmp;
     unsigned long long* stmp = tmp + nb + 1;
-    k_ms_count<<<(unsigned)nb, kMThreads, 0, st>>>(bits, W, H, bps, codes, blk);
+    if (blkl)
+        k_ms_count<true><<<(unsigned)nb, kMThreads, 0, st>>>(bits, W, H, bps, codes, blk);
+    else
+        k_ms_count<false><<<(unsigned)nb, kMThreads, 0, st>>>(bits, W, H, bps, codes, blk);
     LSL_HIP(hipGetLastError());
     // exclusive scan over nb + 1 entries: the last one receives the total
     LSL_TRY(fill_bytes0(blk + nb, 8, st));
@@ -174,13 +204,17 @@ lsl_status launch_contours_count(const uint32_t* bits, int32_t nk, int32_t W, in
     return LSL_OK;
 }
 
-lsl_status launch_contours_emit(const uint32_t* bits, int32_t nk, int32_t W, int32_t H,
+lsl_status launch_contours_emit(const void* bits, bool blkl, int32_t nk, int32_t W, int32_t H,
                                 const unsigned long long* tmp, unsigned long long* base,
                                 float* segs, int64_t capacity, hipStream_t st) {
     const uint32_t bps = blocks_per_slice(W, H);
     const size_t nb = (size_t)nk * bps;
-    k_ms_emit<<<(unsigned)nb, kMThreads, 0, st>>>(bits, W, H, bps, tmp, base, (float4*)segs,
-                                                  capacity);
+    if (blkl)
+        k_ms_emit<true><<<(unsigned)nb, kMThreads, 0, st>>>(bits, W, H, bps, tmp, base,
+                                                            (float4*)segs, capacity);
+    else
+        k_ms_emit<false><<<(unsigned)nb, kMThreads, 0, st>>>(bits, W, H, bps, tmp, base,
+                                                             (float4*)segs, capacity);
     if (base) k_ms_advance<<<1, 64, 0, st>>>(base, tmp, nb);
     LSL_HIP(hipGetLastError());
     return LSL_OK;

@@ -34,7 +34,7 @@ namespace lsl {
 namespace {
 
 template <typename T, int SZ, bool STATS>
-__global__ __launch_bounds__(256) void k_field(FieldArgs a, uint32_t n_items) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_field(FieldArgs a, uint32_t n_items) {
     __shared__ Stage<T> stage[4][kWave];
     const int wv = threadIdx.x >> 6;
     const uint32_t blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -52,30 +52,31 @@ __global__ __launch_bounds__(256) void k_field(FieldArgs a, uint32_t n_items) {
     fieldk::field_block<T, SZ, STATS>(a, a.s_lo + (int)t, tx, ty, sub, stage[wv]);
 }
 
-// Binary image of a field: one wave packs 512 pixels of a row, 64 at a time
-// with coalesced loads; each ballot is two words of the bit row.
+// Block-major binary image of a field: one wave takes 8 rows x 64 columns
+// (8 blocks); each row's ballot gives one byte of each block's word.
 template <typename T>
-__global__ __launch_bounds__(256) void k_bits(const T* field, int32_t nk, int32_t W, int32_t H,
-                                              T C, uint32_t* bits) {
+__global__ __launch_bounds__(256) void k_bits_blk(const T* field, int32_t nk, int32_t W,
+                                                  int32_t H, T C, uint64_t* out) {
     const int lane = lane_id();
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int chunks = (W + 511) / 512;
-    const int words = (W + 31) / 32;
-    const uint64_t rows = (uint64_t)nk * (uint64_t)H;
-    if (wave >= rows * (uint64_t)chunks) return;
-    const uint64_t row = wave / (uint64_t)chunks;
+    const int nbx = (W + 7) / 8, nby = (H + 7) / 8;
+    const int chunks = (W + 63) / 64;
+    const uint64_t n = (uint64_t)nk * (uint64_t)nby * (uint64_t)chunks;
+    if (wave >= n) return;
     const int c = (int)(wave % (uint64_t)chunks);
-    const T* f = field + row * (uint64_t)W;
-    uint32_t* out = bits + row * (uint64_t)words;
-    uint32_t mine = 0;                   // lane q < 16 keeps word c*16 + q
+    const uint64_t kb = wave / (uint64_t)chunks;           // plane * nby + block row
+    const int by = (int)(kb % (uint64_t)nby);
+    const uint64_t k = kb / (uint64_t)nby;
+    const T* f = field + k * (uint64_t)W * (uint64_t)H;
+    const int i = c * 64 + lane;
+    uint64_t word = 0;                                     // lane b < 8: block c*8 + b
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-        const int i = c * 512 + r * 64 + lane;
-        const uint64_t m = ballot64(i < W && f[i] >= C);
-        if (lane == 2 * r) mine = (uint32_t)m;
-        if (lane == 2 * r + 1) mine = (uint32_t)(m >> 32);
+        const int j = by * 8 + r;
+        const uint64_t m = ballot64(i < W && j < H && f[(size_t)j * W + i] >= C);
+        word |= ((m >> (8 * (lane & 7))) & 0xffull) << (8 * r);
     }
-    if (lane < 16 && c * 16 + lane < words) out[c * 16 + lane] = mine;
+    if (lane < 8 && c * 8 + lane < nbx) out[kb * (uint64_t)nbx + (uint64_t)(c * 8 + lane)] = word;
 }
 
 template <typename T, int SZ>
@@ -113,16 +114,17 @@ lsl_status launch_field(int dtype, const FieldArgs& a, bool stats, hipStream_t s
     return launch_dt<double>(a, stats, (uint32_t)n_items, st);
 }
 
-lsl_status launch_bits(int dtype, const void* field, int32_t nk, int32_t W, int32_t H, double C,
-                       uint32_t* bits, hipStream_t st) {
-    const uint64_t waves = (uint64_t)nk * (uint64_t)H * (uint64_t)((W + 511) / 512);
+lsl_status launch_bits_blk(int dtype, const void* field, int32_t nk, int32_t W, int32_t H,
+                           double C, uint64_t* out, hipStream_t st) {
+    const uint64_t waves = (uint64_t)nk * (uint64_t)((H + 7) / 8) * (uint64_t)((W + 63) / 64);
     if (waves == 0) return LSL_OK;
     const uint64_t blocks = (waves + 3) / 4;
     if (dtype == LSL_F32)
-        k_bits<float><<<(unsigned)blocks, 256, 0, st>>>((const float*)field, nk, W, H, (float)C,
-                                                        bits);
+        k_bits_blk<float><<<(unsigned)blocks, 256, 0, st>>>((const float*)field, nk, W, H,
+                                                            (float)C, out);
     else
-        k_bits<double><<<(unsigned)blocks, 256, 0, st>>>((const double*)field, nk, W, H, C, bits);
+        k_bits_blk<double><<<(unsigned)blocks, 256, 0, st>>>((const double*)field, nk, W, H, C,
+                                                             out);
     LSL_HIP(hipGetLastError());
     return LSL_OK;
 }

@@ -178,9 +178,23 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
                 out[((size_t)(kb + k - a.k0) * (size_t)a.H + (size_t)pj) * (size_t)a.W + (size_t)pi] =
                     acc_s[k] + acc_c[k];
     }
+    if (a.bits_blk) {
+        // binary image, block-major: the block's ballot is its word
+        const size_t nbx = (size_t)(a.W + 7) / 8, nby = (size_t)(a.H + 7) / 8;
+        const T C = (T)a.C;
+#pragma unroll
+        for (int k = 0; k < SZ; ++k) {
+            if (k < nvalid) {
+                const uint64_t m = ballot64(pix && acc_s[k] + acc_c[k] >= C);
+                if (lane == 0)
+                    a.bits_blk[((size_t)(kb + k - a.k0) * nby + (size_t)(j0 >> 3)) * nbx +
+                               (size_t)(i0 >> 3)] = m;
+            }
+        }
+    }
     if (a.bits) {
-        // binary image: the block's ballot holds 8 rows of 8 bits; lane r
-        // stores row r's byte (bit i % 32 of word i / 32 is pixel i)
+        // binary image, row-major: the block's ballot holds 8 rows of 8 bits;
+        // lane r stores row r's byte (bit i % 32 of word i / 32 is pixel i)
         const size_t words = (size_t)(a.W + 31) / 32;
         const T C = (T)a.C;
 #pragma unroll

@@ -64,7 +64,7 @@ struct GroupBuffers {
     uint32_t* eoff;                   // [n_active + 1]
     uint32_t* offsets;                // [n_buckets + 1]
     uint32_t* ids;                    // [n_pairs] sorted positions
-    uint32_t* inv;                    // [n_pairs] emission -> bucket position
+    uint32_t* emi;                    // [n_pairs] bucket entry -> emission index
     uint32_t* owner;                  // [n_pairs] scratch
     uint32_t* k0; uint32_t* v0; uint32_t* k1; uint32_t* v1;   // [n_pairs] scratch
     uint32_t* tmp;                    // scan / sort scratch
@@ -87,22 +87,26 @@ struct FieldArgs {
     double x0, y0, dx, dy, z0, dz, R;
     void* field;                      // [nk][H][W] or null (not written)
     uint32_t* bits;                   // [nk][H][ceil(W/32)] or null: field >= C
+    uint64_t* bits_blk;               // [nk][ceil(H/8)][ceil(W/8)] or null: the same
+                                      // image, one word per 8x8 block (bit 8*row+col)
     double C;
     unsigned long long* stats;        // [3] (stats kernels only)
 };
 lsl_status launch_field(int dtype, const FieldArgs& a, bool stats, hipStream_t st);
-lsl_status launch_bits(int dtype, const void* field, int32_t nk, int32_t W, int32_t H,
-                       double C, uint32_t* bits, hipStream_t st);
+// Block-major binary image (see FieldArgs::bits_blk) of a field.
+lsl_status launch_bits_blk(int dtype, const void* field, int32_t nk, int32_t W, int32_t H,
+                           double C, uint64_t* bits_blk, hipStream_t st);
 
 // ------------------------------------------------------------- contours.hip
 size_t contour_tmp_elems(int32_t nk, int32_t W, int32_t H);
-// Marching squares on binary images bits [nk][H][ceil(W/32)].
+// Marching squares on binary images: row-major bits [nk][H][ceil(W/32)]
+// (blk = false) or block-major words [nk][ceil(H/8)][ceil(W/8)] (blk = true).
 // base (optional, device): running segment count added to this call's
 // offsets and positions; the emit pass advances it by this call's total.
-lsl_status launch_contours_count(const uint32_t* bits, int32_t nk, int32_t W, int32_t H,
+lsl_status launch_contours_count(const void* bits, bool blk, int32_t nk, int32_t W, int32_t H,
                                  int64_t* offsets, uint8_t* codes, unsigned long long* tmp,
                                  const unsigned long long* base, hipStream_t st);
-lsl_status launch_contours_emit(const uint32_t* bits, int32_t nk, int32_t W, int32_t H,
+lsl_status launch_contours_emit(const void* bits, bool blk, int32_t nk, int32_t W, int32_t H,
                                 const unsigned long long* tmp, unsigned long long* base,
                                 float* segs, int64_t capacity, hipStream_t st);
 
@@ -118,17 +122,17 @@ struct BackArgs {
     int32_t k0, nk;
     int32_t W, H;
     double x0, y0, dx, dy, z0, dz, R;
+    const uint32_t* emi;              // bucket entry -> emission index
     const void* grad;                 // [nk][H][W]
-    void* partial;                    // [n_pairs][9] T
+    void* partial;                    // [n_pairs][9] T, in emission order
 };
 lsl_status launch_backward(int dtype, const BackArgs& a, hipStream_t st);
 
 struct ReduceArgs {
-    const void* partial;              // [n_pairs][9]
+    const void* partial;              // [n_pairs][9], emission order
     const uint32_t* active;           // [n_active] sorted positions
     uint32_t n_active;
     const uint32_t* eoff;             // [n_active + 1]
-    const uint32_t* inv;              // emission -> bucket position
     const void* rec;
     const void* w;
     double R;
