@@ -45,7 +45,25 @@ def parse():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--slab", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (x -> -x), the reference "
+                         "for scaling the HBM byte counters")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """One elementwise kernel that reads 1 GiB and writes 1 GiB: what the
+    FETCH_SIZE / WRITE_SIZE counters report for it converts their units to
+    bytes for the other kernels."""
+    import torch
+    n = 1 << 28
+    x = torch.full((n,), 1.0, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_read_bytes": 4 * n, "copy_write_bytes": 4 * n,
+                      "kernel": "neg (float32, contiguous)"}), flush=True)
 
 
 def main():
@@ -54,6 +72,9 @@ def main():
         print(json.dumps({"error": "this path runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import torch
     from paper_2101_05031_amd import api, synth
 

@@ -321,7 +321,6 @@ FieldArgs field_args(const lattice_bins* b, int32_t k0, int32_t nk, void* field)
     a.R = b->R;
     a.C = b->C;
     a.field = field;
-    a.bits = nullptr;
     a.bits_blk = nullptr;
     return a;
 }
@@ -366,6 +365,20 @@ unsigned nblk(size_t n) { return (unsigned)((n + 255) / 256); }
 // 32-bit words of a block-major binary image of nk planes
 size_t blk_words(const lattice_bins* b, int32_t nk) {
     return 2 * (size_t)nk * (size_t)((b->grid.H + 7) / 8) * (size_t)((b->grid.W + 7) / 8);
+}
+
+// library scratch for the block-major binary images of nk planes
+lsl_status ensure_cbits(lattice_bins* b, int32_t nk, hipStream_t st) {
+    const size_t nbits = blk_words(b, nk);
+    if (nbits <= b->cbits_elems) return LSL_OK;
+    LSL_HIP(hipStreamSynchronize(st));
+    b->release(b->cbits);
+    b->cbits = nullptr;
+    b->cbits_elems = 0;
+    LSL_TRY(b->alloc_t(&b->cbits, nbits));
+    b->cbits_elems = nbits;
+    b->drop_graphs();
+    return LSL_OK;
 }
 
 }  // namespace
@@ -650,17 +663,22 @@ lsl_status slice_field(lattice_bins* b, int32_t k0, int32_t nk, void* field, uin
             LSL_TRY(fill_bytes0(bits, (size_t)nk * b->grid.H * ((b->grid.W + 31) / 32) * 4, st));
         return LSL_OK;
     }
+    // binary images: block-major in library scratch, then the caller's
+    // row-major copy
+    if (bits) LSL_TRY(ensure_cbits(b, nk, st));
     // the plan covers every slab, so every block of every plane is written
-    return for_groups(b, k0, nk, [&](int g, int s_lo, int s_hi) -> lsl_status {
+    LSL_TRY(for_groups(b, k0, nk, [&](int g, int s_lo, int s_hi) -> lsl_status {
         LSL_TRY(ensure_group(b, g, st));
         FieldArgs a = field_args(b, k0, nk, field);
-        a.bits = bits;
+        a.bits_blk = bits ? (uint64_t*)b->cbits : nullptr;
         a.n_pairs = (uint32_t)b->groups[g].pairs;
         a.group_s0 = b->groups[g].sa;
         a.s_lo = s_lo;
         a.s_hi = s_hi;
         return launch_field(b->dtype, a, false, st);
-    });
+    }));
+    if (bits) LSL_TRY(launch_bits_rows((const uint64_t*)b->cbits, nk, b->grid.W, b->grid.H, bits, st));
+    return LSL_OK;
 }
 
 lsl_status slice_field_stats(lattice_bins* b, int32_t k0, int32_t nk, int64_t* counts,
@@ -713,21 +731,13 @@ lsl_status slice_contours(const lattice_bins* cb, int32_t nk, const void* field,
         b->ctmp_elems = need;
         b->drop_graphs();
     }
-    const size_t nbits = blk_words(b, nk);
-    if (nbits > b->cbits_elems) {
-        LSL_HIP(hipStreamSynchronize(st));
-        b->release(b->cbits);
-        b->cbits = nullptr;
-        b->cbits_elems = 0;
-        LSL_TRY(b->alloc_t(&b->cbits, nbits));
-        b->cbits_elems = nbits;
-        b->drop_graphs();
-    }
+    LSL_TRY(ensure_cbits(b, nk, st));
     // the binary images (block-major), then marching squares on them
+    const uint64_t* img = (const uint64_t*)b->cbits;
     LSL_TRY(launch_bits_blk(b->dtype, field, nk, b->grid.W, b->grid.H, b->C,
                             (uint64_t*)b->cbits, st));
-    LSL_TRY(launch_contours_count(b->cbits, true, nk, b->grid.W, b->grid.H, offsets, case_codes,
-                                  b->ctmp, nullptr, st));
+    LSL_TRY(launch_contours_count(img, nk, b->grid.W, b->grid.H, offsets, case_codes, b->ctmp,
+                                  nullptr, st));
     int64_t tot = 0;
     LSL_HIP(hipMemcpyAsync(&tot, offsets + nk, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     LSL_HIP(hipStreamSynchronize(st));
@@ -738,8 +748,8 @@ lsl_status slice_contours(const lattice_bins* cb, int32_t nk, const void* field,
         return LSL_ECAPACITY;
     }
     if (tot > 0)
-        LSL_TRY(launch_contours_emit(b->cbits, true, nk, b->grid.W, b->grid.H, b->ctmp, nullptr,
-                                     segs, capacity, st));
+        LSL_TRY(launch_contours_emit(img, nk, b->grid.W, b->grid.H, b->ctmp, nullptr, segs,
+                                     capacity, st));
     return LSL_OK;
 }
 
@@ -827,12 +837,12 @@ lsl_status batch_group_work(lattice_bins* b, int g, int32_t k0, int32_t nk, int 
     // this group's planes: the caller's field (if any) and binary images (the
     // caller's, or library scratch)
     void* fbase = field ? (void*)((char*)field + (size_t)(kg0 - k0) * plane * b->esize()) : nullptr;
-    // caller's bits: row-major; otherwise library scratch, block-major
+    // binary images: block-major in library scratch; the caller's bits, if
+    // any, get a row-major copy
     uint32_t* bbase = bits ? bits + (size_t)(kg0 - k0) * (size_t)b->grid.H * words : nullptr;
     FieldArgs a = field_args(b, kg0, nkg, fbase);
-    a.bits = bbase;
-    a.bits_blk = bits ? nullptr : (uint64_t*)b->cbits;
-    const void* img = bits ? (const void*)bbase : (const void*)b->cbits;
+    a.bits_blk = (uint64_t*)b->cbits;
+    const uint64_t* img = (const uint64_t*)b->cbits;
     a.n_pairs = (uint32_t)b->groups[g].pairs;
     a.group_s0 = b->groups[g].sa;
     a.s_lo = s_lo;
@@ -860,10 +870,11 @@ lsl_status batch_group_work(lattice_bins* b, int g, int32_t k0, int32_t nk, int 
         ba.counter = counter;
         return launch_persistent(b->dtype, ba, persistent_blocks(b->dtype, b->slab), st);
     }
-    LSL_TRY(launch_contours_count(img, !bits, nkg, b->grid.W, b->grid.H, offsets + (kg0 - k0),
-                                  nullptr, b->ctmp, base, st));
-    LSL_TRY(launch_contours_emit(img, !bits, nkg, b->grid.W, b->grid.H, b->ctmp, base, segs,
-                                 capacity, st));
+    LSL_TRY(launch_contours_count(img, nkg, b->grid.W, b->grid.H, offsets + (kg0 - k0), nullptr,
+                                  b->ctmp, base, st));
+    LSL_TRY(launch_contours_emit(img, nkg, b->grid.W, b->grid.H, b->ctmp, base, segs, capacity,
+                                 st));
+    if (bbase) LSL_TRY(launch_bits_rows(img, nkg, b->grid.W, b->grid.H, bbase, st));
     return LSL_OK;
 }
 
@@ -979,21 +990,20 @@ lsl_status slice_batch(lattice_bins* b, int32_t k0, int32_t nk, void* field, uin
         b->ctmp_elems = ct;
         b->drop_graphs();
     }
-    const size_t nbits = blk_words(b, (int32_t)max_planes);
-    if (!bits && b->cbits_elems < nbits) {
-        LSL_HIP(hipStreamSynchronize(st));
-        b->release(b->cbits);
-        b->cbits = nullptr;
-        b->cbits_elems = 0;
-        LSL_TRY(b->alloc_t(&b->cbits, nbits));
-        b->cbits_elems = nbits;
-        b->drop_graphs();
-    }
+    LSL_TRY(ensure_cbits(b, (int32_t)max_planes, st));
     uint32_t* counter = b->queue_buf + 4 * b->queue_cap;
     unsigned long long* base = (unsigned long long*)(counter + 32);
     LSL_TRY(fill_bytes0(base, 8, st));
     if (b->n_binned == 0 || b->groups.empty()) {
+        // nothing binned: empty field, empty images, no segments
         if (field) LSL_TRY(fill_bytes0(field, (size_t)nk * plane * b->esize(), st));
+        if (bits)
+            LSL_TRY(fill_bytes0(bits, (size_t)nk * b->grid.H * ((b->grid.W + 31) / 32) * 4, st));
+        LSL_TRY(fill_bytes0(offsets, (size_t)(nk + 1) * 8, st));
+        if (total) *total = 0;
+        LSL_HIP(hipStreamSynchronize(st));
+        b->last_field_ms = 0.0;
+        return LSL_OK;
     }
     hipStream_t cap = nullptr;
     LSL_TRY(for_groups(b, k0, nk, [&](int g, int s_lo, int s_hi) -> lsl_status {

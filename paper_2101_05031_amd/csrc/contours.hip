@@ -1,26 +1,32 @@
 // Marching squares on the binary slice images (Sec. 4: rough boundary
-// curves from the binary image), read as bit images (one bit per pixel), in
-// two passes so that segments come out in row-major cell order with no
-// atomics on the output:
-//
-//   count: case code and segment count (0, 1 or 2) per cell; per-block totals
-//   scan : exclusive prefix over (plane, block) totals -> per-plane offsets
-//   emit : re-derive the counts, rank them inside the block with wave ballots
-//          (count bits 0 and 1 -> two ballots) and a per-wave LDS prefix, and
-//          write each cell's segments at its offset.
+// curves from the binary image).  The images are block-major: one 64-bit
+// word per 8x8 pixel block, bit 8 r + c = pixel (8 bx + c, 8 by + r).
 //
 // Cell (i, j) has corners (i,j), (i+1,j), (i+1,j+1), (i,j+1) -> bits b0..b3
-// (the image's bits).  Segment ends are edge midpoints in grid units;
-// the inside lies on the left of each segment; the saddles 5 and 10 keep the
-// two inside corners apart.
+// of its case code.  For the 64 cells of a block these are four 64-bit masks
+// built from the block word and its right, lower and lower-right neighbours
+// with shifts, so one lane finds all boundary cells of a block at once:
+//   M = (b0|b1|b2|b3) & ~(b0&b1&b2&b3)       cells with one or two segments
+//   S = saddles 5 and 10                        cells with two segments
+// A wave takes one strip of 8 pixel rows of one plane (lane = block column):
+//
+//   count: popcount(M) + popcount(S) over the strip -> per-strip totals
+//   scan : exclusive prefix over (plane, strip) -> per-plane offsets
+//   emit : per-row totals of the strip, then per 64-block chunk a wave prefix
+//          of the per-(row, block) counts, so every boundary cell knows its
+//          rank in row-major cell order; each writes its segments there.
+//
+// Segment ends are edge midpoints in grid units; the inside lies on the left
+// of each segment; the saddles 5 and 10 keep the two inside corners apart.
+// Outputs are deterministic and written with no atomics.
 #include "kernels.hpp"
 
 namespace lsl {
 namespace {
 
 constexpr int kMThreads = 256;
-constexpr int kMRounds = 8;
-constexpr int kMTile = kMThreads * kMRounds;   // cells per block
+constexpr uint64_t kCol0 = 0x0101010101010101ull;   // column 0 of every row
+constexpr uint64_t kCol7 = 0x8080808080808080ull;   // column 7 of every row
 
 // Per case: number of segments and up to two segments as
 // (x0, y0, x1, y1) in half units of the cell.
@@ -45,177 +51,267 @@ __constant__ int8_t kSeg[16][2][4] = {
     {{0, 0, 0, 0}, {0, 0, 0, 0}},
 };
 
-__device__ __forceinline__ uint32_t bit_at(const uint32_t* row, int i) {
-    return (row[i >> 5] >> (i & 31)) & 1u;
-}
 
-// One plane of a binary image, row-major (BLK = false: `words` 32-bit words
-// per row) or block-major (BLK = true: `words` 8x8-block words per block row).
-template <bool BLK>
-struct Img {
-    const void* p;
-    size_t words;
-    __device__ __forceinline__ uint32_t at(int i, int j) const {
-        if (BLK) {
-            const uint64_t w = ((const uint64_t*)p)[(size_t)(j >> 3) * words + (size_t)(i >> 3)];
-            return (uint32_t)(w >> (8 * (j & 7) + (i & 7))) & 1u;
-        }
-        return bit_at((const uint32_t*)p + (size_t)j * words, i);
-    }
+// The four corner masks of the 64 cells of block (bx, by) of one plane, with
+// the cells outside [0, W-1) x [0, H-1) cleared from M and S.
+struct CellMasks {
+    uint64_t b0, b1, b2, b3, m, s;
 };
 
-template <bool BLK>
-__device__ __forceinline__ Img<BLK> plane_img(const void* bits, int32_t W, int32_t H, uint32_t k) {
-    Img<BLK> m;
-    if (BLK) {
-        m.words = (size_t)(W + 7) / 8;
-        m.p = (const uint64_t*)bits + (size_t)k * (size_t)((H + 7) / 8) * m.words;
-    } else {
-        m.words = (size_t)(W + 31) / 32;
-        m.p = (const uint32_t*)bits + (size_t)k * (size_t)H * m.words;
-    }
-    return m;
+__device__ __forceinline__ CellMasks cell_masks(const uint64_t* P, int nbx, int nby, int bx,
+                                                int by, int32_t W, int32_t H) {
+    const size_t row = (size_t)by * (size_t)nbx;
+    const bool right = bx + 1 < nbx, down = by + 1 < nby;
+    const uint64_t w = P[row + bx];
+    const uint64_t wr = right ? P[row + bx + 1] : 0ull;
+    const uint64_t wd = down ? P[row + nbx + bx] : 0ull;
+    const uint64_t wdr = (right && down) ? P[row + nbx + bx + 1] : 0ull;
+    CellMasks c;
+    c.b0 = w;
+    c.b1 = ((w >> 1) & ~kCol7) | ((wr & kCol0) << 7);              // pixel (i+1, j)
+    c.b3 = (w >> 8) | (wd << 56);                                   // pixel (i, j+1)
+    const uint64_t b1d = ((wd >> 1) & ~kCol7) | ((wdr & kCol0) << 7);
+    c.b2 = (c.b1 >> 8) | (b1d << 56);                               // pixel (i+1, j+1)
+    int nc = W - 1 - 8 * bx, nr = H - 1 - 8 * by;                   // valid cell columns / rows
+    nc = nc < 0 ? 0 : (nc > 8 ? 8 : nc);
+    nr = nr < 0 ? 0 : (nr > 8 ? 8 : nr);
+    const uint64_t cols = (uint64_t)((1u << nc) - 1u) * kCol0;
+    const uint64_t rows = nr >= 8 ? ~0ull : ((1ull << (8 * nr)) - 1ull);
+    const uint64_t valid = cols & rows;
+    const uint64_t all = c.b0 & c.b1 & c.b2 & c.b3;
+    const uint64_t any = c.b0 | c.b1 | c.b2 | c.b3;
+    c.m = any & ~all & valid;
+    c.s = ((c.b0 & c.b2 & ~c.b1 & ~c.b3) | (c.b1 & c.b3 & ~c.b0 & ~c.b2)) & valid;
+    return c;
 }
 
-// case code of cell (i, j)
-template <bool BLK>
-__device__ __forceinline__ int cell_case(const Img<BLK>& m, int i, int j) {
-    return (int)(m.at(i, j) | (m.at(i + 1, j) << 1) | (m.at(i + 1, j + 1) << 2) |
-                 (m.at(i, j + 1) << 3));
+// segments of row r (0..7) of a block: one per boundary cell, two per saddle
+__device__ __forceinline__ uint32_t row_count(const CellMasks& c, int r) {
+    return (uint32_t)(__popc((uint32_t)(c.m >> (8 * r)) & 0xffu) +
+                      __popc((uint32_t)(c.s >> (8 * r)) & 0xffu));
 }
 
-template <bool BLK>
-__global__ __launch_bounds__(kMThreads) void k_ms_count(const void* bits, int32_t W,
-                                                        int32_t H, uint32_t bps, uint8_t* codes,
-                                                        unsigned long long* blk) {
-    __shared__ uint32_t sm[4];
-    const uint32_t k = blockIdx.x / bps, b = blockIdx.x % bps;
-    const uint32_t cw = (uint32_t)(W - 1);
-    const uint64_t cps = (uint64_t)cw * (uint64_t)(H - 1);
-    const Img<BLK> f = plane_img<BLK>(bits, W, H, k);
+__global__ __launch_bounds__(kMThreads) void k_strip_count(const uint64_t* img, int32_t nk,
+                                                           int32_t W, int32_t H,
+                                                           unsigned long long* tot) {
+    const int lane = lane_id();
+    const int nbx = (W + 7) / 8, nby = (H + 7) / 8;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    if (wave >= (uint64_t)nk * (uint64_t)nby) return;
+    const uint64_t k = wave / (uint64_t)nby;
+    const int by = (int)(wave % (uint64_t)nby);
+    const uint64_t* P = img + k * (uint64_t)nby * (uint64_t)nbx;
     uint32_t cnt = 0;
-    for (int r = 0; r < kMRounds; ++r) {
-        const uint64_t c = (uint64_t)b * kMTile + (uint64_t)r * kMThreads + threadIdx.x;
-        if (c < cps) {
-            const int j = (int)(c / cw), i = (int)(c % cw);
-            const int cs = cell_case<BLK>(f, i, j);
-            cnt += (uint32_t)kSegCount[cs];
-            if (codes) codes[(size_t)k * cps + c] = (uint8_t)cs;
-        }
+    for (int bx = lane; bx < nbx; bx += kWave) {
+        const CellMasks c = cell_masks(P, nbx, nby, bx, by, W, H);
+        cnt += (uint32_t)(__popcll(c.m) + __popcll(c.s));
     }
     for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d, kWave);
-    if (lane_id() == 0) sm[threadIdx.x >> 6] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) blk[blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3];
+    if (lane == 0) tot[wave] = cnt;
 }
 
-__global__ void k_ms_offsets(const unsigned long long* blk, uint32_t bps, int32_t nk,
+__global__ void k_ms_offsets(const unsigned long long* scan, uint32_t per_plane, int32_t nk,
                              const unsigned long long* base, int64_t* offsets) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k <= nk) offsets[k] = (int64_t)(blk[(size_t)k * bps] + (base ? *base : 0ull));
+    if (k <= nk) offsets[k] = (int64_t)(scan[(size_t)k * per_plane] + (base ? *base : 0ull));
 }
 
 // base += this call's total (the segments of several calls share one array)
-__global__ void k_ms_advance(unsigned long long* base, const unsigned long long* blk,
-                             size_t nb) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *base += blk[nb];
+__global__ void k_ms_advance(unsigned long long* base, const unsigned long long* scan,
+                             size_t n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *base += scan[n];
 }
 
-template <bool BLK>
-__global__ __launch_bounds__(kMThreads) void k_ms_emit(const void* bits, int32_t W, int32_t H,
-                                                       uint32_t bps,
-                                                       const unsigned long long* blk,
-                                                       const unsigned long long* base,
-                                                       float4* segs, int64_t capacity) {
-    __shared__ uint32_t wsum[4];
-    const int lane = lane_id(), w = threadIdx.x >> 6;
-    const uint32_t k = blockIdx.x / bps, b = blockIdx.x % bps;
-    const uint32_t cw = (uint32_t)(W - 1);
-    const uint64_t cps = (uint64_t)cw * (uint64_t)(H - 1);
-    const Img<BLK> f = plane_img<BLK>(bits, W, H, k);
-    uint64_t run = blk[blockIdx.x] + (base ? *base : 0ull);
-    const uint64_t lt = lanes_below(lane);
-    for (int r = 0; r < kMRounds; ++r) {
-        const uint64_t c = (uint64_t)b * kMTile + (uint64_t)r * kMThreads + threadIdx.x;
-        int cs = 0, i = 0, j = 0;
-        if (c < cps) {
-            j = (int)(c / cw);
-            i = (int)(c % cw);
-            cs = cell_case<BLK>(f, i, j);
-        }
-        const int n = kSegCount[cs];
-        const uint64_t m0 = ballot64(n & 1), m1 = ballot64(n >> 1);
-        const uint32_t wtot = (uint32_t)(__popcll(m0) + 2 * __popcll(m1));
-        const uint32_t pre = (uint32_t)(__popcll(m0 & lt) + 2 * __popcll(m1 & lt));
-        if (lane == 0) wsum[w] = wtot;
-        __syncthreads();
-        uint32_t before = 0, tot = 0;
+// inclusive prefix over the wave's lanes
+__device__ __forceinline__ uint64_t wave_incl(uint64_t v, int lane) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint64_t t = __shfl_up(v, (unsigned)d, kWave);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_total(uint64_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+__global__ __launch_bounds__(kMThreads) void k_strip_emit(const uint64_t* img, int32_t nk,
+                                                          int32_t W, int32_t H,
+                                                          const unsigned long long* scan,
+                                                          const unsigned long long* base,
+                                                          float4* segs, int64_t capacity) {
+    const int lane = lane_id();
+    const int nbx = (W + 7) / 8, nby = (H + 7) / 8;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    if (wave >= (uint64_t)nk * (uint64_t)nby) return;
+    const uint64_t k = wave / (uint64_t)nby;
+    const int by = (int)(wave % (uint64_t)nby);
+    const uint64_t* P = img + k * (uint64_t)nby * (uint64_t)nbx;
+
+    // per-row totals of the strip (two rows per 64-bit word, 32 bits each)
+    uint64_t t2[4] = {0, 0, 0, 0};
+    for (int bx = lane; bx < nbx; bx += kWave) {
+        const CellMasks c = cell_masks(P, nbx, nby, bx, by, W, H);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            t2[q] += (uint64_t)row_count(c, 2 * q) | ((uint64_t)row_count(c, 2 * q + 1) << 32);
+    }
+    uint64_t pos[8];                 // next free position of each row, for this lane
+    {
+        uint64_t run = scan[wave] + (base ? *base : 0ull);
+#pragma unroll
         for (int q = 0; q < 4; ++q) {
-            before += q < w ? wsum[q] : 0u;
-            tot += wsum[q];
+            const uint64_t t = wave_total(t2[q]);
+            pos[2 * q] = run;
+            run += t & 0xffffffffull;
+            pos[2 * q + 1] = run;
+            run += t >> 32;
         }
-        const uint64_t o = run + before + pre;
-        for (int s = 0; s < n; ++s) {
-            if ((int64_t)(o + s) < capacity) {
-                const int8_t* g = kSeg[cs][s];
-                segs[o + s] = make_float4((float)i + 0.5f * g[0], (float)j + 0.5f * g[1],
-                                          (float)i + 0.5f * g[2], (float)j + 0.5f * g[3]);
+    }
+    for (int bx0 = 0; bx0 < nbx; bx0 += kWave) {
+        const int bx = bx0 + lane;
+        CellMasks c{};
+        if (bx < nbx) c = cell_masks(P, nbx, nby, bx, by, W, H);
+        const int i0 = 8 * bx, j0 = 8 * by;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint64_t v = (uint64_t)row_count(c, 2 * q) | ((uint64_t)row_count(c, 2 * q + 1) << 32);
+            const uint64_t inc = wave_incl(v, lane);
+            const uint64_t all = __shfl(inc, kWave - 1, kWave);
+            const uint64_t ex = inc - v;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int r = 2 * q + h;
+                uint64_t o = pos[r] + ((ex >> (32 * h)) & 0xffffffffull);
+                uint32_t mb = (uint32_t)(c.m >> (8 * r)) & 0xffu;
+                while (mb) {
+                    const int cc = __ffs(mb) - 1;
+                    mb &= mb - 1u;
+                    const int bit = 8 * r + cc;
+                    const int cs = (int)(((c.b0 >> bit) & 1ull) | (((c.b1 >> bit) & 1ull) << 1) |
+                                         (((c.b2 >> bit) & 1ull) << 2) |
+                                         (((c.b3 >> bit) & 1ull) << 3));
+                    const int n = kSegCount[cs];
+                    const float fi = (float)(i0 + cc), fj = (float)(j0 + r);
+                    for (int sg = 0; sg < n; ++sg) {
+                        if ((int64_t)(o + sg) < capacity) {
+                            const int8_t* g = kSeg[cs][sg];
+                            segs[o + sg] = make_float4(fi + 0.5f * g[0], fj + 0.5f * g[1],
+                                                       fi + 0.5f * g[2], fj + 0.5f * g[3]);
+                        }
+                    }
+                    o += (uint64_t)n;
+                }
+                pos[r] += (all >> (32 * h)) & 0xffffffffull;
             }
         }
-        run += tot;
-        __syncthreads();
     }
 }
 
-uint32_t blocks_per_slice(int32_t W, int32_t H) {
-    const uint64_t cps = (uint64_t)(W - 1) * (uint64_t)(H - 1);
-    return (uint32_t)((cps + kMTile - 1) / kMTile);
+// Case code of every cell, [nk][H-1][W-1] bytes (optional output).
+__global__ __launch_bounds__(kMThreads) void k_ms_codes(const uint64_t* img, int32_t W, int32_t H,
+                                                        uint8_t* codes) {
+    const uint32_t k = blockIdx.y;
+    const int nbx = (W + 7) / 8, nby = (H + 7) / 8;
+    const uint64_t cw = (uint64_t)(W - 1), cps = cw * (uint64_t)(H - 1);
+    const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cps) return;
+    const int j = (int)(c / cw), i = (int)(c % cw);
+    const uint64_t* P = img + (uint64_t)k * (uint64_t)nby * (uint64_t)nbx;
+    auto at = [&](int x, int y) -> uint32_t {
+        const uint64_t w = P[(size_t)(y >> 3) * (size_t)nbx + (size_t)(x >> 3)];
+        return (uint32_t)(w >> (8 * (y & 7) + (x & 7))) & 1u;
+    };
+    codes[(uint64_t)k * cps + c] =
+        (uint8_t)(at(i, j) | (at(i + 1, j) << 1) | (at(i + 1, j + 1) << 2) | (at(i, j + 1) << 3));
+}
+
+// Row-major copy of block-major images: word w of row j holds pixels
+// 32 w .. 32 w + 31 (bit x % 32 is pixel x).
+__global__ __launch_bounds__(256) void k_bits_rows(const uint64_t* img, uint64_t n, int32_t W,
+                                                   int32_t H, uint32_t* out) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int words = (W + 31) / 32, nbx = (W + 7) / 8, nby = (H + 7) / 8;
+    const int w = (int)(t % (uint64_t)words);
+    const uint64_t kj = t / (uint64_t)words;
+    const int j = (int)(kj % (uint64_t)H);
+    const uint64_t k = kj / (uint64_t)H;
+    const uint64_t* row = img + (k * (uint64_t)nby + (uint64_t)(j >> 3)) * (uint64_t)nbx;
+    uint32_t v = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int bx = 4 * w + q;
+        if (bx < nbx) v |= (uint32_t)((row[bx] >> (8 * (j & 7))) & 0xffull) << (8 * q);
+    }
+    out[t] = v;
 }
 
 }  // namespace
 
 size_t contour_tmp_elems(int32_t nk, int32_t W, int32_t H) {
-    const size_t n = (size_t)nk * blocks_per_slice(W, H) + 1;
+    (void)W;
+    const size_t n = (size_t)nk * (size_t)((H + 7) / 8) + 1;
     return n + scan_tmp_elems(n);
 }
 
-lsl_status launch_contours_count(const void* bits, bool blkl, int32_t nk, int32_t W, int32_t H,
+lsl_status launch_contours_count(const uint64_t* img, int32_t nk, int32_t W, int32_t H,
                                  int64_t* offsets, uint8_t* codes, unsigned long long* tmp,
                                  const unsigned long long* base, hipStream_t st) {
-    const uint32_t bps = blocks_per_slice(W, H);
-    const size_t nb = (size_t)nk * bps;
-    if (nb > 0x7fffffffull) {
+    const uint32_t nby = (uint32_t)((H + 7) / 8);
+    const size_t n = (size_t)nk * nby;
+    if (n > 0x7fffffffull / 4) {
         set_error("slice_contours: too many planes in one call");
         return LSL_EINVAL;
     }
-    unsigned long long* blk = tmp;
-    unsigned long long* stmp = tmp + nb + 1;
-    if (blkl)
-        k_ms_count<true><<<(unsigned)nb, kMThreads, 0, st>>>(bits, W, H, bps, codes, blk);
+    unsigned long long* tot = tmp;
+    unsigned long long* stmp = tmp + n + 1;
+    if (W > 1 && H > 1)
+        k_strip_count<<<(unsigned)((n + 3) / 4), kMThreads, 0, st>>>(img, nk, W, H, tot);
     else
-        k_ms_count<false><<<(unsigned)nb, kMThreads, 0, st>>>(bits, W, H, bps, codes, blk);
+        LSL_TRY(fill_bytes0(tot, n * 8, st));
     LSL_HIP(hipGetLastError());
-    // exclusive scan over nb + 1 entries: the last one receives the total
-    LSL_TRY(fill_bytes0(blk + nb, 8, st));
-    LSL_TRY(exclusive_scan_u64((const uint64_t*)blk, (uint64_t*)blk, nb + 1, (uint64_t*)stmp,
+    if (codes && W > 1 && H > 1) {
+        const uint64_t cps = (uint64_t)(W - 1) * (uint64_t)(H - 1);
+        const uint64_t words = (uint64_t)((H + 7) / 8) * (uint64_t)((W + 7) / 8);
+        for (int32_t k = 0; k < nk; k += 65535) {        // grid y holds at most 65535 planes
+            const int32_t m = nk - k < 65535 ? nk - k : 65535;
+            const dim3 grid((unsigned)((cps + kMThreads - 1) / kMThreads), (unsigned)m);
+            k_ms_codes<<<grid, kMThreads, 0, st>>>(img + (uint64_t)k * words, W, H,
+                                                   codes + (uint64_t)k * cps);
+        }
+        LSL_HIP(hipGetLastError());
+    }
+    // exclusive scan over n + 1 entries: the last one receives the total
+    LSL_TRY(fill_bytes0(tot + n, 8, st));
+    LSL_TRY(exclusive_scan_u64((const uint64_t*)tot, (uint64_t*)tot, n + 1, (uint64_t*)stmp,
                                nullptr, st));
-    k_ms_offsets<<<(nk + 1 + 255) / 256, 256, 0, st>>>(blk, bps, nk, base, offsets);
+    k_ms_offsets<<<(nk + 1 + 255) / 256, 256, 0, st>>>(tot, nby, nk, base, offsets);
     LSL_HIP(hipGetLastError());
     return LSL_OK;
 }
 
-lsl_status launch_contours_emit(const void* bits, bool blkl, int32_t nk, int32_t W, int32_t H,
+lsl_status launch_contours_emit(const uint64_t* img, int32_t nk, int32_t W, int32_t H,
                                 const unsigned long long* tmp, unsigned long long* base,
                                 float* segs, int64_t capacity, hipStream_t st) {
-    const uint32_t bps = blocks_per_slice(W, H);
-    const size_t nb = (size_t)nk * bps;
-    if (blkl)
-        k_ms_emit<true><<<(unsigned)nb, kMThreads, 0, st>>>(bits, W, H, bps, tmp, base,
-                                                            (float4*)segs, capacity);
-    else
-        k_ms_emit<false><<<(unsigned)nb, kMThreads, 0, st>>>(bits, W, H, bps, tmp, base,
-                                                             (float4*)segs, capacity);
-    if (base) k_ms_advance<<<1, 64, 0, st>>>(base, tmp, nb);
+    const uint32_t nby = (uint32_t)((H + 7) / 8);
+    const size_t n = (size_t)nk * nby;
+    if (W > 1 && H > 1)
+        k_strip_emit<<<(unsigned)((n + 3) / 4), kMThreads, 0, st>>>(img, nk, W, H, tmp, base,
+                                                                  (float4*)segs, capacity);
+    if (base) k_ms_advance<<<1, 64, 0, st>>>(base, tmp, n);
+    LSL_HIP(hipGetLastError());
+    return LSL_OK;
+}
+
+lsl_status launch_bits_rows(const uint64_t* img, int32_t nk, int32_t W, int32_t H,
+                            uint32_t* bits, hipStream_t st) {
+    const uint64_t n = (uint64_t)nk * (uint64_t)H * (uint64_t)((W + 31) / 32);
+    if (n == 0) return LSL_OK;
+    k_bits_rows<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(img, n, W, H, bits);
     LSL_HIP(hipGetLastError());
     return LSL_OK;
 }

@@ -192,23 +192,6 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
             }
         }
     }
-    if (a.bits) {
-        // binary image, row-major: the block's ballot holds 8 rows of 8 bits;
-        // lane r stores row r's byte (bit i % 32 of word i / 32 is pixel i)
-        const size_t words = (size_t)(a.W + 31) / 32;
-        const T C = (T)a.C;
-#pragma unroll
-        for (int k = 0; k < SZ; ++k) {
-            if (k < nvalid) {
-                const uint64_t m = ballot64(pix && acc_s[k] + acc_c[k] >= C);
-                if (lane < kBlockPix && j0 + lane < a.H) {
-                    uint8_t* row = (uint8_t*)(a.bits + ((size_t)(kb + k - a.k0) * (size_t)a.H +
-                                                        (size_t)(j0 + lane)) * words);
-                    row[i0 >> 3] = (uint8_t)(m >> (kBlockPix * lane));
-                }
-            }
-        }
-    }
 }
 
 

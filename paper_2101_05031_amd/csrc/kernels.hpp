@@ -86,9 +86,8 @@ struct FieldArgs {
     int32_t W, H;
     double x0, y0, dx, dy, z0, dz, R;
     void* field;                      // [nk][H][W] or null (not written)
-    uint32_t* bits;                   // [nk][H][ceil(W/32)] or null: field >= C
-    uint64_t* bits_blk;               // [nk][ceil(H/8)][ceil(W/8)] or null: the same
-                                      // image, one word per 8x8 block (bit 8*row+col)
+    uint64_t* bits_blk;               // [nk][ceil(H/8)][ceil(W/8)] or null: field >= C,
+                                      // one word per 8x8 block (bit 8*row+col)
     double C;
     unsigned long long* stats;        // [3] (stats kernels only)
 };
@@ -99,16 +98,18 @@ lsl_status launch_bits_blk(int dtype, const void* field, int32_t nk, int32_t W, 
 
 // ------------------------------------------------------------- contours.hip
 size_t contour_tmp_elems(int32_t nk, int32_t W, int32_t H);
-// Marching squares on binary images: row-major bits [nk][H][ceil(W/32)]
-// (blk = false) or block-major words [nk][ceil(H/8)][ceil(W/8)] (blk = true).
+// Marching squares on block-major binary images [nk][ceil(H/8)][ceil(W/8)].
 // base (optional, device): running segment count added to this call's
 // offsets and positions; the emit pass advances it by this call's total.
-lsl_status launch_contours_count(const void* bits, bool blk, int32_t nk, int32_t W, int32_t H,
+lsl_status launch_contours_count(const uint64_t* img, int32_t nk, int32_t W, int32_t H,
                                  int64_t* offsets, uint8_t* codes, unsigned long long* tmp,
                                  const unsigned long long* base, hipStream_t st);
-lsl_status launch_contours_emit(const void* bits, bool blk, int32_t nk, int32_t W, int32_t H,
+lsl_status launch_contours_emit(const uint64_t* img, int32_t nk, int32_t W, int32_t H,
                                 const unsigned long long* tmp, unsigned long long* base,
                                 float* segs, int64_t capacity, hipStream_t st);
+// Row-major bits [nk][H][ceil(W/32)] from block-major images.
+lsl_status launch_bits_rows(const uint64_t* img, int32_t nk, int32_t W, int32_t H,
+                            uint32_t* bits, hipStream_t st);
 
 // ------------------------------------------------------------- backward.hip
 struct BackArgs {

@@ -183,8 +183,18 @@ def test_empty_and_absent_lattices():
             l2.nodes = l2.nodes + np.float32(1000.0)
         b = bin_lattice(l2, grid)
         assert b.info()["n_binned"] == 0
-        f = api.slice_field(b, 0, 3)
-        assert float(f.abs().max()) == 0.0
+        f, bits = api.slice_field(b, 0, 3, bits=True)
+        assert float(f.abs().max()) == 0.0 and int(bits.abs().max()) == 0
+        # the batched path writes its outputs too: empty images, no segments
+        field = torch.full((3, grid.H, grid.W), 7.0, dtype=f.dtype, device="cuda")
+        bits = torch.full((3, grid.H, (grid.W + 31) // 32), -1, dtype=torch.int32, device="cuda")
+        offs = torch.full((4,), -1, dtype=torch.int64, device="cuda")
+        st, total, _, offs = api.slice_batch(b, 0, 3, field=field, bits=bits, capacity=4,
+                                             segs=torch.empty((4, 4), device="cuda"),
+                                             offsets=offs)
+        assert st == N.LSL_OK and total == 0
+        assert float(field.abs().max()) == 0.0 and int(bits.abs().max()) == 0
+        assert offs.tolist() == [0, 0, 0, 0]
 
 
 @pytest.mark.parametrize("bad", ["index", "negative", "nan_weight", "nan_node"])
