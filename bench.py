@@ -141,10 +141,19 @@ def main():
                                         segs=segs, offsets=offsets)
         return bb
 
+    if target is not None:
+        # loss constants: L = sum (sigmoid((g - C)/tau) - target)^2
+        c0 = torch.tensor(-lat.C / tau, dtype=dtype, device=dev)
+        tneg = target * (-2.0 / tau)
+
     def fwd_bwd_step():
         bb = fwd_step()
-        occ = torch.sigmoid((field - lat.C) / tau)
-        G = (2.0 / tau) * (occ - target) * occ * (1.0 - occ)
+        # dL/dg = (2/tau) (s - target) s (1 - s), s = sigmoid((g - C)/tau), in
+        # five elementwise passes
+        s_ = torch.add(c0, field, alpha=1.0 / tau).sigmoid_()
+        w_ = torch.addcmul(s_, s_, s_, value=-1.0)
+        G = torch.add(tneg, s_, alpha=2.0 / tau).mul_(w_)
+        del s_, w_
         api.slice_field_backward(bb, 0, S, G, grad_weight, grad_nodes)
         return bb
 

@@ -26,15 +26,17 @@
 //
 // Around the 8x8 block centre c, q_perp = m - d + (d.u) u with m = F - c the
 // offset of the foot F of c (uniform per strut and plane) and d = p - c the
-// pixel's offset, so sum G K q_perp = sum G K m - d sum G K + u sum G K (d.u):
-// each pair adds to thirteen registers without forming q_perp.
+// pixel's offset (the same in every plane).  Within a slab m is affine in the
+// plane index k, m_k = m_0 + k dm, so over the slab's planes
+//   sum G K q_perp = (m_0 - d + (d.u) u) sum G K + dm sum k G K
+// and likewise for J: each (pixel, strut, plane) adds to seven registers.
 //
 // Work split.  One wave takes one (tile, slab) bucket and walks the tile's
 // 8x8 blocks in a fixed order.  For 32 list entries at a time it stages, per
 // block and plane, the same block-centre quantities as the forward pass
 // (m and tc), compacts the struts that reach the block in any
 // plane of the slab, and then for each such strut loops over only the planes
-// it reaches: every lane adds its pixel's contribution to thirteen registers,
+// it reaches: every lane adds its pixel's contribution to seven registers,
 // the wave sums them once per (strut, block), and one lane adds the sums into
 // the entry's LDS slot.  The slots are written once per bucket entry, at the
 // entry's emission index, so each (slab, tile, strut) pair gets exactly one
@@ -50,11 +52,12 @@ namespace {
 constexpr int kChunk = 32;      // bucket entries staged at a time
 constexpr int kParts = 9;       // pixel sums per (strut, bucket)
 
-// per (strut, plane): m = F - c, H0 = R^2 - |m|^2, and the ends -tc, L - tc
+// per (strut, plane): the in-plane part of m = F - c, H0 = R^2 - |m|^2, and
+// the ends -tc, L - tc
 template <typename T>
 struct alignas(8) BPlane {
-    T mx, my, mz, H0;
-    T ntc, nbtc;
+    T mx, my, H0, ntc;
+    T nbtc, pad;
 };
 
 template <typename T>
@@ -183,6 +186,7 @@ template <typename T, int SZ>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_backward(BackArgs a, uint32_t n_items) {
     // compacted list of the struts that reach the current block
     __shared__ T bs_ux[kChunk], bs_uy[kChunk], bs_uz[kChunk];
+    __shared__ T bs_m0[3][kChunk], bs_dm[3][kChunk];   // m at the slab's first plane, step per plane
     __shared__ uint32_t bs_planes[kChunk], bs_pos[kChunk];
     __shared__ BPlane<T> bp[kChunk][SZ];
     __shared__ T slot[kChunk][kParts];
@@ -272,7 +276,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
                         BPlane<T> P;
                         P.mx = (T)mx;
                         P.my = (T)my;
-                        P.mz = (T)mz;
                         P.H0 = (T)(R2 - m2);
                         P.ntc = (T)(-tc);
                         P.nbtc = (T)(L - tc);
@@ -289,6 +292,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
                 bs_uz[q] = (T)uz;
                 bs_planes[q] = planes;
                 bs_pos[q] = (uint32_t)lane;
+                // m is affine in the plane index: m_k = m_0 + k dm
+                const double wz0 = a.z0 + ((double)kb + 0.5) * a.dz - az;
+                const double tc0 = fma(wz0, uz, txy);
+                const double dtc = a.dz * uz;
+                bs_m0[0][q] = (T)fma(tc0, ux, -wx);
+                bs_m0[1][q] = (T)fma(tc0, uy, -wy);
+                bs_m0[2][q] = (T)fma(tc0, uz, -wz0);
+                bs_dm[0][q] = (T)(dtc * ux);
+                bs_dm[1][q] = (T)(dtc * uy);
+                bs_dm[2][q] = (T)fma(dtc, uz, -a.dz);
             }
             __builtin_amdgcn_wave_barrier();
             const int n = __popcll(mask);
@@ -296,8 +309,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
                 const T bux = bs_ux[j], buy = bs_uy[j], buz = bs_uz[j];
                 const uint32_t bpos = bs_pos[j];
                 const uint32_t planes_s = __builtin_amdgcn_readfirstlane(bs_planes[j]);
-                T Aw = 0, Aa = 0, Ab = 0, AK = 0, AKx = 0, AKy = 0, AKz = 0, AKd = 0, AJ = 0,
-                  AJx = 0, AJy = 0, AJz = 0, AJd = 0;
+                // sums over the planes: G I, G phi(alpha), G phi(beta), G K, k G K,
+                // G J, k G J (k = plane index in the slab)
+                T Aw = 0, Aa = 0, Ab = 0, AK = 0, AKk = 0, AJ = 0, AJk = 0;
                 const T du = dfma(dX, bux, dY * buy);         // d.u: the same in every plane
                 const T dd = dfma(du, du, -d2);               // (d.u)^2 - |d|^2
 #pragma unroll
@@ -330,24 +344,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
                         const T K = dfma(T(2) * al, J, pb - pa);               // K R^4
                         const T gK = g * K, gJ = g * J;
                         AK += gK;
-                        AKx = dfma(gK, P.mx, AKx);
-                        AKy = dfma(gK, P.my, AKy);
-                        AKz = dfma(gK, P.mz, AKz);
-                        AKd = dfma(gK, du, AKd);
                         AJ += gJ;
-                        AJx = dfma(gJ, P.mx, AJx);
-                        AJy = dfma(gJ, P.my, AJy);
-                        AJz = dfma(gJ, P.mz, AJz);
-                        AJd = dfma(gJ, du, AJd);
+                        if (k > 0) {
+                            AKk = dfma(gK, T(k), AKk);
+                            AJk = dfma(gJ, T(k), AJk);
+                        }
                     }
                 }
-                // sum G K q_perp = sum G K m - d sum G K + u sum G K (d.u), d = (dX, dY, 0)
-                AKx = dfma(bux, AKd, dfma(-dX, AK, AKx));
-                AKy = dfma(buy, AKd, dfma(-dY, AK, AKy));
-                AKz = dfma(buz, AKd, AKz);
-                AJx = dfma(bux, AJd, dfma(-dX, AJ, AJx));
-                AJy = dfma(buy, AJd, dfma(-dY, AJ, AJy));
-                AJz = dfma(buz, AJd, AJz);
+                // sum G K q_perp over the planes, q_perp = m_k - d + (d.u) u and
+                // m_k = m_0 + k dm:  (m_0 - d + (d.u) u) sum G K + dm sum k G K
+                const T qx = dfma(du, bux, bs_m0[0][j] - dX), qy = dfma(du, buy, bs_m0[1][j] - dY),
+                        qz = dfma(du, buz, bs_m0[2][j]);
+                const T dmx = bs_dm[0][j], dmy = bs_dm[1][j], dmz = bs_dm[2][j];
+                const T AKx = dfma(qx, AK, dmx * AKk), AKy = dfma(qy, AK, dmy * AKk),
+                        AKz = dfma(qz, AK, dmz * AKk);
+                const T AJx = dfma(qx, AJ, dmx * AJk), AJy = dfma(qy, AJ, dmy * AJk),
+                        AJz = dfma(qz, AJ, dmz * AJk);
                 const T v[9] = {Aw, Aa, Ab, AKx, AKy, AKz, AJx, AJy, AJz};
                 deposit(slot[bpos], v, lane, own);
                 __builtin_amdgcn_wave_barrier();
