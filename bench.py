@@ -45,10 +45,40 @@ def parse():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--slab", type=int, default=0)
+    ap.add_argument("--peak-probe", action="store_true",
+                    help="only run the vector-ALU throughput probes and print them")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (x -> -x), the reference "
                          "for scaling the HBM byte counters")
     return ap.parse_args()
+
+
+def peak_probe():
+    """Measured vector-ALU ceilings beside the published peak: FP32 FMA with
+    register operands (VOP2) and with scalar operands (VOP3), FP32 sqrt,
+    FP64 FMA, and the field kernel's per-pair sequence on staged data."""
+    from paper_2101_05031_amd import api
+    names = {0: "fp32 fma, vgpr operands", 1: "fp32 fma, sgpr operands", 2: "fp32 sqrt",
+             3: "fp64 fma", 4: "field term per pair"}
+    iters = {0: 65536, 1: 65536, 2: 16384, 3: 32768, 4: 1024}
+    out = {}
+    for m in range(5):
+        api.probe_valu(m, 16)                      # warm-up
+        best = None
+        for _ in range(3):
+            r = api.probe_valu(m, iters[m])
+            best = r if best is None or r["ms"] < best["ms"] else best
+        rate = best["lane_ops"] / (best["ms"] * 1e-3)
+        rec = {"ms": best["ms"], "lane_ops_per_s": rate}
+        if m in (0, 1, 3):
+            rec["tflops"] = 2.0 * rate / 1e12
+        if m == 4:
+            rec["pairs_per_s"] = rate
+            rec["tflops_at_36_flop_per_pair"] = 36.0 * rate / 1e12
+        out[names[m]] = rec
+        print(f"[probe] {names[m]}: {rec}", file=sys.stderr, flush=True)
+    print(json.dumps({"peak_probe": out, "published_fp32_tflops": PEAK_FP32_VECTOR / 1e12}),
+          flush=True)
 
 
 def copy_calibration():
@@ -74,6 +104,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.peak_probe:
+        peak_probe()
         return
     import torch
     from paper_2101_05031_amd import api, synth

@@ -133,9 +133,18 @@ lsl_status lattice_bin(const lsl_lattice* lattice, const lsl_grid* grid,
                        const lsl_bin_params* params, lattice_bins** out,
                        void* stream);
 
-/* Frees the handle and its device memory (synchronises the device first).
- * NULL is accepted. */
+/* Frees the handle (synchronises the device first).  Its device buffers go
+ * to the library's device-memory cache, from which later handles of similar
+ * sizes take them without hipMalloc; lsl_cache_trim returns them to the
+ * device.  NULL is accepted. */
 lsl_status lattice_bins_free(lattice_bins* bins);
+
+/* Returns every cached device buffer to the device (hipFree, after
+ * synchronising each device that holds some).  *cached_bytes (host,
+ * nullable) receives the bytes the cache held.  Setting LSL_NO_CACHE=1 in
+ * the environment before the first call disables the cache: buffers are
+ * then allocated and freed directly. */
+lsl_status lsl_cache_trim(int64_t* cached_bytes);
 
 /* Sizes and memory use of a handle.  `out` is [host]. */
 lsl_status lattice_bins_info(const lattice_bins* bins, lsl_bins_info* out);
@@ -255,6 +264,26 @@ const char* lsl_status_string(lsl_status s);
 const char* lsl_last_error(void);
 /* Library version string. */
 const char* lsl_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Diagnostics: vector-ALU throughput of the GPU, the ceiling against which
+ * the field and adjoint kernels are measured.  Not part of the slicing path.
+ *
+ * lsl_probe_valu runs one probe kernel on `stream` (16 blocks of 256 threads
+ * per compute unit, `iters` iterations) and returns its duration in *ms and
+ * the lane operations it issued in *lane_ops:
+ *   mode 0  FP32 multiply-add with register operands (v_fmac_f32),
+ *           16 independent chains per lane          -> 1 lane-op = 2 FLOP
+ *   mode 1  FP32 multiply-add with scalar-register operands (v_fma_f32)
+ *   mode 2  FP32 square root (v_sqrt_f32)
+ *   mode 3  FP64 multiply-add
+ *   mode 4  the field kernel's per-pair term and compensated add, from 64
+ *           staged struts in LDS                   -> 1 lane-op = 1 pair
+ * The probe allocates and frees its own small device buffers and
+ * synchronizes the stream.  LSL_EINVAL for a bad mode or iters < 1.
+ * ------------------------------------------------------------------------- */
+lsl_status lsl_probe_valu(int32_t mode, int32_t iters, float* ms, double* lane_ops,
+                          void* stream);
 
 #ifdef __cplusplus
 }

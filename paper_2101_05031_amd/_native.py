@@ -3,8 +3,8 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import (POINTER, Structure, c_char_p, c_double, c_int32, c_int64, c_uint8,
-                    c_uint32, c_void_p)
+from ctypes import (POINTER, Structure, c_char_p, c_double, c_float, c_int32, c_int64,
+                    c_uint8, c_uint32, c_void_p)
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblsl.so")
 
@@ -49,6 +49,7 @@ SIGNATURES = {
     "lattice_bin": (c_int32, [POINTER(LslLattice), POINTER(LslGrid), POINTER(LslBinParams),
                               POINTER(c_void_p), c_void_p]),
     "lattice_bins_free": (c_int32, [c_void_p]),
+    "lsl_cache_trim": (c_int32, [POINTER(c_int64)]),
     "lattice_bins_info": (c_int32, [c_void_p, POINTER(LslBinsInfo)]),
     "lattice_bins_group": (c_int32, [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32),
                                      POINTER(c_int64)]),
@@ -67,6 +68,8 @@ SIGNATURES = {
     "lsl_status_string": (c_char_p, [c_int32]),
     "lsl_last_error": (c_char_p, []),
     "lsl_version": (c_char_p, []),
+    "lsl_probe_valu": (c_int32, [c_int32, c_int32, POINTER(c_float), POINTER(c_double),
+                                 c_void_p]),
 }
 
 _lib = None

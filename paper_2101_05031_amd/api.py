@@ -4,7 +4,7 @@ native library's kernels."""
 from __future__ import annotations
 
 import ctypes
-from ctypes import byref, c_int32, c_int64, c_void_p
+from ctypes import byref, c_double, c_float, c_int32, c_int64, c_void_p
 
 import torch
 
@@ -195,3 +195,21 @@ def slice_autotune(nodes, edges, weight, R: float, C: float, grid, cache_path: s
     N.check(N.lib().slice_autotune(byref(L), byref(g), byref(p), path, _stream(stream)),
             "slice_autotune")
     return {"tile": p.tile, "slab": p.slab}
+
+
+def probe_valu(mode: int, iters: int = 4096, stream=None) -> dict:
+    """Vector-ALU throughput probe (diagnostics): duration and lane
+    operations of one probe kernel; see lsl_probe_valu."""
+    ms = c_float()
+    ops = c_double()
+    N.check(N.lib().lsl_probe_valu(int(mode), int(iters), byref(ms), byref(ops),
+                                   _stream(stream)), "lsl_probe_valu")
+    return {"mode": int(mode), "ms": ms.value, "lane_ops": ops.value}
+
+
+def cache_trim() -> int:
+    """Return the library's cached device buffers to the device; returns the
+    bytes the cache held."""
+    n = c_int64()
+    N.check(N.lib().lsl_cache_trim(byref(n)), "lsl_cache_trim")
+    return n.value

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblsl.so")
 SOURCES = ["primitives.hip", "prep.hip", "bin.hip", "field.hip", "contours.hip",
-           "backward.hip", "batch.hip", "api.cpp", "autotune.cpp"]
+           "backward.hip", "batch.hip", "probe.hip", "api.cpp", "autotune.cpp"]
 ARCH = os.environ.get("LSL_OFFLOAD_ARCH", "gfx950")
 
 
@@ -45,7 +45,7 @@ def _compile(src: str, out_dir: str) -> str:
 
 
 KERNEL_SOURCES = {
-    "field": ["field_block.hpp", "batch.hip", "common.hpp"],
+    "field": ["field_block.hpp", "batch.hip", "common.hpp", "kernels.hpp"],
     "backward": ["backward.hip", "common.hpp"],
 }
 

@@ -5,8 +5,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,6 +20,97 @@ namespace lsl {
 static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
 const char* last_error() { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// Device memory cache.  Binning a lattice of a million struts takes ~7 GB in
+// a few dozen buffers; hipMalloc / hipFree of that much costs milliseconds
+// per handle, so freed buffers are kept per device in size classes (eight
+// per power of two, at most 1/8 over the request) and handed to the next
+// request of the same class.  Buffers only return to the cache once the
+// device is idle (handles synchronize before releasing), so reuse never
+// races with work still in flight.  lsl_cache_trim gives the memory back;
+// LSL_NO_CACHE=1 in the environment turns the cache off.
+// ---------------------------------------------------------------------------
+class DeviceCache {
+  public:
+    static DeviceCache& get() {
+        static DeviceCache* c = new DeviceCache();   // never destroyed: no teardown at exit
+        return *c;
+    }
+    static size_t size_class(size_t bytes) {
+        bytes = std::max<size_t>(bytes, 256);
+        size_t p = 1;
+        while (p <= bytes / 2) p <<= 1;              // largest power of two <= bytes
+        const size_t step = std::max<size_t>(256, p / 8);
+        return (bytes + step - 1) / step * step;
+    }
+    hipError_t alloc(void** p, size_t bytes) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        if (enabled_) {
+            std::lock_guard<std::mutex> lk(mu_);
+            auto it = free_.find(Key{dev, bytes});
+            if (it != free_.end() && !it->second.empty()) {
+                *p = it->second.back();
+                it->second.pop_back();
+                cached_ -= bytes;
+                return hipSuccess;
+            }
+        }
+        e = hipMalloc(p, bytes);
+        if (e == hipErrorOutOfMemory && enabled_) {
+            // give back what the cache holds and try once more
+            trim();
+            hipGetLastError();
+            e = hipMalloc(p, bytes);
+        }
+        return e;
+    }
+    void release(void* p, size_t bytes) {
+        if (!p) return;
+        int dev = 0;
+        if (!enabled_ || hipGetDevice(&dev) != hipSuccess) {
+            hipFree(p);
+            return;
+        }
+        std::lock_guard<std::mutex> lk(mu_);
+        free_[Key{dev, bytes}].push_back(p);
+        cached_ += bytes;
+    }
+    void trim() {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (free_.empty()) return;
+        int cur = 0;
+        hipGetDevice(&cur);
+        for (auto& kv : free_) {
+            hipSetDevice(kv.first.dev);
+            hipDeviceSynchronize();
+            for (void* p : kv.second) hipFree(p);
+        }
+        free_.clear();
+        cached_ = 0;
+        hipSetDevice(cur);
+    }
+    size_t cached() const { return cached_; }
+
+  private:
+    DeviceCache() {
+        const char* v = std::getenv("LSL_NO_CACHE");
+        enabled_ = !(v && *v && std::strcmp(v, "0") != 0);
+    }
+    struct Key {
+        int dev;
+        size_t bytes;
+        bool operator<(const Key& o) const {
+            return dev != o.dev ? dev < o.dev : bytes < o.bytes;
+        }
+    };
+    std::mutex mu_;
+    std::map<Key, std::vector<void*>> free_;
+    size_t cached_ = 0;
+    bool enabled_ = true;
+};
 
 }  // namespace lsl
 
@@ -100,14 +194,13 @@ struct lattice_bins {
     ~lattice_bins() {
         hipDeviceSynchronize();
         drop_graphs();
-        for (auto& a : allocs) hipFree(a.first);
+        for (auto& a : allocs) DeviceCache::get().release(a.first, a.second);
     }
 
     lsl_status alloc(void** p, size_t bytes) {
         *p = nullptr;
-        if (bytes == 0) bytes = 16;
-        bytes = (bytes + 255) & ~size_t(255);
-        hipError_t e = hipMalloc(p, bytes);
+        bytes = DeviceCache::size_class(bytes);
+        hipError_t e = DeviceCache::get().alloc(p, bytes);
         if (e != hipSuccess) {
             hipGetLastError();
             *p = nullptr;
@@ -124,11 +217,12 @@ struct lattice_bins {
     lsl_status alloc_t(T** p, size_t n) {
         return alloc((void**)p, n * sizeof(T));
     }
+    // callers release only buffers no queued work still uses
     void release(void* p) {
         if (!p) return;
         for (size_t i = 0; i < allocs.size(); ++i)
             if (allocs[i].first == p) {
-                hipFree(p);
+                DeviceCache::get().release(p, allocs[i].second);
                 dev_bytes -= (int64_t)allocs[i].second;
                 allocs.erase(allocs.begin() + (long)i);
                 return;
@@ -595,6 +689,12 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
 
 lsl_status lattice_bins_free(lattice_bins* b) {
     delete b;
+    return LSL_OK;
+}
+
+lsl_status lsl_cache_trim(int64_t* cached_bytes) {
+    if (cached_bytes) *cached_bytes = (int64_t)DeviceCache::get().cached();
+    DeviceCache::get().trim();
     return LSL_OK;
 }
 

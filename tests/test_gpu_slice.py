@@ -277,3 +277,24 @@ def test_full_size_sampled(name, k0, nk):
              (r["ty1"][order] >= ty) & (r["tx0"][order] <= tx) & (r["tx1"][order] >= tx))
         key = ((s - s0) * nty + ty) * ntx + tx
         assert np.array_equal(ids[off[key]:off[key + 1]], order[m])
+
+
+def test_device_cache_reuse_and_trim():
+    """Freed handles leave their buffers in the library's cache; new handles
+    reuse them (dirty) with identical results; trimming empties the cache."""
+    import gc
+    lat, grid = small_kuhn()
+    b = bin_lattice(lat, grid)
+    f0 = api.slice_field(b, 0, grid.n_slices).cpu().numpy()
+    del b
+    gc.collect()
+    b = bin_lattice(lat, grid)
+    f1 = api.slice_field(b, 0, grid.n_slices).cpu().numpy()
+    assert np.array_equal(f0.view(np.uint32), f1.view(np.uint32))
+    del b
+    gc.collect()
+    assert api.cache_trim() > 0
+    assert api.cache_trim() == 0
+    b = bin_lattice(lat, grid)
+    f2 = api.slice_field(b, 0, grid.n_slices).cpu().numpy()
+    assert np.array_equal(f0.view(np.uint32), f2.view(np.uint32))
