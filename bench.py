@@ -211,6 +211,16 @@ def main():
     if not args.no_backward:
         t_fb, _ = timed(fwd_bwd_step, args.steps)
 
+    # the field kernel against its own per-pair sequence on staged data
+    # (lsl_probe_valu mode 4), measured here on the same GPU
+    inner = None
+    if field_ms > 0:
+        best = min((api.probe_valu(4, 256) for _ in range(3)), key=lambda r: r["ms"])
+        ceiling = best["lane_ops"] / (best["ms"] * 1e-3)
+        evaluated = stats["candidates"] / (field_ms * 1e-3)
+        inner = {"evaluated_pairs_per_s": evaluated, "probe_pairs_per_s": ceiling,
+                 "frac": evaluated / ceiling,
+                 "useful_fraction": stats["useful"] / max(stats["candidates"], 1)}
     useful = stats["useful"]
     value = useful / t_fwd
     field_s = field_ms * 1e-3
@@ -267,6 +277,7 @@ def main():
             "traffic": traffic,
             "field_ms_per_launch": field_ms,
             "flop_per_useful_pair": FLOP_PER_USEFUL_PAIR,
+            "inner_loop": inner,
         },
     }
     if not args.no_cpu_baseline:
@@ -276,19 +287,20 @@ def main():
 
 def cpu_baseline(lat, grid):
     """The FP64 oracle, as it stands, on a bounded sample of the workload: a
-    1024 x 1024 pixel window of the middle plane (one core)."""
+    1536 x 1536 pixel window of the middle plane (one core)."""
     import copy
 
     from oracle import field as OF
     from oracle import slicer as OS
     k = grid.n_slices // 2
     sub = copy.copy(grid)
-    i0 = (grid.W - 1024) // 2 if grid.W > 1024 else 0
-    j0 = (grid.H - 1024) // 2 if grid.H > 1024 else 0
+    side = 1536
+    i0 = (grid.W - side) // 2 if grid.W > side else 0
+    j0 = (grid.H - side) // 2 if grid.H > side else 0
     sub.x0 = grid.x0 + i0 * grid.dx
     sub.y0 = grid.y0 + j0 * grid.dy
-    sub.W = min(1024, grid.W)
-    sub.H = min(1024, grid.H)
+    sub.W = min(side, grid.W)
+    sub.H = min(side, grid.H)
     count = [0]
     orig = OF.strut_integral
 
