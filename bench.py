@@ -39,7 +39,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="M1", choices=["M1", "A2", "D4", "P1", "B3"])
+    ap.add_argument("--workload", default="M1", choices=["M1", "A2", "D4", "P1", "B3", "S5"])
+    ap.add_argument("--no-field", action="store_true",
+                    help="write bits and segments only (automatic when the field buffer "
+                         "would exceed 48 GB); no backward step")
     ap.add_argument("--slices", type=int, default=0, help="limit planes (0 = all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
@@ -128,13 +131,26 @@ def main():
     print(f"[bench] workload {args.workload}: E={lat.n_edges} N={lat.n_nodes} "
           f"{S} planes of {W}x{H}", file=sys.stderr, flush=True)
 
-    field = torch.empty((S, H, W), dtype=dtype, device=dev)
+    esize = 8 if dtype == torch.float64 else 4
+    keep_field = not args.no_field and S * H * W * esize <= 48e9
+    if not keep_field:
+        args.no_backward = True
+    field = torch.empty((S, H, W), dtype=dtype, device=dev) if keep_field else None
     bits = torch.empty((S, H, (W + 31) // 32), dtype=torch.int32, device=dev)
     offsets = torch.empty(S + 1, dtype=torch.int64, device=dev)
 
+    # tile edge chosen by the autotuner (binning time + field time on sampled
+    # plane windows); the slab stays at 8 planes unless given, since the
+    # adjoint keeps one gradient value per plane of the slab in registers
+    tile, slab = args.tile, args.slab
+    autotuned = False
+    if not tile:
+        p = api.slice_autotune(nodes, edges, weight, lat.R, lat.C, grid, slab=slab or 8)
+        tile, slab, autotuned = p["tile"], p["slab"], True
+        print(f"[bench] autotuned tile {tile}, slab {slab}", file=sys.stderr, flush=True)
+
     def binit():
-        return api.lattice_bin(nodes, edges, weight, lat.R, lat.C, grid, tile=args.tile,
-                               slab=args.slab)
+        return api.lattice_bin(nodes, edges, weight, lat.R, lat.C, grid, tile=tile, slab=slab)
 
     # size the segment buffer once (untimed)
     b = binit()
@@ -260,10 +276,14 @@ def main():
                 "A2": "Kuhn 40^3 tetrahedral lattice, 462,520 struts, 1000 planes, 2048x2048",
                 "D4": "Kuhn 25^3 tetrahedral lattice, 115,075 struts, 64 planes, 1024x1024",
                 "P1": "BCC 4^3 cells, 812 struts, 50 planes, 256x256, float64",
-                "B3": "Kuhn 110^3, 9,426,230 struts, 2000 planes, 4096x4096",
+                "B3": "Kuhn 110^3, 9,426,230 struts (8-blob radii, voids absent), 2000 planes "
+                      "at 0.05 mm, 4096x4096",
+                "S5": "Kuhn 243^3 in a 200 mm cube, 100,974,519 struts, 4000 planes at 0.05 mm, "
+                      "8192x8192",
             }[args.workload],
             "n_struts": lat.n_edges, "planes": S, "grid": [W, H],
-            "tile": info["tile"], "slab": info["slab"],
+            "tile": info["tile"], "slab": info["slab"], "autotuned": autotuned,
+            "field_output": keep_field, "peak_device_bytes": info["peak_device_bytes"],
             "useful_pairs": useful, "candidate_pairs": stats["candidates"],
             "segments": total,
         },
