@@ -105,3 +105,51 @@ def test_autotune_choice_and_cache(tmp_path):
     f0 = api.slice_field(b0, 0, grid.n_slices)
     f1 = api.slice_field(b1, 0, grid.n_slices)
     assert torch.equal(f0.view(torch.int32), f1.view(torch.int32))
+
+
+@pytest.mark.parametrize("name,k0,nk", [("B3", 1000, 8), ("S5", 2000, 4)])
+def test_full_size_batched_sampled(name, k0, nk):
+    """The 9.4M- and 100M-strut workloads at full size, in the launch
+    configuration the benchmark times (autotuned tile, slabs of 8 planes,
+    persistent graph path): sampled pixels against the oracle one by one, the
+    bits against the field, and one plane's segments exactly against marching
+    squares of the GPU's own image."""
+    from oracle import field as OF
+    lat, grid = synth.config(name)
+    print(f"full size {name}: E={lat.n_edges}", flush=True)
+    n, e, w = to_dev(lat)
+    p = api.slice_autotune(n, e, w, lat.R, lat.C, grid, slab=8)
+    b = api.lattice_bin(n, e, w, lat.R, lat.C, grid, tile=p["tile"], slab=p["slab"])
+    print(f"  tile {p['tile']} slab {p['slab']}: {b.info()['n_groups']} slab groups", flush=True)
+    field = torch.empty((nk, grid.H, grid.W), dtype=torch.float32, device="cuda")
+    bits = torch.empty((nk, grid.H, (grid.W + 31) // 32), dtype=torch.int32, device="cuda")
+    st, total, _, _ = api.slice_batch(b, k0, nk, field=field, bits=bits, capacity=0)
+    assert st == N.LSL_ECAPACITY or total == 0
+    st, total2, segs, offs = api.slice_batch(b, k0, nk, field=field, bits=bits,
+                                             capacity=total)
+    assert st == N.LSL_OK and total2 == total > 0
+    f = field.cpu().numpy()
+    # sampled pixels, one by one
+    rng = np.random.default_rng(11)
+    zlo, zhi = OS.strut_z_range(lat.nodes, lat.edges)
+    act = {k: OS.active_set(zlo, zhi, lat.R, float(grid.slice_z(k))) for k in range(k0, k0 + nk)}
+    worst, n_in = 0.0, 0
+    for _ in range(60):
+        k = int(rng.integers(k0, k0 + nk))
+        i = int(rng.integers(0, grid.W))
+        j = int(rng.integers(0, grid.H))
+        q = OS.slice_points(grid, k, np.array([i]), np.array([j]))[0]
+        ref = OF.field_at_point(q, lat.nodes, lat.edges, lat.weight, lat.R, act[k])
+        worst = max(worst, abs(float(f[k - k0, j, i]) - ref) / max(abs(ref), lat.C))
+        n_in += ref > 0
+    print(f"  sampled field: worst scaled error {worst:.2e}", flush=True)
+    assert worst <= 1e-5 and n_in > 10
+    # bits of every plane, and one plane's segments
+    bb = bits.cpu().numpy().view(np.uint8)
+    img = np.unpackbits(bb, axis=-1, bitorder="little")[..., :grid.W].astype(bool)
+    assert np.array_equal(img, f >= lat.C)
+    offs = offs.cpu().numpy()
+    k = nk // 2
+    mine = OC.segments(img[k])
+    got = segs[offs[k]:offs[k + 1]].cpu().numpy().astype(np.float64)
+    assert np.array_equal(got, mine)
