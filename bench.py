@@ -184,8 +184,19 @@ def main():
     grad_weight = torch.empty(lat.n_edges, dtype=dtype, device=dev)
     grad_nodes = torch.empty((lat.n_nodes, 3), dtype=dtype, device=dev)
 
+    stage_acc = {"lattice_bin": 0.0, "group_bin": 0.0, "queue": 0.0, "field": 0.0,
+                 "contours": 0.0, "n": 0}
+
+    bin_events = []
+
     def fwd_step():
+        # lattice_bin's device work, some of it still queued when it returns,
+        # between two events on its stream (read after the step's last sync)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         bb = binit()
+        e1.record()
+        bin_events.append((e0, e1))
         st, tot, _, _ = api.slice_batch(bb, 0, S, field=field, bits=bits, capacity=capacity,
                                         segs=segs, offsets=offsets)
         return bb
@@ -210,9 +221,20 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         field_ms = 0.0
+        for key in stage_acc:
+            stage_acc[key] = 0.0 if key != "n" else 0
+        bin_events.clear()
         for i in range(k):
             bb = fn()
-            field_ms += bb.info()["last_field_ms"]
+            e0, e1 = bin_events.pop()
+            stage_acc["lattice_bin"] += e0.elapsed_time(e1)      # slice_batch synchronised
+            inf = bb.info()
+            field_ms += inf["last_field_ms"]
+            stage_acc["group_bin"] += inf["last_group_bin_ms"]
+            stage_acc["queue"] += inf["last_queue_ms"]
+            stage_acc["field"] += inf["last_field_ms"]
+            stage_acc["contours"] += inf["last_contour_ms"]
+            stage_acc["n"] += 1
             print(f"[bench] step {i + 1}/{k} done", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / k, field_ms / k
@@ -223,6 +245,11 @@ def main():
             fwd_bwd_step()
         print(f"[bench] warmup {i + 1}/{args.warmup}", file=sys.stderr, flush=True)
     t_fwd, field_ms = timed(fwd_step, args.steps)
+    n_slabs = (S + info["slab"] - 1) // info["slab"]
+    stages = {key: v / max(stage_acc["n"], 1) for key, v in stage_acc.items() if key != "n"}
+    stages = {"ms_per_step": stages,
+              "ms_per_slab": {key: v / n_slabs for key, v in stages.items()},
+              "n_slabs": n_slabs}
     t_fb = None
     if not args.no_backward:
         t_fb, _ = timed(fwd_bwd_step, args.steps)
@@ -264,6 +291,7 @@ def main():
         "fwd_bwd_ratio": None if t_fb is None else t_fb / t_fwd,
         "slices_per_s": S / t_fwd,
         "executed_evals_per_s": stats["candidates"] / t_fwd,
+        "stages": stages,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -294,6 +322,10 @@ def main():
             "peak": PEAK_FP32_VECTOR / 1e12,
             "unit": "TFLOP/s",
             "frac": None if achieved is None else achieved / PEAK_FP32_VECTOR,
+            # the same with every evaluated pair counted (counter view)
+            "frac_executed": (None if field_s <= 0 else
+                              stats["candidates"] * FLOP_PER_USEFUL_PAIR / field_s /
+                              PEAK_FP32_VECTOR),
             "traffic": traffic,
             "field_ms_per_launch": field_ms,
             "flop_per_useful_pair": FLOP_PER_USEFUL_PAIR,

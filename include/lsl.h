@@ -102,6 +102,9 @@ typedef struct lsl_bins_info {
     double last_field_ms;   /* device time of the persistent field launches of
                                the last slice_batch call (HIP events around the
                                kernel on its stream); -1 if unavailable          */
+    double last_group_bin_ms;   /* the same call's other stages, summed over its */
+    double last_queue_ms;       /* slab groups: binning of groups not resident,  */
+    double last_contour_ms;     /* work-queue build, binary image + contours     */
 } lsl_bins_info;
 
 /* ---------------------------------------------------------------------------

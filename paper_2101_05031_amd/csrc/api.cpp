@@ -185,15 +185,24 @@ struct lattice_bins {
     struct GraphEntry {
         std::vector<unsigned char> key;
         hipGraphExec_t exec[3];     // queue build | persistent field | image + contours
-        hipEvent_t e0, e1;          // recorded on the caller's stream around exec[1]
     };
-    double last_field_ms = -1.0;
+    // per slab group of a slice_batch call, on the caller's stream: before and
+    // after binning the group, after each of the three graphs
+    struct StageEvents {
+        hipEvent_t ev[5];
+    };
+    std::vector<StageEvents> stage_events;
+    double last_field_ms = -1.0, last_group_bin_ms = -1.0, last_queue_ms = -1.0,
+           last_contour_ms = -1.0;
     bool queue_in_alt = false;      // the sorted work queue is in the alternate buffer
     std::vector<GraphEntry> graphs;
 
     ~lattice_bins() {
         hipDeviceSynchronize();
         drop_graphs();
+        for (auto& se : stage_events)
+            for (auto& e : se.ev)
+                if (e) hipEventDestroy(e);
         for (auto& a : allocs) DeviceCache::get().release(a.first, a.second);
     }
 
@@ -230,12 +239,9 @@ struct lattice_bins {
     }
     size_t esize() const { return dtype == LSL_F64 ? 8 : 4; }
     void drop_graphs() {
-        for (auto& g : graphs) {
+        for (auto& g : graphs)
             for (auto& x : g.exec)
                 if (x) hipGraphExecDestroy(x);
-            if (g.e0) hipEventDestroy(g.e0);
-            if (g.e1) hipEventDestroy(g.e1);
-        }
         graphs.clear();
     }
 };
@@ -716,6 +722,9 @@ lsl_status lattice_bins_info(const lattice_bins* b, lsl_bins_info* o) {
     o->n_groups = (int32_t)b->groups.size();
     o->current_group = b->cur_group;
     o->last_field_ms = b->last_field_ms;
+    o->last_group_bin_ms = b->last_group_bin_ms;
+    o->last_queue_ms = b->last_queue_ms;
+    o->last_contour_ms = b->last_contour_ms;
     return LSL_OK;
 }
 
@@ -1102,12 +1111,21 @@ lsl_status slice_batch(lattice_bins* b, int32_t k0, int32_t nk, void* field, uin
         LSL_TRY(fill_bytes0(offsets, (size_t)(nk + 1) * 8, st));
         if (total) *total = 0;
         LSL_HIP(hipStreamSynchronize(st));
-        b->last_field_ms = 0.0;
+        b->last_field_ms = b->last_group_bin_ms = b->last_queue_ms = b->last_contour_ms = 0.0;
         return LSL_OK;
     }
     hipStream_t cap = nullptr;
+    size_t n_call_groups = 0;
     LSL_TRY(for_groups(b, k0, nk, [&](int g, int s_lo, int s_hi) -> lsl_status {
+        if (b->stage_events.size() <= n_call_groups) {
+            lattice_bins::StageEvents se{};
+            for (auto& e : se.ev) LSL_HIP(hipEventCreate(&e));
+            b->stage_events.push_back(se);
+        }
+        hipEvent_t* ev = b->stage_events[n_call_groups++].ev;
+        LSL_HIP(hipEventRecord(ev[0], st));
         LSL_TRY(ensure_group(b, g, st));
+        LSL_HIP(hipEventRecord(ev[1], st));
         BatchKey key{g, k0, nk, 0, field, bits, segs, offsets, capacity};
         std::vector<unsigned char> kb((unsigned char*)&key, (unsigned char*)&key + sizeof(key));
         lattice_bins::GraphEntry* ent = nullptr;
@@ -1129,40 +1147,40 @@ lsl_status slice_batch(lattice_bins* b, int32_t k0, int32_t nk, void* field, uin
                     return cs;
                 }
             }
-            LSL_HIP(hipEventCreate(&ne.e0));
-            LSL_HIP(hipEventCreate(&ne.e1));
             b->graphs.push_back(ne);
             ent = &b->graphs.back();
+            // capturing took host time: restart the group's binning stage here
+            LSL_HIP(hipEventRecord(ev[1], st));
         }
         LSL_HIP(hipGraphLaunch(ent->exec[0], st));
-        LSL_HIP(hipEventRecord(ent->e0, st));
+        LSL_HIP(hipEventRecord(ev[2], st));
         LSL_HIP(hipGraphLaunch(ent->exec[1], st));
-        LSL_HIP(hipEventRecord(ent->e1, st));
+        LSL_HIP(hipEventRecord(ev[3], st));
         LSL_HIP(hipGraphLaunch(ent->exec[2], st));
+        LSL_HIP(hipEventRecord(ev[4], st));
         return LSL_OK;
     }));
     if (cap) hipStreamDestroy(cap);
     unsigned long long tot = 0;
     LSL_HIP(hipMemcpyAsync(&tot, base, 8, hipMemcpyDeviceToHost, st));
     LSL_HIP(hipStreamSynchronize(st));
-    // field time of this call: the launched graphs' event pairs
-    b->last_field_ms = 0.0;
-    LSL_TRY(for_groups(b, k0, nk, [&](int g, int, int) -> lsl_status {
-        BatchKey key{g, k0, nk, 0, field, bits, segs, offsets, capacity};
-        std::vector<unsigned char> kb((unsigned char*)&key, (unsigned char*)&key + sizeof(key));
-        for (auto& ge : b->graphs)
-            if (ge.key == kb) {
-                float ms = 0.0f;
-                if (hipEventElapsedTime(&ms, ge.e0, ge.e1) == hipSuccess) {
-                    b->last_field_ms += ms;
-                } else {
-                    hipGetLastError();
-                    b->last_field_ms = -1e30;
-                }
-            }
-        return LSL_OK;
-    }));
-    if (b->last_field_ms < 0) b->last_field_ms = -1.0;
+    // stage times of this call from its event sets
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    bool ok = true;
+    for (size_t i = 0; i < n_call_groups && ok; ++i)
+        for (int q = 0; q < 4 && ok; ++q) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, b->stage_events[i].ev[q], b->stage_events[i].ev[q + 1]) ==
+                hipSuccess)
+                acc[q] += ms;
+            else
+                ok = false;
+        }
+    if (!ok) hipGetLastError();
+    b->last_group_bin_ms = ok ? acc[0] : -1.0;
+    b->last_queue_ms = ok ? acc[1] : -1.0;
+    b->last_field_ms = ok ? acc[2] : -1.0;
+    b->last_contour_ms = ok ? acc[3] : -1.0;
     if (total) *total = (int64_t)tot;
     if ((int64_t)tot > capacity) {
         set_error("slice_batch: " + std::to_string(tot) + " segments exceed capacity " +

@@ -49,7 +49,8 @@ def test_batch_equals_plain_path(max_pairs):
         assert torch.equal(offs, roff)
         assert torch.equal(segs[:total], rsegs)
     info = b.info()
-    assert info["last_field_ms"] > 0
+    assert info["last_field_ms"] > 0 and info["last_contour_ms"] > 0
+    assert info["last_queue_ms"] >= 0 and info["last_group_bin_ms"] >= 0
 
 
 def test_batch_without_field_buffer_and_capacity():
