@@ -127,8 +127,9 @@ typedef struct lsl_bins_info {
  * [i0/tile, i1/tile] x [j0/tile, j1/tile].  A bucket (slab, tile_y, tile_x)
  * lists the struts covering it in edge-list order.
  *
- * On success *out holds a new handle.  Synchronises `stream` (reads back the
- * plan).  Errors: LSL_EINVAL (bad argument, edge index out of range,
+ * On success *out holds a new handle.  Synchronises `stream` while it runs
+ * (to read back the plan); the first group's bucket lists may still be in
+ * flight on `stream` when it returns.  Errors: LSL_EINVAL (bad argument, edge index out of range,
  * negative or non-finite weight, non-finite node used by an edge),
  * LSL_ENOMEM, LSL_EDEVICE.
  * ------------------------------------------------------------------------- */
@@ -239,19 +240,21 @@ lsl_status slice_field_backward(lattice_bins* bins, int32_t k0, int32_t nk,
  * slicing time follows the number of struts meeting a plane).  Each group's
  * launch sequence is captured once into a HIP graph and replayed.
  *
- * field: optional [nk][H][W]; when NULL the field lives in library scratch
- * (one group at a time).  bits, segs, offsets, case_codes: as in
- * slice_field / slice_contours.  Synchronises `stream` once at the end.
- * LSL_ECAPACITY as in slice_contours (segments beyond capacity are not
- * written; offsets are).
+ * field: optional [nk][H][W]; when NULL the field is not written (the
+ * binary image is built in library scratch, one slab group at a time).
+ * bits (optional), segs, offsets, *total: as in slice_field /
+ * slice_contours.  Synchronises `stream` once at the end.  If the total
+ * exceeds capacity, LSL_ECAPACITY is returned with offsets and *total
+ * written and only the segments that fit below capacity stored.
  * ------------------------------------------------------------------------- */
 lsl_status slice_batch(lattice_bins* bins, int32_t k0, int32_t nk, void* field,
                        uint32_t* bits, float* segs, int64_t capacity,
                        int64_t* offsets, int64_t* total, void* stream);
 
 /* ---------------------------------------------------------------------------
- * slice_autotune -- choose tile and slab sizes by timing the field on
- * sampled planes of this lattice and grid.  params is [host] in/out:
+ * slice_autotune -- choose tile and slab sizes by binning with each
+ * candidate and timing the binning plus the field on sampled plane windows
+ * of this lattice and grid (the field time scaled to all planes).  params is [host] in/out:
  * nonzero fields are kept, zero fields are filled.  cache_path (optional,
  * [host] C string) is a JSON file of earlier choices keyed by problem shape;
  * a hit skips the timing.  Synchronises `stream`.  The field values do not

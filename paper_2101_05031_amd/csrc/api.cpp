@@ -156,15 +156,17 @@ struct lattice_bins {
     uint32_t* active[2] = {nullptr, nullptr};
     uint32_t* eoff = nullptr;
     uint32_t* offsets = nullptr;
-    uint32_t* ids = nullptr;
-    uint32_t* emi = nullptr;
-    uint32_t* owner = nullptr;
+    const uint32_t* ids = nullptr;     // bucket entries (points into v0 or v1)
+    const uint32_t* skeys = nullptr;   // their sorted bucket keys (k0 or k1)
     uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
     uint32_t* tmp = nullptr;
     uint32_t* blk = nullptr;
     size_t cap_active = 0, cap_pairs = 0, cap_buckets = 0;
 
     // backward
+    uint32_t* emi = nullptr;           // [cap_pairs] entry -> emission index
+    uint32_t* inv = nullptr;           // [n_binned] inverse of the active list
+    int emi_group = -1;                // group whose emi is current
     void* partial = nullptr;
     double* acc = nullptr;
     uint32_t* node_off = nullptr;
@@ -382,9 +384,8 @@ lsl_status ensure_group(lattice_bins* b, int g, hipStream_t st) {
     gb.n_buckets = G.n_buckets;
     gb.eoff = b->eoff;
     gb.offsets = b->offsets;
-    gb.ids = b->ids;
-    gb.emi = b->emi;
-    gb.owner = b->owner;
+    gb.keys_out = &b->skeys;
+    gb.ids_out = &b->ids;
     gb.k0 = b->k0;
     gb.v0 = b->v0;
     gb.k1 = b->k1;
@@ -392,6 +393,7 @@ lsl_status ensure_group(lattice_bins* b, int g, hipStream_t st) {
     gb.tmp = b->tmp;
     gb.blk = b->blk;
     b->cur_group = -1;   // invalid until the launches below are enqueued
+    b->emi_group = -1;
     LSL_TRY(bin_group(gb, st));
     b->cur_group = g;
     b->cur_buf = out;
@@ -681,8 +683,7 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
     b->cap_buckets = max_bk;
     if ((s = b->alloc_t(&b->active[0], max_act)) || (s = b->alloc_t(&b->active[1], max_act)) ||
         (s = b->alloc_t(&b->eoff, max_act + 1)) || (s = b->alloc_t(&b->offsets, max_bk + 1)) ||
-        (s = b->alloc_t(&b->ids, max_pairs)) || (s = b->alloc_t(&b->emi, max_pairs)) ||
-        (s = b->alloc_t(&b->owner, max_pairs)) || (s = b->alloc_t(&b->k0, max_pairs)) ||
+        (s = b->alloc_t(&b->k0, max_pairs)) ||
         (s = b->alloc_t(&b->v0, max_pairs)) || (s = b->alloc_t(&b->k1, max_pairs)) ||
         (s = b->alloc_t(&b->v1, max_pairs)) ||
         (s = b->alloc_t(&b->tmp, group_tmp_elems(max_pairs, max_act, max_cand))) ||
@@ -1028,6 +1029,8 @@ lsl_status slice_field_backward(lattice_bins* b, int32_t k0, int32_t nk, const v
     hipStream_t st = S(stream);
     if (!b->acc) LSL_TRY(b->alloc_t(&b->acc, (size_t)std::max<uint32_t>(b->n_binned, 1) * 7));
     if (!b->partial) LSL_TRY(b->alloc(&b->partial, b->cap_pairs * 9 * b->esize()));
+    if (!b->emi) LSL_TRY(b->alloc_t(&b->emi, b->cap_pairs));
+    if (!b->inv) LSL_TRY(b->alloc_t(&b->inv, std::max<uint32_t>(b->n_binned, 1)));
     LSL_TRY(ensure_node_csr(b, st));
     LSL_TRY(fill_bytes0(b->acc, (size_t)std::max<uint32_t>(b->n_binned, 1) * 7 * 8, st));
     if (b->n_binned && !b->groups.empty()) {
@@ -1035,6 +1038,23 @@ lsl_status slice_field_backward(lattice_bins* b, int32_t k0, int32_t nk, const v
             LSL_TRY(ensure_group(b, g, st));
             const Group& G = b->groups[g];
             if (G.pairs == 0) return LSL_OK;
+            if (b->emi_group != g) {
+                EmiArgs ea{};
+                ea.keys = b->skeys;
+                ea.ids = b->ids;
+                ea.active = b->active[b->cur_buf];
+                ea.eoff = b->eoff;
+                ea.ranges = b->ranges;
+                ea.n_pairs = (uint32_t)G.pairs;
+                ea.n_active = G.n_active;
+                ea.sa = G.sa;
+                ea.ntx = b->ntx;
+                ea.nty = b->nty;
+                ea.inv = b->inv;
+                ea.emi = b->emi;
+                LSL_TRY(group_emi(ea, st));
+                b->emi_group = g;
+            }
             BackArgs a = back_args(b, g, k0, nk, s_lo, s_hi, grad_field);
             LSL_TRY(launch_backward(b->dtype, a, st));
             ReduceArgs r{};

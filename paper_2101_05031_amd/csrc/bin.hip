@@ -7,7 +7,8 @@
 // starts in the new slabs.  Each active strut then emits one (bucket, strut)
 // pair per (slab, tile) of its range; a stable radix sort by bucket keeps
 // edge-list order inside every bucket, and the bucket offsets are the
-// boundaries of the sorted keys.
+// boundaries of the sorted keys.  The adjoint also needs each entry's
+// emission index, which group_emi rebuilds from the key and the strut's box.
 #include "kernels.hpp"
 
 namespace lsl {
@@ -89,20 +90,22 @@ __global__ void k_pair_counts(const uint32_t* active, uint32_t n, const SRange* 
 }
 
 // One wave emits the pairs of 64 active struts, one strut at a time, the
-// wave's lanes writing consecutive pairs (coalesced stores).
+// wave's lanes writing consecutive pairs (coalesced stores).  Each pair is
+// (bucket key, the strut's edge-list position): after the stable sort the
+// values are the bucket lists themselves.
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* active, uint32_t n,
                                               const SRange* rg, int32_t sa, int32_t sb,
                                               int32_t ntx, int32_t nty, const uint32_t* eoff,
-                                              uint32_t* keys, uint32_t* vals,
-                                              uint32_t* owner, uint32_t cap) {
+                                              uint32_t* keys, uint32_t* vals, uint32_t cap) {
     const int lane = lane_id();
     const uint32_t a0 = (blockIdx.x * blockDim.x + threadIdx.x) & ~63u;
     if (a0 >= n) return;
     const uint32_t a = a0 + lane;
     SRange r{0, 0, 0, 0, 0, -1};
-    uint32_t off = 0;
+    uint32_t off = 0, pos = 0;
     if (a < n) {
-        r = rg[active[a]];
+        pos = active[a];
+        r = rg[pos];
         off = eoff[a];
     }
     const int32_t s0 = r.s0 > sa ? r.s0 : sa;
@@ -113,6 +116,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* active, uint32_t n
     for (int s = 0; s < m; ++s) {
         const uint32_t c = __shfl(cnt, s, kWave);
         const uint32_t o = __shfl(off, s, kWave);
+        const uint32_t p = __shfl(pos, s, kWave);
         const uint32_t bx = __shfl(nx, s, kWave), by = __shfl(ny, s, kWave);
         const uint32_t tx0 = __shfl((uint32_t)r.tx0, s, kWave);
         const uint32_t ty0 = __shfl((uint32_t)r.ty0, s, kWave);
@@ -125,8 +129,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* active, uint32_t n
             const uint32_t e = o + j;
             if (e >= cap) break;
             keys[e] = (sr + sl) * per_slab + (ty0 + ty) * (uint32_t)ntx + tx0 + tx;
-            vals[e] = e;
-            owner[e] = a0 + (uint32_t)s;
+            vals[e] = p;
         }
     }
 }
@@ -141,13 +144,26 @@ __global__ void k_csr_offsets(const uint32_t* keys, uint32_t n, uint32_t n_bucke
     for (uint32_t b = kprev; b <= k && b <= n_buckets; ++b) offsets[b] = i;
 }
 
-__global__ void k_ids_emi(const uint32_t* sorted_vals, const uint32_t* owner,
-                          const uint32_t* active, uint32_t n, uint32_t* ids, uint32_t* emi) {
+__global__ void k_inverse(const uint32_t* active, uint32_t n, uint32_t* inv) {
+    const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < n) inv[active[a]] = a;
+}
+
+// entry i: bucket key -> (slab, tile); its strut's emission began at eoff and
+// ran over the strut's box slab-major, then tile row, then tile column
+__global__ void k_emi(EmiArgs a) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t e = sorted_vals[i];
-    ids[i] = active[owner[e]];
-    emi[i] = e;
+    if (i >= a.n_pairs) return;
+    const uint32_t key = a.keys[i], p = a.ids[i];
+    const uint32_t per_slab = (uint32_t)a.ntx * (uint32_t)a.nty;
+    const uint32_t sl = key / per_slab, rem = key % per_slab;
+    const uint32_t ty = rem / (uint32_t)a.ntx, tx = rem % (uint32_t)a.ntx;
+    const SRange r = a.ranges[p];
+    const int32_t s0 = r.s0 > a.sa ? r.s0 : a.sa;
+    const uint32_t nx = (uint32_t)(r.tx1 - r.tx0 + 1), ny = (uint32_t)(r.ty1 - r.ty0 + 1);
+    const uint32_t local = (((uint32_t)((int32_t)sl + a.sa - s0) * ny + (ty - r.ty0)) * nx) +
+                           (tx - r.tx0);
+    a.emi[i] = a.eoff[a.inv[p]] + local;
 }
 
 int bits_for(uint32_t n) {
@@ -187,23 +203,31 @@ lsl_status bin_group(const GroupBuffers& g, hipStream_t st) {
         // 3. emit (bucket, emission index) pairs in edge-list order
         const unsigned ge = (unsigned)(((size_t)g.n_active + 255) / 256);
         k_emit<<<ge, 256, 0, st>>>(g.active, g.n_active, g.ranges, g.sa, g.sb, g.ntx, g.nty,
-                                   g.eoff, g.k0, g.v0, g.owner, g.n_pairs);
+                                   g.eoff, g.k0, g.v0, g.n_pairs);
         LSL_HIP(hipGetLastError());
         // 4. stable sort by bucket
         int which = 0;
         LSL_TRY(radix_sort_pairs(g.k0, g.v0, g.k1, g.v1, g.n_pairs, bits_for(g.n_buckets), g.tmp,
                                  &which, st));
         const uint32_t* ks = which ? g.k1 : g.k0;
-        const uint32_t* vs = which ? g.v1 : g.v0;
-        // 5. bucket offsets, strut ids and each entry's emission index
+        *g.keys_out = ks;
+        *g.ids_out = which ? g.v1 : g.v0;
+        // 5. bucket offsets: the boundaries of the sorted keys
         k_csr_offsets<<<(g.n_pairs + 1 + 255) / 256, 256, 0, st>>>(ks, g.n_pairs, g.n_buckets,
                                                                    g.offsets);
-        k_ids_emi<<<(g.n_pairs + 255) / 256, 256, 0, st>>>(vs, g.owner, g.active, g.n_pairs,
-                                                           g.ids, g.emi);
         LSL_HIP(hipGetLastError());
     } else {
+        *g.keys_out = g.k0;
+        *g.ids_out = g.v0;
         LSL_TRY(fill_u32(g.offsets, 0u, (size_t)g.n_buckets + 1, st));
     }
+    return LSL_OK;
+}
+
+lsl_status group_emi(const EmiArgs& a, hipStream_t st) {
+    if (a.n_active) k_inverse<<<(a.n_active + 255) / 256, 256, 0, st>>>(a.active, a.n_active, a.inv);
+    if (a.n_pairs) k_emi<<<(a.n_pairs + 255) / 256, 256, 0, st>>>(a);
+    LSL_HIP(hipGetLastError());
     return LSL_OK;
 }
 

@@ -63,15 +63,31 @@ struct GroupBuffers {
     // outputs
     uint32_t* eoff;                   // [n_active + 1]
     uint32_t* offsets;                // [n_buckets + 1]
-    uint32_t* ids;                    // [n_pairs] sorted positions
-    uint32_t* emi;                    // [n_pairs] bucket entry -> emission index
-    uint32_t* owner;                  // [n_pairs] scratch
-    uint32_t* k0; uint32_t* v0; uint32_t* k1; uint32_t* v1;   // [n_pairs] scratch
+    uint32_t* k0; uint32_t* v0; uint32_t* k1; uint32_t* v1;   // [n_pairs] sort buffers
+    const uint32_t** keys_out;        // out: sorted bucket keys (k0 or k1)
+    const uint32_t** ids_out;         // out: bucket entries, edge-list positions (v0 or v1)
     uint32_t* tmp;                    // scan / sort scratch
     uint32_t* blk;                    // compaction block counts
 };
 size_t group_tmp_elems(size_t n_pairs, size_t n_active, size_t n_cand);
 lsl_status bin_group(const GroupBuffers& g, hipStream_t st);
+
+// Emission index of every bucket entry of the resident group (the position
+// of the (strut, bucket) pair in the strut-major emission order), rebuilt
+// from the sorted keys, the entry's strut and the strut's box.  inv
+// ([n_binned], scratch) receives the inverse of the active list.
+struct EmiArgs {
+    const uint32_t* keys;             // [n_pairs] sorted bucket keys
+    const uint32_t* ids;              // [n_pairs] edge-list positions
+    const uint32_t* active;           // [n_active]
+    const uint32_t* eoff;             // [n_active + 1]
+    const SRange* ranges;             // [n_binned]
+    uint32_t n_pairs, n_active;
+    int32_t sa, ntx, nty;
+    uint32_t* inv;
+    uint32_t* emi;                    // out [n_pairs]
+};
+lsl_status group_emi(const EmiArgs& a, hipStream_t st);
 
 // ---------------------------------------------------------------- field.hip
 struct FieldArgs {
