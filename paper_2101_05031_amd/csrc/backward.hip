@@ -54,10 +54,10 @@ constexpr int kParts = 9;       // pixel sums per (strut, bucket)
 
 // per (strut, plane): the in-plane part of m = F - c, H0 = R^2 - |m|^2, and
 // the ends -tc, L - tc
+// (packed: 20 bytes in float32, so the wave's LDS keeps five waves per SIMD)
 template <typename T>
-struct alignas(8) BPlane {
-    T mx, my, H0, ntc;
-    T nbtc, pad;
+struct BPlane {
+    T mx, my, H0, ntc, nbtc;
 };
 
 template <typename T>

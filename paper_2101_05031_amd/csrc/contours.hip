@@ -176,16 +176,20 @@ __global__ __launch_bounds__(kMThreads) void k_strip_emit(const uint64_t* img, i
         CellMasks c{};
         if (bx < nbx) c = cell_masks(P, nbx, nby, bx, by, W, H);
         const int i0 = 8 * bx, j0 = 8 * by;
+        // this chunk's per-row counts, four rows of 16 bits per word (a row
+        // of a 64-block chunk holds at most 2 x 8 x 64 = 1024 segments)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint64_t v = (uint64_t)row_count(c, 2 * q) | ((uint64_t)row_count(c, 2 * q + 1) << 32);
+        for (int q = 0; q < 2; ++q) {
+            uint64_t v = 0;
+#pragma unroll
+            for (int h = 0; h < 4; ++h) v |= (uint64_t)row_count(c, 4 * q + h) << (16 * h);
             const uint64_t inc = wave_incl(v, lane);
             const uint64_t all = __shfl(inc, kWave - 1, kWave);
             const uint64_t ex = inc - v;
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int r = 2 * q + h;
-                uint64_t o = pos[r] + ((ex >> (32 * h)) & 0xffffffffull);
+            for (int h = 0; h < 4; ++h) {
+                const int r = 4 * q + h;
+                uint64_t o = pos[r] + ((ex >> (16 * h)) & 0xffffull);
                 uint32_t mb = (uint32_t)(c.m >> (8 * r)) & 0xffu;
                 while (mb) {
                     const int cc = __ffs(mb) - 1;
@@ -205,7 +209,7 @@ __global__ __launch_bounds__(kMThreads) void k_strip_emit(const uint64_t* img, i
                     }
                     o += (uint64_t)n;
                 }
-                pos[r] += (all >> (32 * h)) & 0xffffffffull;
+                pos[r] += (all >> (16 * h)) & 0xffffull;
             }
         }
     }
