@@ -13,6 +13,8 @@ Modules
                per-slice field and the inside test
   binning   -- the (slab, tile, strut) bin set the native binning must equal
   contours  -- marching squares on the binary slice image (Sec. 4)
+  polylines -- sub-pixel contour endpoints and the chaining of segments
+               into closed loops / open chains (the step after Sec. 4)
   gradient  -- derivatives of a pixel-weighted field sum with respect to
                strut weights and node positions
 
