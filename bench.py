@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--slices", type=int, default=0, help="limit planes (0 = all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--no-polylines", action="store_true",
+                    help="skip timing slice_polylines (sub-pixel contours + chaining)")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--slab", type=int, default=0)
     ap.add_argument("--peak-probe", action="store_true",
@@ -254,6 +256,24 @@ def main():
     if not args.no_backward:
         t_fb, _ = timed(fwd_bwd_step, args.steps)
 
+    # sub-pixel contours and chains of every plane of the last forward step's
+    # field (the step after the path's contours), timed with events
+    poly = None
+    if field is not None and not args.no_polylines:
+        bb = binit()
+        api.slice_polylines(bb, field)                         # sizes, warms up
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        psegs, _, pchain, prank = api.slice_polylines(bb, field, capacity=capacity)
+        e1.record()
+        torch.cuda.synchronize()
+        pms = e0.elapsed_time(e1)
+        n_chains = int((prank == 0).sum())
+        poly = {"ms": pms, "segments": int(len(psegs)), "chains": n_chains,
+                "segments_per_s": len(psegs) / (pms * 1e-3)}
+        del bb, psegs, pchain, prank
+        print(f"[bench] polylines {pms:.2f} ms, {n_chains} chains", file=sys.stderr, flush=True)
+
     # the field kernel against its own per-pair sequence on staged data
     # (lsl_probe_valu mode 4), measured here on the same GPU
     inner = None
@@ -292,6 +312,7 @@ def main():
         "slices_per_s": S / t_fwd,
         "executed_evals_per_s": stats["candidates"] / t_fwd,
         "stages": stages,
+        "polylines": poly,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

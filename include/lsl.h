@@ -214,6 +214,31 @@ lsl_status slice_contours(const lattice_bins* bins, int32_t nk,
                           void* stream);
 
 /* ---------------------------------------------------------------------------
+ * slice_polylines -- sub-pixel contours and their chaining into polylines
+ * (the step after Sec. 4's boundary curves, toward toolpaths).
+ *
+ * Same planes, cells, segment count, order, offsets and capacity rules as
+ * slice_contours (without case codes), except that each segment end sits
+ * where g - C, interpolated linearly along its cell edge from the edge's
+ * lower-(j, i) grid point P to the other point Q, vanishes:
+ * P + t (Q - P), t = (C - g(P)) / (g(Q) - g(P)) (exactly one of P, Q is
+ * inside).  Both segments meeting on an edge compute the point identically.
+ *
+ * chain, rank: optional (both or neither) [capacity] int32, per plane.  The
+ * segment that follows s starts on the edge where s ends (the inside stays on
+ * the left).  A chain starts at a segment with no predecessor (where a contour
+ * enters from the grid border) or, for a closed loop, at its smallest segment
+ * index.  chain[s] is that start's index within the plane, rank[s] the steps
+ * from it.  Sorting a plane's segments by (chain, rank) gives its polylines.
+ * Bitwise deterministic.  Synchronises `stream` (reads the offsets).
+ * LSL_ECAPACITY as in slice_contours; LSL_EINVAL beyond 2^30 segments.
+ * ------------------------------------------------------------------------- */
+lsl_status slice_polylines(const lattice_bins* bins, int32_t nk, const void* field,
+                           float* segs, int64_t capacity, int64_t* offsets,
+                           int32_t* chain, int32_t* rank, int64_t* total,
+                           void* stream);
+
+/* ---------------------------------------------------------------------------
  * slice_field_backward -- gradient of a loss of the sliced field.
  *
  * Given grad_field = dL/dg at the pixels of planes k0 .. k0+nk-1

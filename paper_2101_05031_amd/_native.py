@@ -60,6 +60,8 @@ SIGNATURES = {
     "slice_field_stats": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_int64), c_void_p]),
     "slice_contours": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int64, c_void_p,
                                  c_void_p, POINTER(c_int64), c_void_p]),
+    "slice_polylines": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int64, c_void_p,
+                                  c_void_p, c_void_p, POINTER(c_int64), c_void_p]),
     "slice_field_backward": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p,
                                        c_void_p, c_int32, c_void_p]),
     "slice_batch": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p,

@@ -155,6 +155,31 @@ def slice_contours(bins: Bins, field, capacity: int | None = None, case_codes: b
     return segs[:total.value], off, codes
 
 
+def slice_polylines(bins: Bins, field, capacity: int | None = None, chains: bool = True,
+                    stream=None):
+    """Sub-pixel contours of planes field[nk,H,W] and their chaining ->
+    (segs float32 [n,4], offsets int64 [nk+1], chain int32 [n] or None,
+    rank int32 [n] or None); chain and rank are per plane."""
+    nk = field.shape[0]
+    off = torch.empty(nk + 1, dtype=torch.int64, device="cuda")
+    total = c_int64()
+    L = N.lib()
+    if capacity is None:
+        st = L.slice_polylines(bins.handle, nk, _ptr(field), c_void_p(0), 0, _ptr(off),
+                               c_void_p(0), c_void_p(0), byref(total), _stream(stream))
+        if st not in (N.LSL_OK, N.LSL_ECAPACITY):
+            N.check(st, "slice_polylines")
+        capacity = total.value
+    segs = torch.empty((max(capacity, 1), 4), dtype=torch.float32, device="cuda")
+    chain = torch.empty(max(capacity, 1), dtype=torch.int32, device="cuda") if chains else None
+    rank = torch.empty(max(capacity, 1), dtype=torch.int32, device="cuda") if chains else None
+    N.check(L.slice_polylines(bins.handle, nk, _ptr(field), _ptr(segs), int(capacity), _ptr(off),
+                              _ptr(chain), _ptr(rank), byref(total), _stream(stream)),
+            "slice_polylines")
+    n = total.value
+    return segs[:n], off, None if chain is None else chain[:n], None if rank is None else rank[:n]
+
+
 def slice_field_backward(bins: Bins, k0: int, nk: int, grad_field, grad_weight=None,
                          grad_nodes=None, accumulate: bool = False, stream=None):
     if grad_weight is None:

@@ -178,6 +178,8 @@ struct lattice_bins {
     size_t ctmp_elems = 0;
     uint32_t* cbits = nullptr;        // binary images: slice_contours, slice_batch
     size_t cbits_elems = 0;
+    uint32_t* pscratch = nullptr;     // slice_polylines: edges, cells, links, jumps
+    size_t pscratch_elems = 0;
     uint32_t* queue_buf = nullptr;     // persistent path: keys/vals/alternates + counter
     size_t queue_cap = 0;
     std::vector<std::pair<void*, size_t>> allocs;
@@ -861,6 +863,63 @@ lsl_status slice_contours(const lattice_bins* cb, int32_t nk, const void* field,
         LSL_TRY(launch_contours_emit(img, nk, b->grid.W, b->grid.H, b->ctmp, nullptr, segs,
                                      capacity, st));
     return LSL_OK;
+}
+
+
+lsl_status slice_polylines(const lattice_bins* cb, int32_t nk, const void* field, float* segs,
+                           int64_t capacity, int64_t* offsets, int32_t* chain, int32_t* rank,
+                           int64_t* total, void* stream) {
+    set_error("");
+    LSL_CHECK(cb != nullptr, "bins handle is NULL");
+    LSL_CHECK(nk >= 1, "nk must be >= 1");
+    LSL_CHECK(field != nullptr && offsets != nullptr, "field and offsets are required");
+    LSL_CHECK(capacity >= 0, "capacity must be >= 0");
+    LSL_CHECK(capacity == 0 || segs != nullptr, "segs is NULL");
+    LSL_CHECK((chain == nullptr) == (rank == nullptr), "chain and rank go together");
+    lattice_bins* b = const_cast<lattice_bins*>(cb);   // scratch only
+    hipStream_t st = S(stream);
+    const size_t need = contour_tmp_elems(nk, b->grid.W, b->grid.H);
+    if (need > b->ctmp_elems) {
+        LSL_HIP(hipStreamSynchronize(st));
+        b->release(b->ctmp);
+        b->ctmp = nullptr;
+        b->ctmp_elems = 0;
+        LSL_TRY(b->alloc_t(&b->ctmp, need));
+        b->ctmp_elems = need;
+        b->drop_graphs();
+    }
+    LSL_TRY(ensure_cbits(b, nk, st));
+    const uint64_t* img = (const uint64_t*)b->cbits;
+    LSL_TRY(launch_bits_blk(b->dtype, field, nk, b->grid.W, b->grid.H, b->C,
+                            (uint64_t*)b->cbits, st));
+    LSL_TRY(launch_contours_count(img, nk, b->grid.W, b->grid.H, offsets, nullptr, b->ctmp,
+                                  nullptr, st));
+    std::vector<int64_t> h_off((size_t)nk + 1);
+    LSL_HIP(hipMemcpyAsync(h_off.data(), offsets, h_off.size() * 8, hipMemcpyDeviceToHost, st));
+    LSL_HIP(hipStreamSynchronize(st));
+    const int64_t tot = h_off[nk];
+    if (total) *total = tot;
+    if (tot > capacity) {
+        set_error("slice_polylines: " + std::to_string(tot) + " segments exceed capacity " +
+                  std::to_string(capacity));
+        return LSL_ECAPACITY;
+    }
+    LSL_CHECK(tot < ((int64_t)1 << 31) / 2, "slice_polylines: too many segments in one call");
+    if (tot == 0) return LSL_OK;
+    int64_t longest = 1;
+    for (int32_t k = 0; k < nk; ++k) longest = std::max<int64_t>(longest, h_off[k + 1] - h_off[k]);
+    int32_t rounds = 1;
+    while (((int64_t)1 << (rounds - 1)) < longest) ++rounds;
+    const size_t ps = polyline_scratch_elems((uint64_t)tot);
+    if (ps > b->pscratch_elems) {
+        b->release(b->pscratch);
+        b->pscratch = nullptr;
+        b->pscratch_elems = 0;
+        LSL_TRY(b->alloc_t(&b->pscratch, ps));
+        b->pscratch_elems = ps;
+    }
+    return launch_polylines(img, field, b->dtype, b->C, nk, b->grid.W, b->grid.H, b->ctmp, offsets,
+                            (uint64_t)tot, rounds, segs, b->pscratch, chain, rank, st);
 }
 
 }  // extern "C"

@@ -19,6 +19,8 @@
 // Segment ends are edge midpoints in grid units; the inside lies on the left
 // of each segment; the saddles 5 and 10 keep the two inside corners apart.
 // Outputs are deterministic and written with no atomics.
+#include <utility>
+
 #include "kernels.hpp"
 
 namespace lsl {
@@ -138,11 +140,44 @@ __device__ __forceinline__ uint64_t wave_total(uint64_t v) {
     return v;
 }
 
+// Optional outputs of the emit pass for sub-pixel segments and chaining:
+// endpoints interpolated on the field, each segment's start and end edge and
+// its cell.  Edge ids per plane: 2 (y W + x) for the edge (x,y)-(x+1,y),
+// 2 (y W + x) + 1 for (x,y)-(x,y+1).
+struct SubPix {
+    const void* field;                // [nk][H][W], T
+    double C;
+    uint32_t* edge_s;                 // [total] start edge of each segment
+    uint32_t* edge_e;                 // [total] end edge
+    uint32_t* cell;                   // [total] j (W-1) + i
+};
+
+// One end of a segment of cell (i, j) at table point g (half units): its
+// edge id and, for SUB, the point where g - C interpolates to zero along the
+// edge, from its lower-(j, i) grid point P to Q.
+template <bool SUB, typename T>
+__device__ __forceinline__ float2 seg_end(const int8_t* g, int i, int j, int32_t W, const T* f,
+                                          T C, uint32_t* edge) {
+    if (!SUB) return make_float2((float)i + 0.5f * g[0], (float)j + 0.5f * g[1]);   // midpoint
+    if (!(g[1] & 1)) {                              // horizontal edge at y = j + g/2
+        const int y = j + (g[1] >> 1);
+        *edge = 2u * ((uint32_t)y * (uint32_t)W + (uint32_t)i);
+        const T gp = f[(size_t)y * W + i], gq = f[(size_t)y * W + i + 1];
+        return make_float2((float)((T)i + (C - gp) / (gq - gp)), (float)y);
+    }
+    const int x = i + (g[0] >> 1);                  // vertical edge at x = i + g/2
+    *edge = 2u * ((uint32_t)j * (uint32_t)W + (uint32_t)x) + 1u;
+    const T gp = f[(size_t)j * W + x], gq = f[(size_t)(j + 1) * W + x];
+    return make_float2((float)x, (float)((T)j + (C - gp) / (gq - gp)));
+}
+
+template <bool SUB, typename T>
 __global__ __launch_bounds__(kMThreads) void k_strip_emit(const uint64_t* img, int32_t nk,
                                                           int32_t W, int32_t H,
                                                           const unsigned long long* scan,
                                                           const unsigned long long* base,
-                                                          float4* segs, int64_t capacity) {
+                                                          float4* segs, int64_t capacity,
+                                                          SubPix sp) {
     const int lane = lane_id();
     const int nbx = (W + 7) / 8, nby = (H + 7) / 8;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -199,12 +234,20 @@ __global__ __launch_bounds__(kMThreads) void k_strip_emit(const uint64_t* img, i
                                          (((c.b2 >> bit) & 1ull) << 2) |
                                          (((c.b3 >> bit) & 1ull) << 3));
                     const int n = kSegCount[cs];
-                    const float fi = (float)(i0 + cc), fj = (float)(j0 + r);
+                    const int ci = i0 + cc, cj = j0 + r;
+                    const T* f = SUB ? (const T*)sp.field + k * (uint64_t)W * (uint64_t)H : nullptr;
                     for (int sg = 0; sg < n; ++sg) {
                         if ((int64_t)(o + sg) < capacity) {
                             const int8_t* g = kSeg[cs][sg];
-                            segs[o + sg] = make_float4(fi + 0.5f * g[0], fj + 0.5f * g[1],
-                                                       fi + 0.5f * g[2], fj + 0.5f * g[3]);
+                            uint32_t es = 0, ee = 0;
+                            const float2 a = seg_end<SUB, T>(g, ci, cj, W, f, (T)sp.C, &es);
+                            const float2 b = seg_end<SUB, T>(g + 2, ci, cj, W, f, (T)sp.C, &ee);
+                            segs[o + sg] = make_float4(a.x, a.y, b.x, b.y);
+                            if (SUB) {
+                                sp.edge_s[o + sg] = es;
+                                sp.edge_e[o + sg] = ee;
+                                sp.cell[o + sg] = (uint32_t)cj * (uint32_t)(W - 1) + (uint32_t)ci;
+                            }
                         }
                     }
                     o += (uint64_t)n;
@@ -252,6 +295,106 @@ __global__ __launch_bounds__(256) void k_bits_rows(const uint64_t* img, uint64_t
         if (bx < nbx) v |= (uint32_t)((row[bx] >> (8 * (j & 7))) & 0xffull) << (8 * q);
     }
     out[t] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Chaining.  Segment s of plane k ends on edge e; the segment that starts on
+// e lies in the cell across e, found by binary search of the plane's
+// row-major cell indices, and follows s.  Chains and ranks then come from
+// pointer jumping over all segments of the call at once:
+//   1. X = succ (a tail points to itself), M = own index; K rounds of
+//      M = min(M, M[X]), X = X[X] give every segment of a closed loop the
+//      loop's smallest index, and leave a segment on an open chain pointing
+//      at the chain's tail (succ[X] < 0).
+//   2. Heads are segments with no predecessor and the smallest segment of
+//      each loop; P = pred (a head points to itself), D = 0 at heads, else 1;
+//      K rounds of D += D[P], P = P[P] give each segment its head and its
+//      distance from it.
+// K = 1 + ceil(log2(longest chain)).  All integer: bitwise deterministic.
+__device__ __forceinline__ uint32_t plane_of(const int64_t* off, int32_t nk, uint64_t s) {
+    int32_t lo = 0, hi = nk;                       // off[lo] <= s < off[hi]
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if ((uint64_t)off[mid] <= s) lo = mid; else hi = mid;
+    }
+    return (uint32_t)lo;
+}
+
+__global__ void k_poly_succ(const int64_t* off, int32_t nk, uint64_t total, int32_t W, int32_t H,
+                            const uint32_t* edge_s, const uint32_t* edge_e, const uint32_t* cell,
+                            int32_t* succ) {
+    const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= total) return;
+    const uint32_t k = plane_of(off, nk, s);
+    const uint64_t lo = (uint64_t)off[k], hi = (uint64_t)off[k + 1];
+    const uint32_t cw = (uint32_t)(W - 1);
+    const uint32_t c = cell[s], i = c % cw, j = c / cw;
+    const uint32_t e = edge_e[s], at = e >> 1;
+    const int x = (int)(at % (uint32_t)W), y = (int)(at / (uint32_t)W);
+    int ni = (int)i, nj = (int)j;
+    if (e & 1u) ni = x == (int)i ? (int)i - 1 : (int)i + 1;     // vertical edge
+    else nj = y == (int)j ? (int)j - 1 : (int)j + 1;            // horizontal edge
+    int32_t r = -1;
+    if (ni >= 0 && nj >= 0 && ni < W - 1 && nj < H - 1) {
+        const uint32_t nc = (uint32_t)nj * cw + (uint32_t)ni;
+        uint64_t a = lo, b = hi;                   // first position with cell >= nc
+        while (a < b) {
+            const uint64_t mid = (a + b) >> 1;
+            if (cell[mid] < nc) a = mid + 1; else b = mid;
+        }
+        for (uint64_t q = a; q < hi && q < a + 2 && cell[q] == nc; ++q)
+            if (edge_s[q] == e) r = (int32_t)q;
+    }
+    succ[s] = r;
+}
+
+__global__ void k_poly_pred(const int32_t* succ, uint64_t total, int32_t* pred) {
+    const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < total && succ[s] >= 0) pred[succ[s]] = (int32_t)s;
+}
+
+__global__ void k_poly_init_min(const int32_t* succ, uint64_t total, int32_t* X, int32_t* M) {
+    const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= total) return;
+    X[s] = succ[s] < 0 ? (int32_t)s : succ[s];
+    M[s] = (int32_t)s;
+}
+
+__global__ void k_poly_jump_min(const int32_t* X, const int32_t* M, uint64_t total, int32_t* X2,
+                                int32_t* M2) {
+    const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= total) return;
+    const int32_t x = X[s];
+    M2[s] = M[s] < M[x] ? M[s] : M[x];
+    X2[s] = X[x];
+}
+
+__global__ void k_poly_heads(const int32_t* succ, const int32_t* pred, const int32_t* X,
+                             const int32_t* M, uint64_t total, int32_t* P, int32_t* D) {
+    const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= total) return;
+    const bool on_loop = succ[X[s]] >= 0;
+    const bool head = pred[s] < 0 || (on_loop && M[s] == (int32_t)s);
+    P[s] = head ? (int32_t)s : pred[s];
+    D[s] = head ? 0 : 1;
+}
+
+__global__ void k_poly_jump_rank(const int32_t* P, const int32_t* D, uint64_t total, int32_t* P2,
+                                 int32_t* D2) {
+    const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= total) return;
+    const int32_t p = P[s];
+    D2[s] = D[s] + D[p];
+    P2[s] = P[p];
+}
+
+__global__ void k_poly_out(const int64_t* off, int32_t nk, uint64_t total, const int32_t* P,
+                           const int32_t* D, int32_t* chain, int32_t* rank) {
+    const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= total) return;
+    const uint32_t k = plane_of(off, nk, s);
+    chain[s] = P[s] - (int32_t)off[k];
+    rank[s] = D[s];
 }
 
 }  // namespace
@@ -304,8 +447,8 @@ lsl_status launch_contours_emit(const uint64_t* img, int32_t nk, int32_t W, int3
     const uint32_t nby = (uint32_t)((H + 7) / 8);
     const size_t n = (size_t)nk * nby;
     if (W > 1 && H > 1)
-        k_strip_emit<<<(unsigned)((n + 3) / 4), kMThreads, 0, st>>>(img, nk, W, H, tmp, base,
-                                                                  (float4*)segs, capacity);
+        k_strip_emit<false, float><<<(unsigned)((n + 3) / 4), kMThreads, 0, st>>>(
+            img, nk, W, H, tmp, base, (float4*)segs, capacity, SubPix{});
     if (base) k_ms_advance<<<1, 64, 0, st>>>(base, tmp, n);
     LSL_HIP(hipGetLastError());
     return LSL_OK;
@@ -319,5 +462,57 @@ lsl_status launch_bits_rows(const uint64_t* img, int32_t nk, int32_t W, int32_t 
     LSL_HIP(hipGetLastError());
     return LSL_OK;
 }
+
+lsl_status launch_polylines(const uint64_t* img, const void* field, int dtype, double C,
+                            int32_t nk, int32_t W, int32_t H, const unsigned long long* tmp,
+                            const int64_t* offsets, uint64_t total, int32_t rounds, float* segs,
+                            uint32_t* scratch, int32_t* chain, int32_t* rank, hipStream_t st) {
+    if (total == 0 || W < 2 || H < 2) return LSL_OK;
+    const uint32_t nby = (uint32_t)((H + 7) / 8);
+    const size_t n = (size_t)nk * nby;
+    SubPix sp;
+    sp.field = field;
+    sp.C = C;
+    sp.edge_s = scratch;
+    sp.edge_e = scratch + total;
+    sp.cell = scratch + 2 * total;
+    if (dtype == LSL_F32)
+        k_strip_emit<true, float><<<(unsigned)((n + 3) / 4), kMThreads, 0, st>>>(
+            img, nk, W, H, tmp, nullptr, (float4*)segs, (int64_t)total, sp);
+    else
+        k_strip_emit<true, double><<<(unsigned)((n + 3) / 4), kMThreads, 0, st>>>(
+            img, nk, W, H, tmp, nullptr, (float4*)segs, (int64_t)total, sp);
+    LSL_HIP(hipGetLastError());
+    if (!chain || !rank) return LSL_OK;
+    int32_t* succ = (int32_t*)(scratch + 3 * total);
+    int32_t* pred = succ + total;
+    int32_t* A0 = pred + total;                    // X | P
+    int32_t* A1 = A0 + total;                      // M | D
+    int32_t* B0 = A1 + total;
+    int32_t* B1 = B0 + total;
+    const unsigned g = (unsigned)((total + 255) / 256);
+    k_poly_succ<<<g, 256, 0, st>>>(offsets, nk, total, W, H, sp.edge_s, sp.edge_e, sp.cell, succ);
+    LSL_TRY(fill_u32((uint32_t*)pred, 0xffffffffu, total, st));
+    k_poly_pred<<<g, 256, 0, st>>>(succ, total, pred);
+    k_poly_init_min<<<g, 256, 0, st>>>(succ, total, A0, A1);
+    for (int r = 0; r < rounds; ++r) {
+        k_poly_jump_min<<<g, 256, 0, st>>>(A0, A1, total, B0, B1);
+        std::swap(A0, B0);
+        std::swap(A1, B1);
+    }
+    k_poly_heads<<<g, 256, 0, st>>>(succ, pred, A0, A1, total, B0, B1);
+    std::swap(A0, B0);
+    std::swap(A1, B1);
+    for (int r = 0; r < rounds; ++r) {
+        k_poly_jump_rank<<<g, 256, 0, st>>>(A0, A1, total, B0, B1);
+        std::swap(A0, B0);
+        std::swap(A1, B1);
+    }
+    k_poly_out<<<g, 256, 0, st>>>(offsets, nk, total, A0, A1, chain, rank);
+    LSL_HIP(hipGetLastError());
+    return LSL_OK;
+}
+
+size_t polyline_scratch_elems(uint64_t total) { return (size_t)(9 * total + 16); }
 
 }  // namespace lsl

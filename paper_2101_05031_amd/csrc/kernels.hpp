@@ -123,6 +123,16 @@ lsl_status launch_contours_count(const uint64_t* img, int32_t nk, int32_t W, int
 lsl_status launch_contours_emit(const uint64_t* img, int32_t nk, int32_t W, int32_t H,
                                 const unsigned long long* tmp, unsigned long long* base,
                                 float* segs, int64_t capacity, hipStream_t st);
+// Sub-pixel segments of nk planes (same cells and order as the emit pass;
+// tmp, offsets from launch_contours_count with no base) and, if chain and
+// rank are given, each segment's chain head and rank within its plane.
+// scratch holds polyline_scratch_elems(total) words; rounds is
+// 1 + ceil(log2(longest chain)).
+lsl_status launch_polylines(const uint64_t* img, const void* field, int dtype, double C,
+                            int32_t nk, int32_t W, int32_t H, const unsigned long long* tmp,
+                            const int64_t* offsets, uint64_t total, int32_t rounds, float* segs,
+                            uint32_t* scratch, int32_t* chain, int32_t* rank, hipStream_t st);
+size_t polyline_scratch_elems(uint64_t total);
 // Row-major bits [nk][H][ceil(W/32)] from block-major images.
 lsl_status launch_bits_rows(const uint64_t* img, int32_t nk, int32_t W, int32_t H,
                             uint32_t* bits, hipStream_t st);
