@@ -15,6 +15,8 @@ Modules
   contours  -- marching squares on the binary slice image (Sec. 4)
   polylines -- sub-pixel contour endpoints and the chaining of segments
                into closed loops / open chains (the step after Sec. 4)
+  support   -- self-support metrics Gamma, Psi (Sec. 5.2, Eqs. 11-14) and
+               dGamma/dv
   gradient  -- derivatives of a pixel-weighted field sum with respect to
                strut weights and node positions
 
