@@ -274,6 +274,15 @@ def main():
         del bb, psegs, pchain, prank
         print(f"[bench] polylines {pms:.2f} ms, {n_chains} chains", file=sys.stderr, flush=True)
 
+    # self-support metrics and dGamma/dv of the lattice (Sec. 5.2), timed
+    api.lattice_support(nodes, edges, weight, grad=True)        # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sres, _ = api.lattice_support(nodes, edges, weight, grad=True)
+    e1.record()
+    torch.cuda.synchronize()
+    support = {"ms": e0.elapsed_time(e1), "gamma": sres["gamma"], "psi": sres["psi"]}
+
     # the field kernel against its own per-pair sequence on staged data
     # (lsl_probe_valu mode 4), measured here on the same GPU
     inner = None
@@ -313,6 +322,7 @@ def main():
         "executed_evals_per_s": stats["candidates"] / t_fwd,
         "stages": stages,
         "polylines": poly,
+        "support": support,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -289,6 +289,39 @@ lsl_status slice_autotune(const lsl_lattice* lattice, const lsl_grid* grid,
                           lsl_bin_params* params, const char* cache_path,
                           void* stream);
 
+/* ---------------------------------------------------------------------------
+ * lattice_support -- self-support metrics of a lattice (Sec. 5.2) and the
+ * gradient of Gamma for the vertex position optimisation.
+ *
+ * For edge j with unit direction u_j, length L_j and weight r_j (the radius
+ * stored on the edge), theta_j = arccos |u_j . t| (Eq. 11), t = print_dir
+ * normalised; the edge is self-supported when theta_j <= pi/4 (the paper's
+ * alpha).  g(theta) is the paper's polynomial for alpha = pi/4 (Eq. 12):
+ * sum_i a_i theta^i, a = (-0.02, -0.31, 1.44, -1.11, 0.58, -0.16), for
+ * theta > pi/4, else 0.  Gamma = sum over unsupported edges of r L g /
+ * sum over all edges of r L (Eq. 13); Psi = 100 * supported length / total
+ * length (Eq. 14).  Zero-length edges add nothing.  Sums are float64 in a
+ * fixed order (bitwise repeatable).
+ *
+ * print_dir: [host] double[3], finite, non-zero.  out: [host].  grad_nodes:
+ * optional [n_nodes][3] lattice dtype, receives dGamma/dv (overwritten; the
+ * step of g at pi/4 contributes no derivative).  R and C of the lattice are
+ * not used.  Synchronises `stream`.  Errors: LSL_EINVAL (bad argument, edge
+ * index out of range), LSL_ENOMEM, LSL_EDEVICE.
+ * ------------------------------------------------------------------------- */
+typedef struct lsl_support {
+    double gamma;             /* Eq. (13)                                      */
+    double psi;               /* Eq. (14), percent                             */
+    double risky_area;        /* sum over unsupported edges of r L g(theta)     */
+    double area;              /* sum over edges of r L                         */
+    double supported_length;  /* sum over supported edges of L                 */
+    double length;            /* sum over edges of L                           */
+    int64_t n_supported;
+} lsl_support;
+
+lsl_status lattice_support(const lsl_lattice* lattice, const double* print_dir,
+                           lsl_support* out, void* grad_nodes, void* stream);
+
 /* Static text for a status code. */
 const char* lsl_status_string(lsl_status s);
 /* Message of the calling thread's last failed call ("" if none). */

@@ -45,6 +45,12 @@ class LslBinsInfo(Structure):
                 ("last_queue_ms", c_double), ("last_contour_ms", c_double)]
 
 
+class LslSupport(Structure):
+    _fields_ = [("gamma", c_double), ("psi", c_double), ("risky_area", c_double),
+                ("area", c_double), ("supported_length", c_double), ("length", c_double),
+                ("n_supported", c_int64)]
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "lattice_bin": (c_int32, [POINTER(LslLattice), POINTER(LslGrid), POINTER(LslBinParams),
@@ -68,6 +74,8 @@ SIGNATURES = {
                               c_int64, c_void_p, POINTER(c_int64), c_void_p]),
     "slice_autotune": (c_int32, [POINTER(LslLattice), POINTER(LslGrid),
                                  POINTER(LslBinParams), c_char_p, c_void_p]),
+    "lattice_support": (c_int32, [POINTER(LslLattice), POINTER(c_double), POINTER(LslSupport),
+                                  c_void_p, c_void_p]),
     "lsl_status_string": (c_char_p, [c_int32]),
     "lsl_last_error": (c_char_p, []),
     "lsl_version": (c_char_p, []),

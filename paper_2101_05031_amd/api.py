@@ -238,3 +238,18 @@ def cache_trim() -> int:
     n = c_int64()
     N.check(N.lib().lsl_cache_trim(byref(n)), "lsl_cache_trim")
     return n.value
+
+
+def lattice_support(nodes, edges, weight, print_dir=(0.0, 0.0, 1.0), grad: bool = False,
+                    stream=None):
+    """Self-support metrics (Sec. 5.2, Eqs. 11-14) of the lattice on the GPU:
+    dict of gamma, psi and the sums behind them; with grad=True also
+    dGamma/dv [n_nodes, 3] (lattice dtype)."""
+    L = _lattice_struct(nodes, edges, weight, 1.0, 1.0)
+    t = (c_double * 3)(*[float(x) for x in print_dir])
+    out = N.LslSupport()
+    g = torch.empty_like(nodes) if grad else None
+    N.check(N.lib().lattice_support(byref(L), t, byref(out), _ptr(g), _stream(stream)),
+            "lattice_support")
+    res = {f: getattr(out, f) for f, _ in N.LslSupport._fields_}
+    return (res, g) if grad else res

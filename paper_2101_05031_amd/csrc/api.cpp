@@ -701,6 +701,87 @@ lsl_status lattice_bins_free(lattice_bins* b) {
     return LSL_OK;
 }
 
+namespace {
+// device scratch from the cache, returned when it goes out of scope (callers
+// synchronise the stream first)
+struct CachedBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    lsl_status get(size_t n) {
+        bytes = DeviceCache::size_class(n);
+        if (DeviceCache::get().alloc(&p, bytes) != hipSuccess) {
+            hipGetLastError();
+            p = nullptr;
+            set_error("device allocation of " + std::to_string(bytes) + " bytes failed");
+            return LSL_ENOMEM;
+        }
+        return LSL_OK;
+    }
+    ~CachedBuf() {
+        if (p) DeviceCache::get().release(p, bytes);
+    }
+};
+}  // namespace
+
+lsl_status lattice_support(const lsl_lattice* L, const double* print_dir, lsl_support* out,
+                           void* grad_nodes, void* stream) {
+    set_error("");
+    LSL_CHECK(L != nullptr && print_dir != nullptr && out != nullptr, "NULL argument");
+    LSL_CHECK(L->dtype == LSL_F32 || L->dtype == LSL_F64, "dtype must be LSL_F32 or LSL_F64");
+    LSL_CHECK(L->n_nodes >= 1 && L->n_edges >= 0, "n_nodes >= 1 and n_edges >= 0 required");
+    LSL_CHECK(L->n_nodes < ((int64_t)1 << 31) && L->n_edges < ((int64_t)1 << 30),
+              "lattice too large");
+    LSL_CHECK(L->nodes != nullptr && (L->n_edges == 0 || (L->edges && L->weight)),
+              "lattice arrays are NULL");
+    const double tn = std::sqrt(print_dir[0] * print_dir[0] + print_dir[1] * print_dir[1] +
+                                print_dir[2] * print_dir[2]);
+    LSL_CHECK(std::isfinite(tn) && tn > 0.0, "print_dir must be finite and non-zero");
+    hipStream_t st = S(stream);
+    SupportArgs a{};
+    a.nodes = L->nodes;
+    a.edges = L->edges;
+    a.weight = L->weight;
+    a.n_nodes = L->n_nodes;
+    a.n_edges = L->n_edges;
+    for (int i = 0; i < 3; ++i) a.t[i] = print_dir[i] / tn;
+    const size_t np = support_part_elems(L->n_edges);
+    CachedBuf small, te, sortb, offb;
+    LSL_TRY(small.get((np + 8) * sizeof(double)));
+    a.part = (double*)small.p;
+    a.sums = a.part + np;
+    a.err = (int*)(a.sums + 6);
+    const size_t n2 = std::max<size_t>(2 * (size_t)L->n_edges, 1);
+    if (grad_nodes) {
+        LSL_TRY(te.get(std::max<size_t>(3 * (size_t)L->n_edges, 1) * sizeof(double)));
+        LSL_TRY(sortb.get((4 * n2 + radix_tmp_elems(n2)) * sizeof(uint32_t)));
+        LSL_TRY(offb.get(((size_t)L->n_nodes + 1) * sizeof(uint32_t)));
+        a.grad = grad_nodes;
+        a.te = (double*)te.p;
+        a.k0 = (uint32_t*)sortb.p;
+        a.v0 = a.k0 + n2;
+        a.k1 = a.v0 + n2;
+        a.v1 = a.k1 + n2;
+        a.tmp = a.v1 + n2;
+        a.off = (uint32_t*)offb.p;
+    }
+    LSL_TRY(fill_u32((uint32_t*)a.err, 0u, 1, st));
+    LSL_TRY(launch_support(L->dtype, a, st));
+    double h[6] = {0, 0, 0, 0, 0, 0};
+    int herr = 0;
+    LSL_HIP(hipMemcpyAsync(h, a.sums, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
+    LSL_HIP(hipMemcpyAsync(&herr, a.err, sizeof(int), hipMemcpyDeviceToHost, st));
+    LSL_HIP(hipStreamSynchronize(st));
+    LSL_CHECK(herr == 0, "edge index out of range");
+    out->risky_area = h[0];
+    out->area = h[1];
+    out->supported_length = h[2];
+    out->length = h[3];
+    out->n_supported = (int64_t)std::llround(h[4]);
+    out->gamma = h[1] > 0.0 ? h[0] / h[1] : 0.0;
+    out->psi = h[3] > 0.0 ? 100.0 * h[2] / h[3] : 0.0;
+    return LSL_OK;
+}
+
 lsl_status lsl_cache_trim(int64_t* cached_bytes) {
     if (cached_bytes) *cached_bytes = (int64_t)DeviceCache::get().cached();
     DeviceCache::get().trim();

@@ -199,4 +199,24 @@ lsl_status launch_queue_build(const FieldArgs& f, uint32_t* keys, uint32_t* vals
 lsl_status launch_persistent(int dtype, const BatchArgs& a, int n_blocks, hipStream_t st);
 int persistent_blocks(int dtype, int slab);
 
+// ---------------------------------------------------------------- support.hip
+// Self-support metrics (Sec. 5.2, Eqs. 11-14) and dGamma/dv.
+struct SupportArgs {
+    const void* nodes;                // [n_nodes][3], lattice dtype
+    const int32_t* edges;             // [n_edges][2]
+    const void* weight;               // [n_edges]
+    int64_t n_nodes, n_edges;
+    double t[3];                      // unit printing direction
+    double* part;                     // [support_part_elems(n_edges)]
+    double* sums;                     // [5]: N, D, supported length, length, #supported
+    int* err;                         // set to 1 on an edge index out of range
+    void* grad;                       // [n_nodes][3] lattice dtype, or null
+    double* te;                       // [n_edges][3] per-edge gradient terms
+    uint32_t *k0, *v0, *k1, *v1;      // [2 n_edges] incidence sort
+    uint32_t* tmp;                    // radix_tmp_elems(2 n_edges)
+    uint32_t* off;                    // [n_nodes + 1]
+};
+size_t support_part_elems(int64_t n_edges);
+lsl_status launch_support(int dtype, const SupportArgs& a, hipStream_t st);
+
 }  // namespace lsl
