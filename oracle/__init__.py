@@ -17,6 +17,9 @@ Modules
                into closed loops / open chains (the step after Sec. 4)
   support   -- self-support metrics Gamma, Psi (Sec. 5.2, Eqs. 11-14) and
                dGamma/dv
+  density   -- per-voxel density by the inside test at pixel centres
+               (Sec. 5, Eq. 9) and a smooth voxel-density loss with its
+               field gradient, for the radius adjustment of Sec. 5.3
   gradient  -- derivatives of a pixel-weighted field sum with respect to
                strut weights and node positions
 
