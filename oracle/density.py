@@ -16,29 +16,26 @@ import numpy as np
 from scipy.special import expit
 
 
-def voxel_density(field: np.ndarray, C: float, vx: int, vy: int, vz: int) -> np.ndarray:
-    """[ceil(nk/vz), ceil(H/vy), ceil(W/vx)] float64 fractions."""
-    inside = np.asarray(field) >= C
-    nk, H, W = inside.shape
-    nz, ny, nx = -(-nk // vz), -(-H // vy), -(-W // vx)
-    out = np.zeros((nz, ny, nx))
-    for l in range(nz):
-        for j in range(ny):
-            for i in range(nx):
-                block = inside[l * vz:(l + 1) * vz, j * vy:(j + 1) * vy, i * vx:(i + 1) * vx]
-                out[l, j, i] = block.mean()
-    return out
-
-
-def _voxel_mean(x: np.ndarray, vx: int, vy: int, vz: int) -> np.ndarray:
+def voxel_sums(x: np.ndarray, vx: int, vy: int, vz: int) -> np.ndarray:
+    """Sum of x over each voxel: consecutive runs of vz planes, vy rows and
+    vx columns, the last run of each axis shorter when the size is ragged."""
+    x = np.asarray(x, dtype=np.float64)
     nk, H, W = x.shape
-    nz, ny, nx = -(-nk // vz), -(-H // vy), -(-W // vx)
-    out = np.zeros((nz, ny, nx))
-    for l in range(nz):
-        for j in range(ny):
-            for i in range(nx):
-                out[l, j, i] = x[l * vz:(l + 1) * vz, j * vy:(j + 1) * vy, i * vx:(i + 1) * vx].mean()
-    return out
+    x = np.add.reduceat(x, np.arange(0, nk, vz), axis=0)
+    x = np.add.reduceat(x, np.arange(0, H, vy), axis=1)
+    return np.add.reduceat(x, np.arange(0, W, vx), axis=2)
+
+
+def voxel_samples(shape, vx: int, vy: int, vz: int) -> np.ndarray:
+    """Number of pixel-centre samples in each voxel."""
+    return voxel_sums(np.ones(shape), vx, vy, vz)
+
+
+def voxel_density(field: np.ndarray, C: float, vx: int, vy: int, vz: int) -> np.ndarray:
+    """[ceil(nk/vz), ceil(H/vy), ceil(W/vx)] float64 fractions of samples with
+    g >= C."""
+    inside = np.asarray(field) >= C
+    return voxel_sums(inside, vx, vy, vz) / voxel_samples(inside.shape, vx, vy, vz)
 
 
 def soft_density(field, C: float, tau: float, vx: int, vy: int, vz: int) -> np.ndarray:
@@ -50,11 +47,12 @@ def soft_density(field, C: float, tau: float, vx: int, vy: int, vz: int) -> np.n
     """
     g = np.asarray(field, dtype=np.float64)
     s = expit((g - C) / tau)
-    return _voxel_mean(s, vx, vy, vz)
+    return voxel_sums(s, vx, vy, vz) / voxel_samples(g.shape, vx, vy, vz)
 
 
 def density_loss(field, target, C: float, tau: float, vx: int, vy: int, vz: int):
-    """L = sum_v (soft_density_v - target_v)^2 and dL/dg per pixel.
+    """L = sum_v (soft_density_v - target_v)^2, the soft densities and dL/dg
+    per pixel.
 
     dL/dg(p) = 2 (soft_density_v - target_v) / n_v * s (1 - s) / tau for the
     voxel v holding pixel p, n_v its sample count.
@@ -64,13 +62,12 @@ def density_loss(field, target, C: float, tau: float, vx: int, vy: int, vz: int)
     rho = soft_density(g, C, tau, vx, vy, vz)
     r = rho - np.asarray(target, dtype=np.float64)
     loss = float(np.sum(r * r))
-    s = expit((g - C) / tau)
-    grad = np.zeros_like(g)
-    for k in range(nk):
-        for y in range(H):
-            for x in range(W):
-                l, j, i = k // vz, y // vy, x // vx
-                nv = (min(nk, (l + 1) * vz) - l * vz) * (min(H, (j + 1) * vy) - j * vy) * \
-                     (min(W, (i + 1) * vx) - i * vx)
-                grad[k, y, x] = 2.0 * r[l, j, i] / nv * s[k, y, x] * (1.0 - s[k, y, x]) / tau
+    z = (g - C) / tau
+    ds = expit(z) * expit(-z)        # s (1 - s), with 1 - s = sigmoid(-z): no cancellation
+    n = voxel_samples(g.shape, vx, vy, vz)
+    # the voxel of every pixel, axis by axis
+    l = (np.arange(nk) // vz)[:, None, None]
+    j = (np.arange(H) // vy)[None, :, None]
+    i = (np.arange(W) // vx)[None, None, :]
+    grad = 2.0 * r[l, j, i] / n[l, j, i] * ds / tau
     return loss, rho, grad

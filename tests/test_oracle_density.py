@@ -79,3 +79,15 @@ def test_density_loss_gradient_matches_finite_differences():
         fd = (OD.density_loss(p, t, 1.0, tau, 4, 3, 2)[0] -
               OD.density_loss(q, t, 1.0, tau, 4, 3, 2)[0]) / (2 * h)
         assert abs(fd - grad[k, y, x]) <= 1e-7 * max(1.0, abs(fd))
+
+
+def test_density_gradient_deep_inside_and_outside():
+    """Far from the iso-surface s (1 - s) is tiny but not zero: the gradient
+    keeps its sign and size there, matching exp(-|z|) to leading order."""
+    tau = 0.05
+    g = np.array([[[1.0 + 70 * tau, 1.0 - 19 * tau]]])
+    _, rho, grad = OD.density_loss(g, np.array([[[0.0]]]), 1.0, tau, 2, 1, 1)
+    r = rho[0, 0, 0]
+    assert grad[0, 0, 0] == pytest.approx(2 * r / 2 * np.exp(-70.0) / tau, rel=1e-12)
+    assert grad[0, 0, 1] == pytest.approx(2 * r / 2 * np.exp(-19.0) / (1 + np.exp(-19.0)) ** 2 / tau,
+                                          rel=1e-12)
