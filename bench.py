@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--slices", type=int, default=0, help="limit planes (0 = all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--no-density", action="store_true",
+                    help="skip timing slice_density and slice_density_loss")
     ap.add_argument("--no-polylines", action="store_true",
                     help="skip timing slice_polylines (sub-pixel contours + chaining)")
     ap.add_argument("--tile", type=int, default=0)
@@ -274,6 +276,40 @@ def main():
         del bb, psegs, pchain, prank
         print(f"[bench] polylines {pms:.2f} ms, {n_chains} chains", file=sys.stderr, flush=True)
 
+    # per-voxel density (Eq. 9) of every plane of the field, and the soft
+    # voxel-density loss with its field gradient (Sec. 5.3), timed with events
+    dens = None
+    if field is not None and not args.no_density:
+        bb = binit()
+        vx, vy, vz = 16, 16, 8
+        dshape = api.voxel_shape(S, H, W, vx, vy, vz)
+        drng = np.random.default_rng(11)
+        dtarget = torch.from_numpy(drng.uniform(0.0, 0.5, size=dshape).astype(np.float32)).to(dev)
+        dgrad = torch.empty_like(field)
+        api.slice_density(bb, field, vx, vy, vz)                  # warm-up
+        api.slice_density_loss(bb, field, dtarget, 0.05, vx, vy, vz, grad_field=dgrad)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record()
+        dvox = api.slice_density(bb, field, vx, vy, vz)
+        ev[1].record()
+        ev[2].record()
+        api.slice_density_loss(bb, field, dtarget, 0.05, vx, vy, vz, grad_field=dgrad)
+        ev[3].record()
+        torch.cuda.synchronize()
+        d_ms, l_ms = ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])
+        fbytes = S * H * W * esize
+        nvox = dshape[0] * dshape[1] * dshape[2]
+        dens = {"voxel": [vx, vy, vz], "voxels": nvox,
+                "density_ms": d_ms,
+                "density_GBps": (fbytes + 4 * nvox) / (d_ms * 1e-3) / 1e9,
+                "loss_grad_ms": l_ms,
+                # two reads of the field, one write of dL/dg, voxel-sized arrays
+                "loss_grad_GBps": (3 * fbytes + 24 * nvox) / (l_ms * 1e-3) / 1e9,
+                "mean_density": float(dvox.mean())}
+        del bb, dgrad, dvox
+        print(f"[bench] density {d_ms:.2f} ms, loss+grad {l_ms:.2f} ms", file=sys.stderr,
+              flush=True)
+
     # self-support metrics and dGamma/dv of the lattice (Sec. 5.2), timed
     api.lattice_support(nodes, edges, weight, grad=True)        # warm-up
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -323,6 +359,7 @@ def main():
         "stages": stages,
         "polylines": poly,
         "support": support,
+        "density": dens,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -239,6 +239,47 @@ lsl_status slice_polylines(const lattice_bins* bins, int32_t nk, const void* fie
                            void* stream);
 
 /* ---------------------------------------------------------------------------
+ * slice_density -- per-voxel material density of the sliced solid
+ * (Sec. 5, Eq. 9), by Monte-Carlo integration of the inside test.
+ *
+ * The samples are the pixel centres of the slice planes (a stratified
+ * sample on the slicing grid).  `field` is [nk][H][W] in the lattice dtype
+ * (from slice_field or slice_batch); voxel (l, j, i) holds its planes
+ * [l vz, (l+1) vz), rows [j vy, (j+1) vy) and columns [i vx, (i+1) vx),
+ * clipped at the field's last plane, row and column, so a field that starts
+ * at plane k0 gives voxels aligned to k0.  density: [nz][ny][nx] float32,
+ * nz = ceil(nk / vz), ny = ceil(H / vy), nx = ceil(W / vx): the fraction of
+ * the voxel's samples with g >= C, C rounded to the field's dtype, computed
+ * as count / samples in float64 and rounded once to float32.  Bitwise
+ * deterministic.  Stream-ordered, no allocation.  LSL_EINVAL on extents < 1.
+ * ------------------------------------------------------------------------- */
+lsl_status slice_density(const lattice_bins* bins, int32_t nk, const void* field,
+                         int32_t vx, int32_t vy, int32_t vz, float* density,
+                         void* stream);
+
+/* ---------------------------------------------------------------------------
+ * slice_density_loss -- a smooth voxel-density loss and its field gradient,
+ * the forward half of a density-matching step by gradient descent on the
+ * strut weights (Sec. 5.3 tunes the radii toward per-voxel targets).
+ *
+ * Voxels and field as in slice_density; the inside test is replaced by
+ * s = sigmoid((g - C) / tau), tau > 0.  soft_density = per-voxel mean of s.
+ * loss = sum_v (soft_density_v - target_v)^2 (one float64 on the device).
+ * grad_field = dL/dg = 2 (soft_density_v - target_v) / n_v * s (1 - s) / tau
+ * at every pixel ([nk][H][W], lattice dtype; n_v the voxel's sample count),
+ * ready for slice_field_backward.  target: [nz][ny][nx] float32 on the
+ * device.  soft_density ([nz][ny][nx] float32), grad_field and loss are each
+ * optional (NULL: not written).  Sums run in a fixed order (bitwise
+ * repeatable).  Stream-ordered; keeps a scratch buffer of one float64 per
+ * voxel on the bins handle (it grows, synchronising `stream`, when a call
+ * needs more).  LSL_EINVAL on extents < 1 or tau <= 0.
+ * ------------------------------------------------------------------------- */
+lsl_status slice_density_loss(const lattice_bins* bins, int32_t nk, const void* field,
+                              int32_t vx, int32_t vy, int32_t vz, const float* target,
+                              double tau, float* soft_density, void* grad_field,
+                              double* loss, void* stream);
+
+/* ---------------------------------------------------------------------------
  * slice_field_backward -- gradient of a loss of the sliced field.
  *
  * Given grad_field = dL/dg at the pixels of planes k0 .. k0+nk-1

@@ -68,6 +68,11 @@ SIGNATURES = {
                                  c_void_p, POINTER(c_int64), c_void_p]),
     "slice_polylines": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int64, c_void_p,
                                   c_void_p, c_void_p, POINTER(c_int64), c_void_p]),
+    "slice_density": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_int32, c_int32,
+                                c_void_p, c_void_p]),
+    "slice_density_loss": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_int32, c_int32,
+                                     c_void_p, c_double, c_void_p, c_void_p, c_void_p,
+                                     c_void_p]),
     "slice_field_backward": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p,
                                        c_void_p, c_int32, c_void_p]),
     "slice_batch": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p,

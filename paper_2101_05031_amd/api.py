@@ -180,11 +180,63 @@ def slice_polylines(bins: Bins, field, capacity: int | None = None, chains: bool
     return segs[:n], off, None if chain is None else chain[:n], None if rank is None else rank[:n]
 
 
+def voxel_shape(nk: int, H: int, W: int, vx: int, vy: int, vz: int) -> tuple:
+    """(nz, ny, nx): voxels of vz x vy x vx samples over a [nk, H, W] field,
+    partial ones at the far borders."""
+    return (-(-nk // vz), -(-H // vy), -(-W // vx))
+
+
+def _check_field(bins: Bins, field):
+    if (field.dim() != 3 or not field.is_contiguous() or field.dtype != bins.dtype
+            or field.shape[1] != bins.grid.H or field.shape[2] != bins.grid.W):
+        raise ValueError("field must be a contiguous [nk, H, W] tensor of the lattice dtype")
+
+
+def slice_density(bins: Bins, field, vx: int, vy: int, vz: int, out=None, stream=None):
+    """Per-voxel density (Sec. 5, Eq. 9) of the planes field[nk, H, W]: the
+    fraction of each voxel's pixel-centre samples with g >= C -> float32
+    [nz, ny, nx]."""
+    _check_field(bins, field)
+    nk = field.shape[0]
+    shape = voxel_shape(nk, bins.grid.H, bins.grid.W, vx, vy, vz)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device="cuda")
+    N.check(N.lib().slice_density(bins.handle, nk, _ptr(field), int(vx), int(vy), int(vz),
+                                  _ptr(out), _stream(stream)), "slice_density")
+    return out
+
+
+def slice_density_loss(bins: Bins, field, target, tau: float, vx: int, vy: int, vz: int,
+                       grad_field=None, soft=None, loss=None, want_grad: bool = True,
+                       stream=None):
+    """Soft voxel-density loss of field[nk, H, W] against target[nz, ny, nx]
+    (float32): returns (loss float64 [1] on the device, soft density float32
+    [nz, ny, nx], dL/dg [nk, H, W] in the lattice dtype or None)."""
+    _check_field(bins, field)
+    nk = field.shape[0]
+    shape = voxel_shape(nk, bins.grid.H, bins.grid.W, vx, vy, vz)
+    if tuple(target.shape) != shape or target.dtype != torch.float32 or not target.is_contiguous():
+        raise ValueError(f"target must be a contiguous float32 tensor of shape {shape}")
+    if soft is None:
+        soft = torch.empty(shape, dtype=torch.float32, device="cuda")
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    if grad_field is None and want_grad:
+        grad_field = torch.empty_like(field)
+    N.check(N.lib().slice_density_loss(bins.handle, nk, _ptr(field), int(vx), int(vy), int(vz),
+                                       _ptr(target), float(tau), _ptr(soft), _ptr(grad_field),
+                                       _ptr(loss), _stream(stream)), "slice_density_loss")
+    return loss, soft, grad_field
+
+
 def slice_field_backward(bins: Bins, k0: int, nk: int, grad_field, grad_weight=None,
-                         grad_nodes=None, accumulate: bool = False, stream=None):
+                         grad_nodes=None, accumulate: bool = False, want_nodes: bool = True,
+                         stream=None):
+    """dL/dw [n_edges] and dL/dv [n_nodes, 3] (None when want_nodes is False)
+    from dL/dg at the pixels of planes k0 .. k0+nk-1."""
     if grad_weight is None:
         grad_weight = torch.empty(bins.n_edges, dtype=bins.dtype, device="cuda")
-    if grad_nodes is None:
+    if grad_nodes is None and want_nodes:
         grad_nodes = torch.empty((bins.n_nodes, 3), dtype=bins.dtype, device="cuda")
     if not grad_field.is_contiguous() or grad_field.dtype != bins.dtype:
         raise ValueError("grad_field must be contiguous with the lattice dtype")

@@ -13,7 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblsl.so")
 SOURCES = ["primitives.hip", "prep.hip", "bin.hip", "field.hip", "contours.hip",
-           "backward.hip", "batch.hip", "probe.hip", "support.hip", "api.cpp", "autotune.cpp"]
+           "backward.hip", "batch.hip", "probe.hip", "support.hip", "density.hip",
+           "api.cpp", "autotune.cpp"]
 ARCH = os.environ.get("LSL_OFFLOAD_ARCH", "gfx950")
 
 

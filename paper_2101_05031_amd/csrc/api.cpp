@@ -180,6 +180,8 @@ struct lattice_bins {
     size_t cbits_elems = 0;
     uint32_t* pscratch = nullptr;     // slice_polylines: edges, cells, links, jumps
     size_t pscratch_elems = 0;
+    double* dscratch = nullptr;       // slice_density_loss: residuals, block partials
+    size_t dscratch_elems = 0;
     uint32_t* queue_buf = nullptr;     // persistent path: keys/vals/alternates + counter
     size_t queue_cap = 0;
     std::vector<std::pair<void*, size_t>> allocs;
@@ -1001,6 +1003,41 @@ lsl_status slice_polylines(const lattice_bins* cb, int32_t nk, const void* field
     }
     return launch_polylines(img, field, b->dtype, b->C, nk, b->grid.W, b->grid.H, b->ctmp, offsets,
                             (uint64_t)tot, rounds, segs, b->pscratch, chain, rank, st);
+}
+
+lsl_status slice_density(const lattice_bins* b, int32_t nk, const void* field, int32_t vx,
+                         int32_t vy, int32_t vz, float* density, void* stream) {
+    set_error("");
+    LSL_CHECK(b != nullptr, "bins handle is NULL");
+    LSL_CHECK(field != nullptr && density != nullptr, "field and density are required");
+    DensityArgs a{};
+    LSL_TRY(density_plan(nk, b->grid.W, b->grid.H, vx, vy, vz, &a));
+    return launch_density(b->dtype, a, field, b->C, density, S(stream));
+}
+
+lsl_status slice_density_loss(const lattice_bins* cb, int32_t nk, const void* field, int32_t vx,
+                              int32_t vy, int32_t vz, const float* target, double tau,
+                              float* soft_density, void* grad_field, double* loss,
+                              void* stream) {
+    set_error("");
+    LSL_CHECK(cb != nullptr, "bins handle is NULL");
+    LSL_CHECK(field != nullptr && target != nullptr, "field and target are required");
+    LSL_CHECK(std::isfinite(tau) && tau > 0.0, "tau must be finite and > 0");
+    lattice_bins* b = const_cast<lattice_bins*>(cb);   // scratch only
+    hipStream_t st = S(stream);
+    DensityArgs a{};
+    LSL_TRY(density_plan(nk, b->grid.W, b->grid.H, vx, vy, vz, &a));
+    const size_t need = density_scratch_elems(a);
+    if (need > b->dscratch_elems) {
+        LSL_HIP(hipStreamSynchronize(st));
+        b->release(b->dscratch);
+        b->dscratch = nullptr;
+        b->dscratch_elems = 0;
+        LSL_TRY(b->alloc_t(&b->dscratch, need));
+        b->dscratch_elems = need;
+    }
+    return launch_density_loss(b->dtype, a, field, b->C, tau, target, soft_density, grad_field,
+                               loss, b->dscratch, st);
 }
 
 }  // extern "C"

@@ -219,4 +219,24 @@ struct SupportArgs {
 size_t support_part_elems(int64_t n_edges);
 lsl_status launch_support(int dtype, const SupportArgs& a, hipStream_t st);
 
+// ---------------------------------------------------------------- density.hip
+// Per-voxel density (Sec. 5, Eq. 9) and the soft voxel-density loss.
+struct DensityArgs {
+    int32_t nk, W, H;                 // field planes and plane size
+    int32_t vx, vy, vz;               // voxel extents, clipped to the field
+    int32_t nx, ny, nz;               // voxels per axis
+    int32_t vpb, nbx;                 // voxel columns per block, blocks per voxel row
+    uint32_t n_blocks;
+};
+lsl_status density_plan(int32_t nk, int32_t W, int32_t H, int32_t vx, int32_t vy, int32_t vz,
+                        DensityArgs* a);
+size_t density_voxels(const DensityArgs& a);
+// doubles: residuals [voxels] + per-block partial losses [n_blocks]
+size_t density_scratch_elems(const DensityArgs& a);
+lsl_status launch_density(int dtype, const DensityArgs& a, const void* field, double C,
+                          float* out, hipStream_t st);
+lsl_status launch_density_loss(int dtype, const DensityArgs& a, const void* field, double C,
+                               double tau, const float* target, float* soft, void* grad,
+                               double* loss, double* scratch, hipStream_t st);
+
 }  // namespace lsl
