@@ -22,7 +22,11 @@ implementation evaluating the same formulas gets the same integers:
   tile range   [i0 // T, i1 // T] x [j0 // T, j1 // T]
 
   The edge list order is ascending (z of the lower end in the input's own
-  precision, id).  A bucket (slab, tile_y, tile_x) holds every binned strut
+  precision, id).  With per-strut supports R_i (R given as an array), lo and
+  hi use R_i and the order is ascending (first slab, z of the lower end, id):
+  the first slab then no longer follows from z alone, and a slab's window
+  must stay a prefix of the list.  With one R the first slab is a monotone
+  function of z, so both orders coincide.  A bucket (slab, tile_y, tile_x) holds every binned strut
   whose ranges cover it, in edge-list order.  Buckets are numbered row-major
   within a slab, slabs in order.
 """
@@ -47,7 +51,7 @@ def axis_range(lo, hi, origin: float, step: float, n: int):
     return i0, i1, ok
 
 
-def strut_ranges(nodes, edges, weight, R: float, grid, tile: int, slab: int):
+def strut_ranges(nodes, edges, weight, R, grid, tile: int, slab: int):
     """Per-strut ranges.  Returns a dict of int64 arrays (slab0, slab1, tx0,
     tx1, ty0, ty1), the boolean mask `binned`, and `order`: the ids of the
     binned struts in edge-list order."""
@@ -55,8 +59,10 @@ def strut_ranges(nodes, edges, weight, R: float, grid, tile: int, slab: int):
     a = nd[edges[:, 0]].astype(np.float64)
     b = nd[edges[:, 1]].astype(np.float64)
     w = np.asarray(weight)
-    lo = np.minimum(a, b) - R
-    hi = np.maximum(a, b) + R
+    per_strut = np.ndim(R) > 0
+    Rc = np.asarray(R, dtype=np.float64)[:, None] if per_strut else R
+    lo = np.minimum(a, b) - Rc
+    hi = np.maximum(a, b) + Rc
     k0, k1, okz = axis_range(lo[:, 2], hi[:, 2], grid.z0, grid.dz, grid.n_slices)
     i0, i1, okx = axis_range(lo[:, 0], hi[:, 0], grid.x0, grid.dx, grid.W)
     j0, j1, oky = axis_range(lo[:, 1], hi[:, 1], grid.y0, grid.dy, grid.H)
@@ -66,7 +72,10 @@ def strut_ranges(nodes, edges, weight, R: float, grid, tile: int, slab: int):
     zin = nd[:, 2]
     zlo_in = np.minimum(zin[edges[:, 0]], zin[edges[:, 1]])
     ids = np.nonzero(binned)[0]
-    order = ids[np.lexsort((ids, zlo_in[ids]))]
+    if per_strut:
+        order = ids[np.lexsort((ids, zlo_in[ids], (k0 // slab)[ids]))]
+    else:
+        order = ids[np.lexsort((ids, zlo_in[ids]))]
     return dict(slab0=k0 // slab, slab1=k1 // slab, tx0=i0 // tile, tx1=i1 // tile,
                 ty0=j0 // tile, ty1=j1 // tile, binned=binned, order=order,
                 k0=k0, k1=k1)

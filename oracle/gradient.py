@@ -10,7 +10,8 @@ gives
   dL/dr_i   = sum_p G(p) I_i(p)
   dL/dv     = sum_p G(p) r_i dI_i/dv        for each end v of strut i,
 
-with I_i the integral of Eq. (6) for strut i.  Below, the strut (a, b) is
+with I_i the integral of Eq. (6) for strut i (R may be one support or an
+array of per-strut supports).  Below, the strut (a, b) is
 described along its unit direction u with the foot of p as origin: the ends
 sit at alpha = (a - p).u and beta = alpha + |b - a|; the support meets the
 line on [-h, h] with h^2 = H = R^2 - |q|^2 + alpha^2 (q = a - p); and
@@ -33,7 +34,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .field import strut_integral
+from .field import strut_integral, support_of
 
 
 def strut_partials(P, a, b, R: float):
@@ -79,7 +80,7 @@ def strut_partials(P, a, b, R: float):
     return I, dI_da, dI_db
 
 
-def field_vjp(points, G, nodes, edges, weight, R: float, struts=None):
+def field_vjp(points, G, nodes, edges, weight, R, struts=None):
     """Gradient of L = sum_p G(p) g(p) with respect to the weights [E] and the
     node positions [N,3], float64.  `struts` limits the work to struts that
     can be non-zero at the points (others have zero gradient)."""
@@ -94,7 +95,7 @@ def field_vjp(points, G, nodes, edges, weight, R: float, struts=None):
         if w[i] == 0.0:
             continue
         ia, ib = int(edges[i, 0]), int(edges[i, 1])
-        I, dA, dB = strut_partials(P, nodes64[ia], nodes64[ib], R)
+        I, dA, dB = strut_partials(P, nodes64[ia], nodes64[ib], support_of(R, i))
         gw[i] = np.dot(G, I)
         gn[ia] += w[i] * (G @ dA)
         gn[ib] += w[i] * (G @ dB)
@@ -114,7 +115,7 @@ def soft_occupancy_loss(g, target, C: float, tau: float) -> float:
     return float(np.sum((s - target) ** 2))
 
 
-def slice_vjp(nodes, edges, weight, R: float, grid, ks, G):
+def slice_vjp(nodes, edges, weight, R, grid, ks, G):
     """field_vjp over the pixel centres of planes ks with G [len(ks), H, W]:
     each active strut (Eq. 8) is evaluated over the window of pixels its
     support can reach (outside it every term and partial is exactly zero)."""
@@ -133,16 +134,17 @@ def slice_vjp(nodes, edges, weight, R: float, grid, ks, G):
                 continue
             ia, ib = int(edges[i, 0]), int(edges[i, 1])
             a, b = nodes64[ia], nodes64[ib]
-            ix0, ix1 = _pixel_window(min(a[0], b[0]) - R, max(a[0], b[0]) + R,
+            Ri = support_of(R, i)
+            ix0, ix1 = _pixel_window(min(a[0], b[0]) - Ri, max(a[0], b[0]) + Ri,
                                      grid.x0, grid.dx, grid.W)
-            iy0, iy1 = _pixel_window(min(a[1], b[1]) - R, max(a[1], b[1]) + R,
+            iy0, iy1 = _pixel_window(min(a[1], b[1]) - Ri, max(a[1], b[1]) + Ri,
                                      grid.y0, grid.dy, grid.H)
             if ix0 > ix1 or iy0 > iy1:
                 continue
             X, Y = np.meshgrid(xs[ix0:ix1 + 1], ys[iy0:iy1 + 1], indexing="xy")
             P = np.stack([X, Y, np.full_like(X, z)], axis=-1).reshape(-1, 3)
             g = Gk[iy0:iy1 + 1, ix0:ix1 + 1].reshape(-1)
-            I, dA, dB = strut_partials(P, a, b, R)
+            I, dA, dB = strut_partials(P, a, b, Ri)
             gw[i] += np.dot(g, I)
             gn[ia] += w[i] * (g @ dA)
             gn[ib] += w[i] * (g @ dB)

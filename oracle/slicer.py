@@ -10,12 +10,16 @@ Test infrastructure (see the package docstring).
   active list, as a second route to the same sets.
 * slice_field: Step 4, the field at every pixel centre of one plane using the
   active struts only; inside where the sum reaches the iso-value.
+
+R is one support for every strut, or an array with one per strut (the
+per-strut variant); the sweep then keeps the list sorted by z_lo - R_i, the
+lower end of each swept sphere, which is z_lo ordering when R is shared.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .field import strut_integral
+from .field import strut_term, support_of
 
 
 def slice_heights(z0: float, t: float, n: int) -> np.ndarray:
@@ -30,25 +34,28 @@ def strut_z_range(nodes, edges):
     return np.minimum(za, zb), np.maximum(za, zb)
 
 
-def active_set(zlo, zhi, R: float, z: float) -> np.ndarray:
-    """Eq. (8): ids j with v_s^z - R <= z and v_e^z + R >= z, ascending."""
+def active_set(zlo, zhi, R, z: float) -> np.ndarray:
+    """Eq. (8): ids j with v_s^z - R <= z and v_e^z + R >= z, ascending
+    (R per strut when given as an array)."""
     return np.nonzero((zlo - R <= z) & (zhi + R >= z))[0]
 
 
-def sweep_active_sets(zlo, zhi, R: float, heights):
+def sweep_active_sets(zlo, zhi, R, heights):
     """Steps 1-6: returns the active set (ascending ids) of every plane."""
-    order = np.argsort(zlo, kind="stable")     # list sorted by lower z
+    Rv = np.broadcast_to(np.asarray(R, dtype=np.float64), np.shape(zlo))
+    bottom = zlo - Rv                          # lower end of each swept sphere
+    order = np.argsort(bottom, kind="stable")  # the list sorted by it
     m = len(order)
     k = 0                                      # first edge not yet added
     active: list[int] = []
     out = []
     for z in heights:
         # Step 2: add edges until one lies completely above the plane
-        while k < m and not (zlo[order[k]] - R > z):
+        while k < m and not (bottom[order[k]] > z):
             active.append(int(order[k]))
             k += 1
         # Step 3: drop edges lying completely below the plane
-        active = [j for j in active if not (zhi[j] + R < z)]
+        active = [j for j in active if not (zhi[j] + Rv[j] < z)]
         out.append(np.array(sorted(active), dtype=np.int64))
     return out
 
@@ -62,12 +69,13 @@ def _pixel_window(lo, hi, origin, step, n):
     return max(i0, 0), min(i1, n - 1)
 
 
-def slice_field(nodes, edges, weight, R: float, grid, k: int,
-                struts=None) -> np.ndarray:
+def slice_field(nodes, edges, weight, R, grid, k: int, struts=None,
+                kind: str = "quartic", sigma: float | None = None) -> np.ndarray:
     """g at every pixel centre of plane k: array [H, W] float64, g[j, i] at
     (x0 + (i+1/2) dx, y0 + (j+1/2) dy).  Struts of the active set (Eq. 8)
     are added in ascending id, each over the window of pixels its support
-    can reach; outside that window its term is exactly zero."""
+    can reach; outside that window its term is exactly zero.  R: one support
+    or one per strut; kind, sigma: the kernel (see field.strut_term)."""
     nodes = np.asarray(nodes, dtype=np.float64)
     weight = np.asarray(weight, dtype=np.float64)
     z = float(grid.slice_z(k))
@@ -81,15 +89,16 @@ def slice_field(nodes, edges, weight, R: float, grid, k: int,
             continue
         a = nodes[edges[i, 0]]
         b = nodes[edges[i, 1]]
-        ix0, ix1 = _pixel_window(min(a[0], b[0]) - R, max(a[0], b[0]) + R,
+        Ri = support_of(R, i)
+        ix0, ix1 = _pixel_window(min(a[0], b[0]) - Ri, max(a[0], b[0]) + Ri,
                                  grid.x0, grid.dx, grid.W)
-        iy0, iy1 = _pixel_window(min(a[1], b[1]) - R, max(a[1], b[1]) + R,
+        iy0, iy1 = _pixel_window(min(a[1], b[1]) - Ri, max(a[1], b[1]) + Ri,
                                  grid.y0, grid.dy, grid.H)
         if ix0 > ix1 or iy0 > iy1:
             continue
         X, Y = np.meshgrid(xs[ix0:ix1 + 1], ys[iy0:iy1 + 1], indexing="xy")
         P = np.stack([X, Y, np.full_like(X, z)], axis=-1)
-        g[iy0:iy1 + 1, ix0:ix1 + 1] += weight[i] * strut_integral(P, a, b, R)
+        g[iy0:iy1 + 1, ix0:ix1 + 1] += weight[i] * strut_term(P, a, b, Ri, kind, sigma)
     return g
 
 

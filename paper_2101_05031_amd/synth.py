@@ -35,7 +35,7 @@ import numpy as np
 __all__ = [
     "Lattice", "Grid", "bcc_lattice", "kuhn_lattice", "weight_for_radius",
     "graded_density", "blob_density", "grid_for", "config", "CONFIGS",
-    "target_density",
+    "target_density", "weight_for_radius_gauss", "with_supports", "with_gauss",
 ]
 
 
@@ -47,6 +47,9 @@ class Lattice:
     R: float               # kernel support radius
     C: float = 1.0         # iso-value
     radius: np.ndarray | None = None  # [E] physical radius the weight encodes
+    support: np.ndarray | None = None  # [E] per-strut supports (variant), else R for all
+    kernel: str = "quartic"            # "quartic" (Eq. 5) or "gauss" (variant)
+    sigma: float | None = None         # width of the Gaussian kernel
 
     @property
     def n_nodes(self) -> int:
@@ -92,6 +95,48 @@ def weight_for_radius(rho, R: float, C: float = 1.0) -> np.ndarray:
         raise ValueError("radius must lie in [0, R)")
     phi = 16.0 * (R * R - rho * rho) ** 2.5 / (15.0 * R ** 4)
     return C / phi
+
+
+def weight_for_radius_gauss(rho, R, sigma: float, C: float = 1.0) -> np.ndarray:
+    """The same convention for the compact Gaussian kernel
+    exp(-d^2/2s^2) - exp(-R^2/2s^2) (d < R): along an infinite line at
+    distance d it integrates to
+        exp(-d^2/2s^2) s sqrt(2 pi) erf(h / (s sqrt 2)) - exp(-R^2/2s^2) 2h,
+    h = sqrt(R^2 - d^2).  float64."""
+    from scipy.special import erf
+    rho = np.asarray(rho, dtype=np.float64)
+    R = np.asarray(R, dtype=np.float64)
+    if np.any(rho < 0) or np.any(rho >= R):
+        raise ValueError("radius must lie in [0, R)")
+    h = np.sqrt(R * R - rho * rho)
+    phi = (np.exp(-rho * rho / (2.0 * sigma * sigma)) * sigma * np.sqrt(2.0 * np.pi)
+           * erf(h / (sigma * np.sqrt(2.0))) - np.exp(-R * R / (2.0 * sigma * sigma)) * 2.0 * h)
+    return C / phi
+
+
+def with_supports(lat: "Lattice", factor: float = 1.5) -> "Lattice":
+    """The lattice with per-strut supports R_j = factor x rho_j (the paper's
+    1.5 x radius rule applied strut by strut) and weights that keep every
+    strut's radius; R becomes the largest support."""
+    rho = np.asarray(lat.radius, dtype=np.float64)
+    sup = factor * rho
+    live = np.asarray(lat.weight) != 0
+    w = np.where(live, weight_for_radius(rho, np.where(sup > 0, sup, 1.0), lat.C), 0.0)
+    sup = np.where(sup > 0, sup, float(np.max(sup)))
+    dt = lat.nodes.dtype
+    return dataclasses.replace(lat, weight=w.astype(dt), support=sup.astype(dt),
+                               R=float(np.max(sup)))
+
+
+def with_gauss(lat: "Lattice", sigma_frac: float = 1.0 / 3.0) -> "Lattice":
+    """The lattice under the compact Gaussian kernel of width sigma =
+    sigma_frac x R and support R, weights keeping every strut's radius."""
+    sigma = sigma_frac * lat.R
+    rho = np.asarray(lat.radius, dtype=np.float64)
+    live = np.asarray(lat.weight) != 0
+    w = np.where(live, weight_for_radius_gauss(rho, lat.R, sigma, lat.C), 0.0)
+    return dataclasses.replace(lat, weight=w.astype(lat.nodes.dtype), kernel="gauss",
+                               sigma=float(sigma))
 
 
 # ----------------------------------------------------------------------------
@@ -285,6 +330,8 @@ CONFIGS = {
     "D4": "Kuhn 25^3 in a 100 mm cube, graded r in [0.2,1.0], 64 slices over the height, 1024^2, FP32",
     "S5": "Kuhn 243^3 in a 200 mm cube, graded r in [0.1,0.6], 4000 slices at 0.05 mm, 8192^2, FP32",
     "M1": "Kuhn 52^3 in a 100 mm cube, graded r in [0.2,1.0], 1000 slices at 0.1 mm, 2048^2, FP32",
+    "M1R": "M1 with per-strut supports R_j = 1.5 r_j (kernel variant)",
+    "M1G": "M1 under the compact Gaussian kernel, sigma = R/3 (kernel variant)",
 }
 
 
@@ -310,6 +357,9 @@ def config(name: str, *, scale: int | None = None):
     if name == "M1":
         lat = kuhn_lattice(scale or 52, 100.0, seed=6)
         return lat, grid_for(lat, 2048, 2048, 1000, dz=0.1)
+    if name in ("M1R", "M1G"):
+        lat, grid = config("M1", scale=scale)
+        return (with_supports(lat) if name == "M1R" else with_gauss(lat)), grid
     raise KeyError(name)
 
 
