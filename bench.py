@@ -39,7 +39,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="M1", choices=["M1", "A2", "D4", "P1", "B3", "S5"])
+    ap.add_argument("--workload", default="M1",
+                    choices=["M1", "A2", "D4", "P1", "B3", "S5", "M1R", "M1G"])
     ap.add_argument("--no-field", action="store_true",
                     help="write bits and segments only (automatic when the field buffer "
                          "would exceed 48 GB); no backward step")
@@ -135,6 +136,13 @@ def main():
     print(f"[bench] workload {args.workload}: E={lat.n_edges} N={lat.n_nodes} "
           f"{S} planes of {W}x{H}", file=sys.stderr, flush=True)
 
+    # kernel variants: per-strut supports, the compact Gaussian (no adjoint)
+    variant = {}
+    if lat.support is not None:
+        variant["support"] = torch.from_numpy(lat.support).to(dev)
+    if lat.kernel != "quartic":
+        variant["kernel"], variant["sigma"] = lat.kernel, lat.sigma
+        args.no_backward = True
     esize = 8 if dtype == torch.float64 else 4
     keep_field = not args.no_field and S * H * W * esize <= 48e9
     if not keep_field:
@@ -149,12 +157,14 @@ def main():
     tile, slab = args.tile, args.slab
     autotuned = False
     if not tile:
-        p = api.slice_autotune(nodes, edges, weight, lat.R, lat.C, grid, slab=slab or 8)
+        p = api.slice_autotune(nodes, edges, weight, lat.R, lat.C, grid, slab=slab or 8,
+                               **variant)
         tile, slab, autotuned = p["tile"], p["slab"], True
         print(f"[bench] autotuned tile {tile}, slab {slab}", file=sys.stderr, flush=True)
 
     def binit():
-        return api.lattice_bin(nodes, edges, weight, lat.R, lat.C, grid, tile=tile, slab=slab)
+        return api.lattice_bin(nodes, edges, weight, lat.R, lat.C, grid, tile=tile, slab=slab,
+                               **variant)
 
     # size the segment buffer once (untimed)
     b = binit()
@@ -376,7 +386,11 @@ def main():
                       "at 0.05 mm, 4096x4096",
                 "S5": "Kuhn 243^3 in a 200 mm cube, 100,974,519 struts, 4000 planes at 0.05 mm, "
                       "8192x8192",
+                "M1R": "M1 with per-strut supports R_j = 1.5 x radius (kernel variant)",
+                "M1G": "M1 under the compact Gaussian kernel, sigma = R/3 (kernel variant)",
             }[args.workload],
+            "kernel": lat.kernel,
+            "per_strut_support": lat.support is not None,
             "n_struts": lat.n_edges, "planes": S, "grid": [W, H],
             "tile": info["tile"], "slab": info["slab"], "autotuned": autotuned,
             "field_output": keep_field, "peak_device_bytes": info["peak_device_bytes"],
@@ -422,20 +436,25 @@ def cpu_baseline(lat, grid):
     sub.W = min(side, grid.W)
     sub.H = min(side, grid.H)
     count = [0]
-    orig = OF.strut_integral
+    orig = OS.strut_term
+    assert orig is OF.strut_term
 
     def counting(*a, **kw):
         r = orig(*a, **kw)
         count[0] += int(np.count_nonzero(r))
         return r
 
-    OS.strut_integral = counting
+    R = lat.support if lat.support is not None else lat.R
+    OS.strut_term = counting
     try:
         t0 = time.perf_counter()
-        OS.slice_field(lat.nodes, lat.edges, lat.weight, lat.R, sub, k)
+        OS.slice_field(lat.nodes, lat.edges, lat.weight, R, sub, k, kind=lat.kernel,
+                       sigma=lat.sigma)
         dt = time.perf_counter() - t0
     finally:
-        OS.strut_integral = orig
+        OS.strut_term = orig
+    if count[0] == 0:
+        raise RuntimeError("cpu_baseline counted no useful pairs")
     return {"value": count[0] / dt, "unit": "pixel*strut evals/s", "cores": 1,
             "kind": "oracle",
             "sample": f"plane {k}, {sub.W}x{sub.H} pixel window ({count[0]} useful pairs, "

@@ -62,7 +62,21 @@ typedef struct lsl_lattice {
                                0 marks an absent strut (never binned)            */
     double R;               /* kernel support of Eq. (5), finite, > 0            */
     double C;               /* iso-value, finite, > 0                            */
+    /* Variants beyond the paper's single quartic kernel (zero-initialise for
+     * the paper's method):                                                   */
+    const void* support;    /* NULL: every strut's support is R.  Otherwise
+                               [n_edges] per-strut supports R_j (lattice
+                               dtype), finite, > 0; strut j then uses R_j in
+                               its kernel and its reach (R is not used)        */
+    int32_t kernel;         /* LSL_KERNEL_QUARTIC (Eq. (5)) or LSL_KERNEL_GAUSS:
+                               exp(-d^2/2 sigma^2) - exp(-R^2/2 sigma^2) for
+                               d < R, else 0 (the Gaussian the paper compares
+                               with, shifted and cut at the same support)     */
+    double sigma;           /* LSL_KERNEL_GAUSS only: width, finite, > 0, with
+                               every support <= 12 sigma                       */
 } lsl_lattice;
+
+enum { LSL_KERNEL_QUARTIC = 0, LSL_KERNEL_GAUSS = 1 };
 
 /* Pixel grid and slice planes.  [host] struct. */
 typedef struct lsl_grid {
@@ -125,13 +139,17 @@ typedef struct lsl_bins_info {
  * i1 = ceil(((max(a,b) + R) - o) * (1/s) - 0.5), clamped to [0, n-1]
  * (strut dropped if empty).  Slab range [k0/slab, k1/slab], tile range
  * [i0/tile, i1/tile] x [j0/tile, j1/tile].  A bucket (slab, tile_y, tile_x)
- * lists the struts covering it in edge-list order.
+ * lists the struts covering it in edge-list order.  With per-strut supports
+ * (lattice.support) R is R_j in these formulas and the edge list is ordered
+ * by (first slab, z of the lower end, id), which keeps each slab's window a
+ * prefix of the list; with one R that is the same order.
  *
  * On success *out holds a new handle.  Synchronises `stream` while it runs
  * (to read back the plan); the first group's bucket lists may still be in
  * flight on `stream` when it returns.  Errors: LSL_EINVAL (bad argument, edge index out of range,
- * negative or non-finite weight, non-finite node used by an edge),
- * LSL_ENOMEM, LSL_EDEVICE.
+ * negative or non-finite weight, non-finite node used by an edge, support
+ * not finite and > 0, unknown kernel, sigma not finite and > 0 or a support
+ * above 12 sigma), LSL_ENOMEM, LSL_EDEVICE.
  * ------------------------------------------------------------------------- */
 lsl_status lattice_bin(const lsl_lattice* lattice, const lsl_grid* grid,
                        const lsl_bin_params* params, lattice_bins** out,
@@ -292,6 +310,8 @@ lsl_status slice_density_loss(const lattice_bins* bins, int32_t nk, const void* 
  * grad_weight: [n_edges] lattice dtype (absent or unbinned struts get 0).
  * grad_nodes: [n_nodes][3] lattice dtype.  Either may be NULL.
  * accumulate: 0 overwrites the outputs, 1 adds to them.  Stream-ordered.
+ * Covers the quartic kernel, with one support or per-strut supports (held
+ * fixed); a handle of the Gaussian kernel gives LSL_EINVAL.
  * ------------------------------------------------------------------------- */
 lsl_status slice_field_backward(lattice_bins* bins, int32_t k0, int32_t nk,
                                 const void* grad_field, void* grad_weight,

@@ -18,10 +18,14 @@ LSL_F32 = 0
 LSL_F64 = 1
 
 
+LSL_KERNEL_QUARTIC, LSL_KERNEL_GAUSS = 0, 1
+
+
 class LslLattice(Structure):
     _fields_ = [("n_nodes", c_int64), ("n_edges", c_int64), ("dtype", c_int32),
                 ("nodes", c_void_p), ("edges", c_void_p), ("weight", c_void_p),
-                ("R", c_double), ("C", c_double)]
+                ("R", c_double), ("C", c_double), ("support", c_void_p),
+                ("kernel", c_int32), ("sigma", c_double)]
 
 
 class LslGrid(Structure):

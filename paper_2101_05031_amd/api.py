@@ -30,7 +30,11 @@ def _grid_struct(grid) -> N.LslGrid:
     return g
 
 
-def _lattice_struct(nodes, edges, weight, R, C) -> N.LslLattice:
+_KERNELS = {"quartic": N.LSL_KERNEL_QUARTIC, "gauss": N.LSL_KERNEL_GAUSS}
+
+
+def _lattice_struct(nodes, edges, weight, R, C, support=None, kernel: str = "quartic",
+                    sigma: float | None = None) -> N.LslLattice:
     if nodes.dtype not in _DTYPES:
         raise TypeError("nodes must be float32 or float64")
     for t, name in ((nodes, "nodes"), (edges, "edges"), (weight, "weight")):
@@ -49,6 +53,15 @@ def _lattice_struct(nodes, edges, weight, R, C) -> N.LslLattice:
     L.dtype = _DTYPES[nodes.dtype]
     L.nodes, L.edges, L.weight = nodes.data_ptr(), edges.data_ptr(), weight.data_ptr()
     L.R, L.C = float(R), float(C)
+    if support is not None:
+        if (not support.is_cuda or not support.is_contiguous() or support.dtype != nodes.dtype
+                or support.shape != (edges.shape[0],)):
+            raise ValueError("support must be a contiguous CUDA [E] tensor of the nodes' dtype")
+        L.support = support.data_ptr()
+    if kernel not in _KERNELS:
+        raise ValueError(f"kernel must be one of {sorted(_KERNELS)}")
+    L.kernel = _KERNELS[kernel]
+    L.sigma = float(sigma) if sigma is not None else 0.0
     return L
 
 
@@ -100,8 +113,11 @@ class Bins:
 
 
 def lattice_bin(nodes, edges, weight, R: float, C: float, grid, *, tile: int = 0,
-                slab: int = 0, max_pairs: int = 0, stream=None) -> Bins:
-    L = _lattice_struct(nodes, edges, weight, R, C)
+                slab: int = 0, max_pairs: int = 0, support=None, kernel: str = "quartic",
+                sigma: float | None = None, stream=None) -> Bins:
+    """Bin a lattice for slicing.  support: optional per-strut supports [E]
+    (then R is unused); kernel: "quartic" (Eq. 5) or "gauss" (width sigma)."""
+    L = _lattice_struct(nodes, edges, weight, R, C, support, kernel, sigma)
     g = _grid_struct(grid)
     p = N.LslBinParams(int(tile), int(slab), int(max_pairs))
     h = c_void_p()
@@ -264,8 +280,9 @@ def slice_batch(bins: Bins, k0: int, nk: int, field=None, bits=None, capacity: i
 
 
 def slice_autotune(nodes, edges, weight, R: float, C: float, grid, cache_path: str | None = None,
-                   tile: int = 0, slab: int = 0, stream=None) -> dict:
-    L = _lattice_struct(nodes, edges, weight, R, C)
+                   tile: int = 0, slab: int = 0, support=None, kernel: str = "quartic",
+                   sigma: float | None = None, stream=None) -> dict:
+    L = _lattice_struct(nodes, edges, weight, R, C, support, kernel, sigma)
     g = _grid_struct(grid)
     p = N.LslBinParams(int(tile), int(slab), 0)
     path = cache_path.encode() if cache_path else None

@@ -132,6 +132,9 @@ struct lattice_bins {
     int64_t n_nodes = 0, n_edges = 0;
     uint32_t n_binned = 0;
     double R = 0, C = 0;
+    bool strut_R = false;              // per-strut supports (in rec[].pad)
+    int32_t kernel = LSL_KERNEL_QUARTIC;
+    double sigma = 0;
     lsl_grid grid{};
     double inv_dx = 0, inv_dy = 0, inv_dz = 0;
     int32_t tile = 16, slab = 8, ntx = 0, nty = 0, n_slabs = 0;
@@ -264,6 +267,9 @@ namespace {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
 
+// Gaussian kernel: exp(R^2 / 2 sigma^2) must stay finite in float32
+constexpr double kMaxROverSigma = 12.0;
+
 lsl_status check_lattice(const lsl_lattice* L) {
     LSL_CHECK(L != nullptr, "lattice is NULL");
     LSL_CHECK(L->dtype == LSL_F32 || L->dtype == LSL_F64, "lattice dtype must be LSL_F32 or LSL_F64");
@@ -276,6 +282,13 @@ lsl_status check_lattice(const lsl_lattice* L) {
     LSL_CHECK(L->n_edges == 0 || L->weight != nullptr, "weight is NULL");
     LSL_CHECK(finite_pos(L->R), "R must be finite and > 0");
     LSL_CHECK(finite_pos(L->C), "C must be finite and > 0");
+    LSL_CHECK(L->kernel == LSL_KERNEL_QUARTIC || L->kernel == LSL_KERNEL_GAUSS,
+              "kernel must be LSL_KERNEL_QUARTIC or LSL_KERNEL_GAUSS");
+    if (L->kernel == LSL_KERNEL_GAUSS) {
+        LSL_CHECK(finite_pos(L->sigma), "sigma must be finite and > 0");
+        LSL_CHECK(L->support != nullptr || L->R <= kMaxROverSigma * L->sigma,
+                  "the support may be at most 12 sigma");
+    }
     return LSL_OK;
 }
 
@@ -425,6 +438,13 @@ FieldArgs field_args(const lattice_bins* b, int32_t k0, int32_t nk, void* field)
     a.z0 = b->grid.z0;
     a.dz = b->grid.dz;
     a.R = b->R;
+    a.strut_R = b->strut_R ? 1 : 0;
+    a.kernel = b->kernel;
+    if (b->kernel == LSL_KERNEL_GAUSS) {
+        a.gk1 = 1.0 / (b->sigma * std::sqrt(2.0));
+        a.gk2 = 1.0 / (2.0 * b->sigma * b->sigma);
+        a.gc0 = b->sigma * std::sqrt(std::acos(-1.0) / 2.0);
+    }
     a.C = b->C;
     a.field = field;
     a.bits_blk = nullptr;
@@ -526,6 +546,9 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
     b->n_edges = L->n_edges;
     b->R = L->R;
     b->C = L->C;
+    b->strut_R = L->support != nullptr;
+    b->kernel = L->kernel;
+    b->sigma = L->sigma;
     b->grid = *G;
     b->inv_dx = 1.0 / G->dx;
     b->inv_dy = 1.0 / G->dy;
@@ -547,6 +570,7 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
 
     // ---- prep: ranges, sort keys, plan histograms
     uint32_t *klo = nullptr, *khi = nullptr, *vals = nullptr, *ka = nullptr, *va = nullptr;
+    uint32_t* ks0 = nullptr;
     uint32_t *cnt = nullptr, *stmp = nullptr;
     SRange* rid = nullptr;
     unsigned long long* diff = nullptr;
@@ -557,6 +581,9 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
         (s = b->alloc_t(&stmp, radix_tmp_elems(En))))
         return fail(s);
     if (L->dtype == LSL_F64 && (s = b->alloc_t(&khi, En))) return fail(s);
+    // per-strut supports: first-slab keys by edge id, then the gathered keys
+    // and one alternate key/value pair for their sort
+    if (L->support && (s = b->alloc_t(&ks0, 3 * En))) return fail(s);
     uint32_t* cnt_lo = cnt;
     uint32_t* cnt_hi = cnt + ns;
     uint32_t* counters = cnt + 2 * ns;   // [0] n_binned, [1] err
@@ -591,6 +618,10 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
     pa.pair_diff = diff;
     pa.n_binned = counters;
     pa.err = counters + 1;
+    pa.support = L->support;
+    pa.key_s0 = ks0;
+    pa.max_r_over_sigma = L->kernel == LSL_KERNEL_GAUSS ? kMaxROverSigma : 0.0;
+    pa.sigma = L->sigma;
     if ((s = launch_prep(L->dtype, pa, st))) return fail(s);
 
     // edge list: stable sort by the lower end's z (64-bit keys in two passes)
@@ -608,6 +639,19 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
             int w2 = 0;
             if ((s = radix_sort_pairs(hk, sv, khi, hv, E, 32, stmp, &w2, st))) return fail(s);
             sv = w2 ? hv : sv;
+        }
+        if (ks0) {
+            // per-strut supports: the first slab is the major key (a stable
+            // sort over the z order), so each slab's window is a prefix
+            uint32_t* gk = ks0 + En;                  // keys in z order
+            uint32_t* ak = ks0;                       // alternates: the by-id keys
+            uint32_t* av = ks0 + 2 * En;              //   are no longer needed
+            if ((s = launch_gather_u32(ks0, sv, gk, E, st))) return fail(s);
+            int bits = 1;
+            while (bits < 32 && ((uint64_t)1 << bits) <= (uint64_t)ns) ++bits;
+            int w3 = 0;
+            if ((s = radix_sort_pairs(gk, sv, ak, av, E, bits, stmp, &w3, st))) return fail(s);
+            sv = w3 ? av : sv;
         }
         perm_src = sv;
     }
@@ -629,6 +673,8 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
         if (err & 1u) m += " edge index out of range;";
         if (err & 2u) m += " negative or non-finite weight;";
         if (err & 4u) m += " non-finite node position;";
+        if (err & 8u) m += " support radius not finite and > 0;";
+        if (err & 16u) m += " support radius above 12 sigma;";
         set_error(m);
         return fail(LSL_EINVAL);
     }
@@ -658,6 +704,9 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
         ga.ranges_by_id = rid;
         ga.n_binned = b->n_binned;
         ga.R = L->R;
+        ga.support = L->support;
+        ga.kernel = L->kernel;
+        ga.sigma = L->sigma;
         ga.rec = b->rec;
         ga.ranges = b->ranges;
         ga.w = b->w;
@@ -670,7 +719,7 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
         return fail(LSL_EDEVICE);
     }
     for (void* p : {(void*)klo, (void*)khi, (void*)vals, (void*)ka, (void*)va, (void*)rid,
-                    (void*)cnt, (void*)diff, (void*)stmp})
+                    (void*)cnt, (void*)diff, (void*)stmp, (void*)ks0})
         b->release(p);
 
     // ---- resident-group buffers sized for the largest group
@@ -1096,6 +1145,7 @@ BackArgs back_args(const lattice_bins* b, int g, int32_t k0, int32_t nk, int s_l
     a.z0 = b->grid.z0;
     a.dz = b->grid.dz;
     a.R = b->R;
+    a.strut_R = b->strut_R ? 1 : 0;
     a.emi = b->emi;
     a.grad = grad;
     a.partial = b->partial;
@@ -1203,6 +1253,8 @@ lsl_status slice_field_backward(lattice_bins* b, int32_t k0, int32_t nk, const v
     set_error("");
     LSL_TRY(check_range(b, k0, nk));
     LSL_CHECK(grad_field != nullptr, "grad_field is NULL");
+    LSL_CHECK(b->kernel == LSL_KERNEL_QUARTIC,
+              "slice_field_backward covers the quartic kernel only");
     hipStream_t st = S(stream);
     if (!b->acc) LSL_TRY(b->alloc_t(&b->acc, (size_t)std::max<uint32_t>(b->n_binned, 1) * 7));
     if (!b->partial) LSL_TRY(b->alloc(&b->partial, b->cap_pairs * 9 * b->esize()));
@@ -1242,6 +1294,7 @@ lsl_status slice_field_backward(lattice_bins* b, int32_t k0, int32_t nk, const v
             r.rec = b->rec;
             r.w = b->w;
             r.R = b->R;
+            r.strut_R = b->strut_R ? 1 : 0;
             r.acc = b->acc;
             return launch_reduce(b->dtype, r, b->ranges, G.sa, s_lo, s_hi, (uint32_t)G.pairs,
                                  b->n_binned, st);

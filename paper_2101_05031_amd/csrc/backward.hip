@@ -217,9 +217,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
     const T d2 = dX * dX + dY * dY;
     const T dX2 = dX + dX, dY2 = dY + dY;
     const double rb = 3.5 * sqrt(a.dx * a.dx + a.dy * a.dy);
-    const double thr = (a.R + rb) * (1.0 + 1e-7);
-    const double thr2 = thr * thr;
-    const double R2 = a.R * a.R;
     const uint64_t lt = lanes_below(lane);
     const int own = deposit_owner(lane);
     const StrutRec<T>* recs = (const StrutRec<T>*)a.rec;
@@ -271,12 +268,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
                                  mz = fma(tc, uz, -wz);
                     const double m2 = fma(mx, mx, fma(my, my, mz * mz));
                     const double ex = tc < 0.0 ? -tc : (tc > L ? tc - L : 0.0);
-                    if (valid && fma(ex, ex, m2) < thr2) {
+                    // the strut's support and the cull radius of the block
+                    const double Rs = a.strut_R ? (double)r.pad : a.R;
+                    const double thr = (Rs + rb) * (1.0 + 1e-7);
+                    if (valid && fma(ex, ex, m2) < thr * thr) {
                         planes |= 1u << k;
                         BPlane<T> P;
                         P.mx = (T)mx;
                         P.my = (T)my;
-                        P.H0 = (T)(R2 - m2);
+                        P.H0 = (T)(Rs * Rs - m2);
                         P.ntc = (T)(-tc);
                         P.nbtc = (T)(L - tc);
                         bp[lane][k] = P;
@@ -402,7 +402,8 @@ __global__ void k_reduce(ReduceArgs a, const SRange* ranges, int32_t sa, int32_t
         for (int q = 0; q < kParts; ++q) s[q] += (double)part[(size_t)e * kParts + q];
     const StrutRec<T> r = ((const StrutRec<T>*)a.rec)[p];
     const double w = (double)((const T*)a.w)[p];
-    const double R4 = a.R * a.R * a.R * a.R;
+    const double Rs = a.strut_R ? (double)r.pad : a.R;
+    const double R4 = Rs * Rs * Rs * Rs;
     const Line ln = strut_line(r);
     const double u[3] = {ln.ux, ln.uy, ln.uz};
     const double cw = w / R4;

@@ -19,7 +19,9 @@ constexpr int kBlockPix = 8;       // a wave evaluates one 8x8 pixel block
 // Per-strut records, in edge-list order (ascending z of the lower end).
 // ---------------------------------------------------------------------------
 // One strut: its ends a = v_s and b = v_e as given (the kernels form the
-// direction and length in float64) and the folded weight wq = r / R^4.
+// direction and length in float64), the folded weight wq = r / R^4 (the
+// Gaussian kernel: r exp(-R^2 / 2 sigma^2)) and, with per-strut supports,
+// its support R in pad.
 template <typename T>
 struct alignas(16) StrutRec {
     T ax, ay, az, wq;

@@ -20,6 +20,8 @@ struct Num<float> {
         return __builtin_fmaf(a, b, c);
     }
     static __device__ __forceinline__ float max_(float a, float b) { return __builtin_fmaxf(a, b); }
+    static __device__ __forceinline__ float erf_(float x) { return erff(x); }
+    static __device__ __forceinline__ float exp_(float x) { return expf(x); }
 };
 
 template <>
@@ -32,6 +34,8 @@ struct Num<double> {
         return __builtin_fma(a, b, c);
     }
     static __device__ __forceinline__ double max_(double a, double b) { return __builtin_fmax(a, b); }
+    static __device__ __forceinline__ double erf_(double x) { return erf(x); }
+    static __device__ __forceinline__ double exp_(double x) { return exp(x); }
 };
 
 // One (pixel, strut) term of the field, added to the compensated sum (s, c).
@@ -55,6 +59,26 @@ __device__ __forceinline__ T eval_term(const Stage<T>& e, T dX, T dY, T d2) {
     return (e.wq * D) * Q;
 }
 
+// The Gaussian variant's term: with the same H, h and clamped ends,
+//   wq [exp(H k2) c0 (erf(cb k1) - erf(ca k1)) - (cb - ca)],
+// wq = r exp(-R^2 k2), k1 = 1/(sigma sqrt 2), k2 = 1/(2 sigma^2),
+// c0 = sigma sqrt(pi/2): exp(H k2) wq / r = exp(-dist(p, line)^2 k2).  An
+// empty interval gives erf(x) - erf(x) = 0 and cb - ca = 0: an exact zero.
+template <typename T>
+__device__ __forceinline__ T eval_term_gauss(const Stage<T>& e, T dX, T dY, T d2, T k1, T k2,
+                                             T c0) {
+    using N = Num<T>;
+    const T du = N::fma_(dX, e.ux, dY * e.uy);
+    const T al = e.ntc - du;
+    const T be = e.nbtc - du;
+    const T H = N::fma_(du, du, N::fma_(e.mx2, dX, N::fma_(e.my2, dY, e.H0 - d2)));
+    const T h = N::sqrt_(N::max_(H, T(0)));
+    const T ca = N::clamp_(al, -h, h);
+    const T cb = N::clamp_(be, -h, h);
+    const T E = N::erf_(cb * k1) - N::erf_(ca * k1);
+    return e.wq * N::fma_(N::exp_(H * k2) * c0, E, ca - cb);
+}
+
 template <typename T>
 __device__ __forceinline__ void comp_add(T t, T& s, T& c) {
     const T sn = s + t;
@@ -64,7 +88,8 @@ __device__ __forceinline__ void comp_add(T t, T& s, T& c) {
 
 // One wave evaluates the 8x8 block `sub` of tile (tx, ty) over the planes of
 // `slab` that lie in [k0, k0+nk); `stage` is the wave's 64-entry LDS area.
-template <typename T, int SZ, bool STATS>
+// K: LSL_KERNEL_QUARTIC or LSL_KERNEL_GAUSS.
+template <typename T, int SZ, bool STATS, int K = LSL_KERNEL_QUARTIC>
 __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx, int ty, int sub,
                                             Stage<T>* stage) {
     const int lane = lane_id();
@@ -93,10 +118,8 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
     const T dY = (T)(((double)ly - 3.5) * a.dy);
     const T d2 = dX * dX + dY * dY;
     const double rb = 3.5 * sqrt(a.dx * a.dx + a.dy * a.dy);
-    const double thr = (a.R + rb) * (1.0 + 1e-7);
-    const double thr2 = thr * thr;
-    const double R2 = a.R * a.R;
     const uint64_t lt = lanes_below(lane);
+    const T gk1 = (T)a.gk1, gk2 = (T)a.gk2, gc0 = (T)a.gc0;
 
     T acc_s[SZ], acc_c[SZ];
 #pragma unroll
@@ -125,7 +148,12 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
                 const double mx = fma(tc, ux, -wx), my = fma(tc, uy, -wy), mz = fma(tc, uz, -wz);
                 const double m2 = fma(mx, mx, fma(my, my, mz * mz));
                 const double ex = tc < 0.0 ? -tc : (tc > L ? tc - L : 0.0);
-                const bool pass = valid && fma(ex, ex, m2) < thr2;
+                // the strut's support, and the cull radius of the block
+                // around it (formed here to keep no doubles live across the
+                // evaluation loop)
+                const double Rs = a.strut_R ? (double)r.pad : a.R;
+                const double thr = (Rs + rb) * (1.0 + 1e-7);
+                const bool pass = valid && fma(ex, ex, m2) < thr * thr;
                 const uint64_t mask = ballot64(pass);
                 if (mask == 0ull) continue;
                 if (pass) {
@@ -136,7 +164,7 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
                     s.uy = uyT;
                     s.ntc = (T)(-tc);
                     s.nbtc = (T)(L - tc);
-                    s.H0 = (T)(R2 - m2);
+                    s.H0 = (T)(Rs * Rs - m2);
                     s.wq = r.wq;
                     stage[__popcll(mask & lt)] = s;
                 }
@@ -144,7 +172,9 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
                 const int n = __popcll(mask);
                 T s_ = acc_s[k], c_ = acc_c[k];
                 for (int j = 0; j < n; ++j) {
-                    const T term = eval_term<T>(stage[j], dX, dY, d2);
+                    const T term = K == LSL_KERNEL_GAUSS
+                                       ? eval_term_gauss<T>(stage[j], dX, dY, d2, gk1, gk2, gc0)
+                                       : eval_term<T>(stage[j], dX, dY, d2);
                     comp_add(term, s_, c_);
                     if (STATS) n_useful += term > T(0) ? 1ull : 0ull;
                 }

@@ -25,7 +25,12 @@ struct PrepArgs {
     uint32_t* cnt_hi;                 // [n_slabs] struts whose last slab is s
     unsigned long long* pair_diff;    // [n_slabs + 1] difference array of pairs
     uint32_t* n_binned;
-    uint32_t* err;                    // bit 0 index, 1 weight, 2 node
+    uint32_t* err;                    // bit 0 index, 1 weight, 2 node, 3 support, 4 sigma
+    // variants
+    const void* support;              // [n_edges] per-strut supports, or null (R for all)
+    uint32_t* key_s0;                 // [n_edges] first slab (n_slabs if not binned), or null
+    double max_r_over_sigma;          // > 0: reject supports above this many sigma
+    double sigma;
 };
 lsl_status launch_prep(int dtype, const PrepArgs& a, hipStream_t st);
 
@@ -37,7 +42,10 @@ struct GatherArgs {
     const SRange* ranges_by_id;
     int64_t n_binned;
     double R;
-    void* rec;                        // StrutRec<T> [n_binned]
+    const void* support;              // per-strut supports or null
+    int32_t kernel;                   // LSL_KERNEL_*
+    double sigma;
+    void* rec;                        // StrutRec<T> [n_binned]; pad holds R_j with supports
     SRange* ranges;                   // [n_binned]
     void* w;                          // T [n_binned]
     int2* ends;                       // [n_binned]
@@ -101,6 +109,9 @@ struct FieldArgs {
     int32_t k0, nk;                   // planes written: [k0, k0+nk)
     int32_t W, H;
     double x0, y0, dx, dy, z0, dz, R;
+    int32_t strut_R;                  // 1: strut j's support is rec[j].pad, else R
+    int32_t kernel;                   // LSL_KERNEL_*
+    double gk1, gk2, gc0;             // Gaussian: 1/(sigma sqrt 2), 1/(2 sigma^2), sigma sqrt(pi/2)
     void* field;                      // [nk][H][W] or null (not written)
     uint64_t* bits_blk;               // [nk][ceil(H/8)][ceil(W/8)] or null: field >= C,
                                       // one word per 8x8 block (bit 8*row+col)
@@ -149,6 +160,7 @@ struct BackArgs {
     int32_t k0, nk;
     int32_t W, H;
     double x0, y0, dx, dy, z0, dz, R;
+    int32_t strut_R;                  // 1: strut j's support is rec[j].pad, else R
     const uint32_t* emi;              // bucket entry -> emission index
     const void* grad;                 // [nk][H][W]
     void* partial;                    // [n_pairs][9] T, in emission order
@@ -163,6 +175,7 @@ struct ReduceArgs {
     const void* rec;
     const void* w;
     double R;
+    int32_t strut_R;                  // 1: strut j's support is rec[j].pad, else R
     double* acc;                      // [n_binned][7]: dL/dw, dL/da (3), dL/db (3)
 };
 lsl_status launch_reduce(int dtype, const ReduceArgs& a, const SRange* ranges, int32_t sa,

@@ -79,6 +79,18 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
             atomicOr(a.err, 2u);
             bad = true;
         }
+        double Rs = a.R;                 // this strut's support
+        if (a.support) {
+            Rs = (double)((const T*)a.support)[e];
+            if (!(Rs > 0.0) || !isfinite(Rs)) {
+                atomicOr(a.err, 8u);
+                bad = true;
+            }
+        }
+        if (!bad && a.max_r_over_sigma > 0.0 && !(Rs <= a.max_r_over_sigma * a.sigma)) {
+            atomicOr(a.err, 16u);
+            bad = true;
+        }
         if (!bad) {
             const double ax = (double)nd[3 * ia], ay = (double)nd[3 * ia + 1],
                          az = (double)nd[3 * ia + 2];
@@ -88,11 +100,11 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
                 !isfinite(by) || !isfinite(bz)) {
                 atomicOr(a.err, 4u);
             } else if (w != T(0) && !(ax == bx && ay == by && az == bz)) {
-                const AxisRange rz = axis_range(fmin(az, bz) - a.R, fmax(az, bz) + a.R, a.z0,
+                const AxisRange rz = axis_range(fmin(az, bz) - Rs, fmax(az, bz) + Rs, a.z0,
                                                 a.inv_dz, a.S);
-                const AxisRange rx = axis_range(fmin(ax, bx) - a.R, fmax(ax, bx) + a.R, a.x0,
+                const AxisRange rx = axis_range(fmin(ax, bx) - Rs, fmax(ax, bx) + Rs, a.x0,
                                                 a.inv_dx, a.W);
-                const AxisRange ry = axis_range(fmin(ay, by) - a.R, fmax(ay, by) + a.R, a.y0,
+                const AxisRange ry = axis_range(fmin(ay, by) - Rs, fmax(ay, by) + Rs, a.y0,
                                                 a.inv_dy, a.H);
                 if (rz.ok && rx.ok && ry.ok) {
                     binned = true;
@@ -118,6 +130,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
         }
         a.key_lo[e] = klo;
         if (sizeof(T) == 8) a.key_hi[e] = khi;
+        if (a.key_s0) a.key_s0[e] = binned ? (uint32_t)rg.s0 : (uint32_t)a.n_slabs;
         a.vals[e] = (uint32_t)e;
         a.ranges[e] = rg;
     }
@@ -158,16 +171,20 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
     const int32_t ia = a.edges[2 * (size_t)e], ib = a.edges[2 * (size_t)e + 1];
     const T* nd = (const T*)a.nodes;
     const double w = (double)((const T*)a.weight)[e];
-    const double R2 = a.R * a.R;
+    const double Rs = a.support ? (double)((const T*)a.support)[e] : a.R;
+    const double R2 = Rs * Rs;
     StrutRec<T> r;
     r.ax = nd[3 * ia];
     r.ay = nd[3 * ia + 1];
     r.az = nd[3 * ia + 2];
-    r.wq = (T)(w / (R2 * R2));
+    // the weight folded with the kernel's constant: r / R^4 (Eq. 5), or
+    // r exp(-R^2 / 2 sigma^2) (Gaussian)
+    r.wq = a.kernel == LSL_KERNEL_GAUSS ? (T)(w * exp(-R2 / (2.0 * a.sigma * a.sigma)))
+                                        : (T)(w / (R2 * R2));
     r.bx = nd[3 * ib];
     r.by = nd[3 * ib + 1];
     r.bz = nd[3 * ib + 2];
-    r.pad = T(0);
+    r.pad = a.support ? ((const T*)a.support)[e] : T(0);
     ((StrutRec<T>*)a.rec)[p] = r;
     a.ranges[p] = a.ranges_by_id[e];
     ((T*)a.w)[p] = (T)w;

@@ -13,9 +13,20 @@ def to_dev(lat):
             torch.from_numpy(np.ascontiguousarray(lat.weight)).cuda())
 
 
+def variant_kw(lat):
+    """lattice_bin arguments for a lattice's kernel variant (per-strut
+    supports, Gaussian kernel), empty for the paper's kernel."""
+    kw = {}
+    if lat.support is not None:
+        kw["support"] = torch.from_numpy(np.ascontiguousarray(lat.support)).cuda()
+    if lat.kernel != "quartic":
+        kw["kernel"], kw["sigma"] = lat.kernel, lat.sigma
+    return kw
+
+
 def bin_lattice(lat, grid, **kw):
     n, e, w = to_dev(lat)
-    b = api.lattice_bin(n, e, w, lat.R, lat.C, grid, **kw)
+    b = api.lattice_bin(n, e, w, lat.R, lat.C, grid, **variant_kw(lat), **kw)
     torch.cuda.synchronize()
     return b
 
