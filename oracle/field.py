@@ -219,12 +219,8 @@ def field_at_point(p, nodes, edges, weight, R, struts=None, kind: str = "quartic
     ids = np.arange(len(edges)) if struts is None else np.asarray(struts)
     A = nodes[edges[ids, 0]]
     B = nodes[edges[ids, 1]]
+    # per-strut supports broadcast element by element with the struts
     Rs = np.asarray(R, dtype=np.float64)[ids] if np.ndim(R) else R
-    pt = np.asarray(p, dtype=np.float64)[None, :]
-    if np.ndim(Rs):
-        I = np.array([float(strut_term(pt, A[j], B[j], float(Rs[j]), kind, sigma)[0])
-                      for j in range(len(ids))])
-    else:
-        I = strut_term(pt, A, B, Rs, kind, sigma)
+    I = strut_term(np.asarray(p, dtype=np.float64)[None, :], A, B, Rs, kind, sigma)
     terms = np.asarray(weight, dtype=np.float64)[ids] * I
     return float(np.cumsum(terms)[-1]) if len(terms) else 0.0
