@@ -339,10 +339,12 @@ lsl_status slice_batch(lattice_bins* bins, int32_t k0, int32_t nk, void* field,
 
 /* ---------------------------------------------------------------------------
  * slice_autotune -- choose tile and slab sizes by binning with each
- * candidate and timing the binning plus the field on sampled plane windows
- * of this lattice and grid (the field time scaled to all planes).  params is [host] in/out:
+ * candidate and timing the binning (to the end of its device work, after one
+ * untimed warm-up binning) plus the field on sampled plane windows of this
+ * lattice and grid (the field time scaled to all planes).  params is [host] in/out:
  * nonzero fields are kept, zero fields are filled.  cache_path (optional,
- * [host] C string) is a JSON file of earlier choices keyed by problem shape;
+ * [host] C string) is a JSON file of earlier choices keyed by problem shape
+ * and kernel variant;
  * a hit skips the timing.  Synchronises `stream`.  The field values do not
  * depend on the choice (the same struts reach each pixel in the same order).
  * ------------------------------------------------------------------------- */

@@ -21,9 +21,10 @@ namespace {
 
 std::string shape_key(const lsl_lattice* L, const lsl_grid* G) {
     char buf[512];
-    std::snprintf(buf, sizeof(buf), "E%lld_N%lld_d%d_W%d_H%d_S%d_R%.6g_dx%.6g_dy%.6g_dz%.6g",
+    std::snprintf(buf, sizeof(buf),
+                  "E%lld_N%lld_d%d_W%d_H%d_S%d_R%.6g_dx%.6g_dy%.6g_dz%.6g_k%d_s%.6g_ps%d",
                   (long long)L->n_edges, (long long)L->n_nodes, L->dtype, G->W, G->H, G->n_slices,
-                  L->R, G->dx, G->dy, G->dz);
+                  L->R, G->dx, G->dy, G->dz, L->kernel, L->sigma, L->support ? 1 : 0);
     return buf;
 }
 
@@ -115,15 +116,27 @@ extern "C" lsl_status slice_autotune(const lsl_lattice* L, const lsl_grid* G,
     double best = 1e300;
     int bt = tiles[0], bs = slabs[0];
     lsl_status result = LSL_OK;
+    {
+        // warm-up: the first binning fills the device-memory cache, which
+        // would otherwise be charged to the first candidate
+        lsl_bin_params bp{tiles[0], slabs[0], P->max_pairs};
+        lattice_bins* b = nullptr;
+        if (lattice_bin(L, G, &bp, &b, stream) == LSL_OK) lattice_bins_free(b);
+        set_error("");
+    }
     for (int t : tiles) {
         for (int s : slabs) {
             lsl_bin_params bp{t, s, P->max_pairs};
             lattice_bins* b = nullptr;
             const auto c0 = std::chrono::steady_clock::now();
             lsl_status rs = lattice_bin(L, G, &bp, &b, stream);
+            // lattice_bin leaves the first group's lists in flight: wait for
+            // them, so the score carries the whole binning cost
+            if (rs == LSL_OK && hipStreamSynchronize(st) != hipSuccess) rs = LSL_EDEVICE;
             const double bin_s =
                 std::chrono::duration<double>(std::chrono::steady_clock::now() - c0).count();
             if (rs != LSL_OK) {
+                if (b) lattice_bins_free(b);
                 if (rs == LSL_ENOMEM) continue;    // candidate does not fit
                 result = rs;
                 break;
