@@ -182,7 +182,7 @@ __device__ __forceinline__ int deposit_owner(int lane) {
     return (lane & 7) == 0 ? scatter_index(lane) : -1;
 }
 
-template <typename T, int SZ>
+template <typename T, int SZ, bool SR>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_backward(BackArgs a, uint32_t n_items) {
     // compacted list of the struts that reach the current block
     __shared__ T bs_ux[kChunk], bs_uy[kChunk], bs_uz[kChunk];
@@ -217,6 +217,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
     const T d2 = dX * dX + dY * dY;
     const T dX2 = dX + dX, dY2 = dY + dY;
     const double rb = 3.5 * sqrt(a.dx * a.dx + a.dy * a.dy);
+    // one support: the cull radius of a block and R^2 are uniform
+    const double thr_u = (a.R + rb) * (1.0 + 1e-7);
+    const double thr2_u = thr_u * thr_u;
+    const double R2_u = a.R * a.R;
     const uint64_t lt = lanes_below(lane);
     const int own = deposit_owner(lane);
     const StrutRec<T>* recs = (const StrutRec<T>*)a.rec;
@@ -268,15 +272,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
                                  mz = fma(tc, uz, -wz);
                     const double m2 = fma(mx, mx, fma(my, my, mz * mz));
                     const double ex = tc < 0.0 ? -tc : (tc > L ? tc - L : 0.0);
-                    // the strut's support and the cull radius of the block
-                    const double Rs = a.strut_R ? (double)r.pad : a.R;
-                    const double thr = (Rs + rb) * (1.0 + 1e-7);
-                    if (valid && fma(ex, ex, m2) < thr * thr) {
+                    // per-strut supports: the strut's cull radius and R^2
+                    double thr2 = thr2_u, R2 = R2_u;
+                    if (SR) {
+                        const double Rs = (double)r.pad;
+                        const double thr = (Rs + rb) * (1.0 + 1e-7);
+                        thr2 = thr * thr;
+                        R2 = Rs * Rs;
+                    }
+                    if (valid && fma(ex, ex, m2) < thr2) {
                         planes |= 1u << k;
                         BPlane<T> P;
                         P.mx = (T)mx;
                         P.my = (T)my;
-                        P.H0 = (T)(Rs * Rs - m2);
+                        P.H0 = (T)(R2 - m2);
                         P.ntc = (T)(-tc);
                         P.nbtc = (T)(L - tc);
                         bp[lane][k] = P;
@@ -472,7 +481,10 @@ __global__ void k_fill_t(T* p, size_t n) {
 
 template <typename T, int SZ>
 lsl_status launch_b(const BackArgs& a, uint32_t n_items, hipStream_t st) {
-    k_backward<T, SZ><<<n_items, 64, 0, st>>>(a, n_items);
+    if (a.strut_R)
+        k_backward<T, SZ, true><<<n_items, 64, 0, st>>>(a, n_items);
+    else
+        k_backward<T, SZ, false><<<n_items, 64, 0, st>>>(a, n_items);
     LSL_HIP(hipGetLastError());
     return LSL_OK;
 }

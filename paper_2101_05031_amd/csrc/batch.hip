@@ -33,7 +33,7 @@ __global__ void k_queue_keys(FieldArgs a, uint32_t n_items, uint32_t* keys, uint
     vals[it] = it;
 }
 
-template <typename T, int SZ, int K>
+template <typename T, int SZ, int K, bool SR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_persistent(FieldArgs a, const uint32_t* queue,
                                                     uint32_t n_items, uint32_t* counter) {
     __shared__ Stage<T> stage[4][kWave];
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         const int ty = (int)(t % (uint32_t)a.nty);
         t /= (uint32_t)a.nty;
         for (int sub = wv; sub < nsub * nsub; sub += 4)
-            fieldk::field_block<T, SZ, false, K>(a, a.s_lo + (int)t, tx, ty, sub, stage[wv]);
+            fieldk::field_block<T, SZ, false, K, SR>(a, a.s_lo + (int)t, tx, ty, sub, stage[wv]);
     }
 }
 
@@ -62,8 +62,8 @@ int blocks_t() {
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<T, SZ, LSL_KERNEL_QUARTIC>,
-                                                     256, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per, k_persistent<T, SZ, LSL_KERNEL_QUARTIC, false>, 256, 0) !=
         hipSuccess)
         return 0;
     return cus * (per > 0 ? per : 1);
@@ -78,27 +78,30 @@ int blocks_dt(int slab) {
     return blocks_t<T, 16>();
 }
 
-template <typename T, int K>
+template <typename T, int K, bool SR>
 lsl_status persistent_dtk(const BatchArgs& b, int n_blocks, hipStream_t st) {
     const int s = b.f.slab;
     if (s <= 1)
-        k_persistent<T, 1, K><<<n_blocks, 256, 0, st>>>(b.f, b.queue, b.n_items, b.counter);
+        k_persistent<T, 1, K, SR><<<n_blocks, 256, 0, st>>>(b.f, b.queue, b.n_items, b.counter);
     else if (s <= 2)
-        k_persistent<T, 2, K><<<n_blocks, 256, 0, st>>>(b.f, b.queue, b.n_items, b.counter);
+        k_persistent<T, 2, K, SR><<<n_blocks, 256, 0, st>>>(b.f, b.queue, b.n_items, b.counter);
     else if (s <= 4)
-        k_persistent<T, 4, K><<<n_blocks, 256, 0, st>>>(b.f, b.queue, b.n_items, b.counter);
+        k_persistent<T, 4, K, SR><<<n_blocks, 256, 0, st>>>(b.f, b.queue, b.n_items, b.counter);
     else if (s <= 8)
-        k_persistent<T, 8, K><<<n_blocks, 256, 0, st>>>(b.f, b.queue, b.n_items, b.counter);
+        k_persistent<T, 8, K, SR><<<n_blocks, 256, 0, st>>>(b.f, b.queue, b.n_items, b.counter);
     else
-        k_persistent<T, 16, K><<<n_blocks, 256, 0, st>>>(b.f, b.queue, b.n_items, b.counter);
+        k_persistent<T, 16, K, SR><<<n_blocks, 256, 0, st>>>(b.f, b.queue, b.n_items, b.counter);
     LSL_HIP(hipGetLastError());
     return LSL_OK;
 }
 
 template <typename T>
 lsl_status persistent_dt(const BatchArgs& b, int n_blocks, hipStream_t st) {
-    return b.f.kernel == LSL_KERNEL_GAUSS ? persistent_dtk<T, LSL_KERNEL_GAUSS>(b, n_blocks, st)
-                                          : persistent_dtk<T, LSL_KERNEL_QUARTIC>(b, n_blocks, st);
+    if (b.f.kernel == LSL_KERNEL_GAUSS)
+        return b.f.strut_R ? persistent_dtk<T, LSL_KERNEL_GAUSS, true>(b, n_blocks, st)
+                           : persistent_dtk<T, LSL_KERNEL_GAUSS, false>(b, n_blocks, st);
+    return b.f.strut_R ? persistent_dtk<T, LSL_KERNEL_QUARTIC, true>(b, n_blocks, st)
+                       : persistent_dtk<T, LSL_KERNEL_QUARTIC, false>(b, n_blocks, st);
 }
 
 }  // namespace

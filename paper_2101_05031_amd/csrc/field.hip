@@ -33,7 +33,7 @@
 namespace lsl {
 namespace {
 
-template <typename T, int SZ, bool STATS, int K>
+template <typename T, int SZ, bool STATS, int K, bool SR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_field(FieldArgs a, uint32_t n_items) {
     __shared__ Stage<T> stage[4][kWave];
     const int wv = threadIdx.x >> 6;
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     t /= (uint32_t)a.ntx;
     const int ty = (int)(t % (uint32_t)a.nty);
     t /= (uint32_t)a.nty;
-    fieldk::field_block<T, SZ, STATS, K>(a, a.s_lo + (int)t, tx, ty, sub, stage[wv]);
+    fieldk::field_block<T, SZ, STATS, K, SR>(a, a.s_lo + (int)t, tx, ty, sub, stage[wv]);
 }
 
 // Block-major binary image of a field: one wave takes 8 rows x 64 columns
@@ -79,22 +79,24 @@ __global__ __launch_bounds__(256) void k_bits_blk(const T* field, int32_t nk, in
     if (lane < 8 && c * 8 + lane < nbx) out[kb * (uint64_t)nbx + (uint64_t)(c * 8 + lane)] = word;
 }
 
-template <typename T, int SZ, int K>
+template <typename T, int SZ, int K, bool SR>
 lsl_status launch_tk(const FieldArgs& a, bool stats, uint32_t n_items, hipStream_t st) {
     const unsigned blocks = (n_items + 3u) / 4u;
     if (stats)
-        k_field<T, SZ, true, K><<<blocks, 256, 0, st>>>(a, n_items);
+        k_field<T, SZ, true, K, SR><<<blocks, 256, 0, st>>>(a, n_items);
     else
-        k_field<T, SZ, false, K><<<blocks, 256, 0, st>>>(a, n_items);
+        k_field<T, SZ, false, K, SR><<<blocks, 256, 0, st>>>(a, n_items);
     LSL_HIP(hipGetLastError());
     return LSL_OK;
 }
 
 template <typename T, int SZ>
 lsl_status launch_t(const FieldArgs& a, bool stats, uint32_t n_items, hipStream_t st) {
-    return a.kernel == LSL_KERNEL_GAUSS
-               ? launch_tk<T, SZ, LSL_KERNEL_GAUSS>(a, stats, n_items, st)
-               : launch_tk<T, SZ, LSL_KERNEL_QUARTIC>(a, stats, n_items, st);
+    if (a.kernel == LSL_KERNEL_GAUSS)
+        return a.strut_R ? launch_tk<T, SZ, LSL_KERNEL_GAUSS, true>(a, stats, n_items, st)
+                         : launch_tk<T, SZ, LSL_KERNEL_GAUSS, false>(a, stats, n_items, st);
+    return a.strut_R ? launch_tk<T, SZ, LSL_KERNEL_QUARTIC, true>(a, stats, n_items, st)
+                     : launch_tk<T, SZ, LSL_KERNEL_QUARTIC, false>(a, stats, n_items, st);
 }
 
 template <typename T>

@@ -88,8 +88,9 @@ __device__ __forceinline__ void comp_add(T t, T& s, T& c) {
 
 // One wave evaluates the 8x8 block `sub` of tile (tx, ty) over the planes of
 // `slab` that lie in [k0, k0+nk); `stage` is the wave's 64-entry LDS area.
-// K: LSL_KERNEL_QUARTIC or LSL_KERNEL_GAUSS.
-template <typename T, int SZ, bool STATS, int K = LSL_KERNEL_QUARTIC>
+// K: LSL_KERNEL_QUARTIC or LSL_KERNEL_GAUSS; SR: per-strut supports (in the
+// record's pad) instead of one support R.
+template <typename T, int SZ, bool STATS, int K, bool SR>
 __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx, int ty, int sub,
                                             Stage<T>* stage) {
     const int lane = lane_id();
@@ -118,6 +119,10 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
     const T dY = (T)(((double)ly - 3.5) * a.dy);
     const T d2 = dX * dX + dY * dY;
     const double rb = 3.5 * sqrt(a.dx * a.dx + a.dy * a.dy);
+    // one support: the cull radius of a block and R^2 are uniform
+    const double thr_u = (a.R + rb) * (1.0 + 1e-7);
+    const double thr2_u = thr_u * thr_u;
+    const double R2_u = a.R * a.R;
     const uint64_t lt = lanes_below(lane);
     const T gk1 = (T)a.gk1, gk2 = (T)a.gk2, gc0 = (T)a.gc0;
 
@@ -148,12 +153,16 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
                 const double mx = fma(tc, ux, -wx), my = fma(tc, uy, -wy), mz = fma(tc, uz, -wz);
                 const double m2 = fma(mx, mx, fma(my, my, mz * mz));
                 const double ex = tc < 0.0 ? -tc : (tc > L ? tc - L : 0.0);
-                // the strut's support, and the cull radius of the block
-                // around it (formed here to keep no doubles live across the
-                // evaluation loop)
-                const double Rs = a.strut_R ? (double)r.pad : a.R;
-                const double thr = (Rs + rb) * (1.0 + 1e-7);
-                const bool pass = valid && fma(ex, ex, m2) < thr * thr;
+                // per-strut supports: the strut's cull radius and R^2, formed
+                // here to keep no doubles live across the evaluation loop
+                double thr2 = thr2_u, R2 = R2_u;
+                if (SR) {
+                    const double Rs = (double)r.pad;
+                    const double thr = (Rs + rb) * (1.0 + 1e-7);
+                    thr2 = thr * thr;
+                    R2 = Rs * Rs;
+                }
+                const bool pass = valid && fma(ex, ex, m2) < thr2;
                 const uint64_t mask = ballot64(pass);
                 if (mask == 0ull) continue;
                 if (pass) {
@@ -164,7 +173,7 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
                     s.uy = uyT;
                     s.ntc = (T)(-tc);
                     s.nbtc = (T)(L - tc);
-                    s.H0 = (T)(Rs * Rs - m2);
+                    s.H0 = (T)(R2 - m2);
                     s.wq = r.wq;
                     stage[__popcll(mask & lt)] = s;
                 }
