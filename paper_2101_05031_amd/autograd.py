@@ -10,12 +10,14 @@ class SliceField(torch.autograd.Function):
     """field[nk, H, W] of planes [k0, k0+nk) as a differentiable function of
     the node positions [N,3] and strut weights [E].  The forward pass bins the
     lattice (nodes may have moved since the last call) and evaluates the
-    field; the backward pass runs the native adjoint on the same bins."""
+    field; the backward pass runs the native adjoint on the same bins.
+    support: optional per-strut supports [E] (held fixed)."""
 
     @staticmethod
-    def forward(ctx, nodes, weight, edges, R, C, grid, k0, nk, tile=0, slab=0):
+    def forward(ctx, nodes, weight, edges, R, C, grid, k0, nk, tile=0, slab=0, support=None):
         bins = api.lattice_bin(nodes.detach().contiguous(), edges.contiguous(),
-                               weight.detach().contiguous(), R, C, grid, tile=tile, slab=slab)
+                               weight.detach().contiguous(), R, C, grid, tile=tile, slab=slab,
+                               support=None if support is None else support.detach().contiguous())
         field = api.slice_field(bins, k0, nk)
         ctx.bins = bins
         ctx.k0, ctx.nk = k0, nk
@@ -25,15 +27,16 @@ class SliceField(torch.autograd.Function):
     def backward(ctx, grad):
         need_n, need_w = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         if not (need_n or need_w):
-            return (None,) * 10
+            return (None,) * 11
         gw, gn = api.slice_field_backward(ctx.bins, ctx.k0, ctx.nk,
-                                          grad.contiguous().to(ctx.bins.dtype))
+                                          grad.contiguous().to(ctx.bins.dtype),
+                                          want_nodes=need_n)
         return (gn if need_n else None, gw if need_w else None,
-                None, None, None, None, None, None, None, None)
+                None, None, None, None, None, None, None, None, None)
 
 
-def slice_field(nodes, weight, edges, R, C, grid, k0, nk, tile=0, slab=0):
-    return SliceField.apply(nodes, weight, edges, R, C, grid, k0, nk, tile, slab)
+def slice_field(nodes, weight, edges, R, C, grid, k0, nk, tile=0, slab=0, support=None):
+    return SliceField.apply(nodes, weight, edges, R, C, grid, k0, nk, tile, slab, support)
 
 
 def soft_occupancy_loss(field, target, C: float, tau: float):

@@ -29,9 +29,12 @@ def match_density(nodes, edges, weight, R: float, C: float, grid, target, vx: in
                   vz: int, *, k0: int = 0, nk: int | None = None, tau: float = 0.05,
                   iters: int = 20, lr: float | None = None, w_min: float = 0.0,
                   betas=(0.9, 0.999), eps: float = 1e-12, tile: int = 0, slab: int = 0,
-                  stream=None):
+                  support=None, stream=None):
     """Adjust `weight` so the per-voxel densities of planes k0 .. k0+nk-1 move
     toward `target` (float32 [nz, ny, nx] on the device).
+
+    support: optional per-strut supports [E], held fixed (the adjoint covers
+    the quartic kernel only).
 
     lr defaults to 2% of the mean starting weight per step; it decays along a
     half cosine to a tenth of that over the iterations.  Returns (weight,
@@ -50,7 +53,8 @@ def match_density(nodes, edges, weight, R: float, C: float, grid, target, vx: in
     history = []
 
     def evaluate(w, want_grad):
-        bins = api.lattice_bin(nodes, edges, w, R, C, grid, tile=tile, slab=slab)
+        bins = api.lattice_bin(nodes, edges, w, R, C, grid, tile=tile, slab=slab,
+                               support=support, stream=stream)
         field = api.slice_field(bins, k0, nk, stream=stream)
         loss, _, gfield = api.slice_density_loss(bins, field, target, tau, vx, vy, vz,
                                                  want_grad=want_grad, stream=stream)
