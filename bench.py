@@ -63,14 +63,16 @@ def parse():
 
 def peak_probe():
     """Measured vector-ALU ceilings beside the published peak: FP32 FMA with
-    register operands (VOP2) and with scalar operands (VOP3), FP32 sqrt,
-    FP64 FMA, and the field kernel's per-pair sequence on staged data."""
+    register operands (two- and three-operand forms) and with scalar
+    operands, FP32 sqrt and clamp, FP64 FMA, and the field kernel's per-pair
+    sequence on staged data."""
     from paper_2101_05031_amd import api
     names = {0: "fp32 fma, vgpr operands", 1: "fp32 fma, sgpr operands", 2: "fp32 sqrt",
-             3: "fp64 fma", 4: "field term per pair"}
-    iters = {0: 65536, 1: 65536, 2: 16384, 3: 32768, 4: 1024}
+             3: "fp64 fma", 4: "field term per pair", 5: "fp32 fma, three vgpr operands",
+             6: "fp32 med3 clamp"}
+    iters = {0: 65536, 1: 65536, 2: 16384, 3: 32768, 4: 1024, 5: 65536, 6: 32768}
     out = {}
-    for m in range(5):
+    for m in range(7):
         api.probe_valu(m, 16)                      # warm-up
         best = None
         for _ in range(3):
@@ -78,7 +80,7 @@ def peak_probe():
             best = r if best is None or r["ms"] < best["ms"] else best
         rate = best["lane_ops"] / (best["ms"] * 1e-3)
         rec = {"ms": best["ms"], "lane_ops_per_s": rate}
-        if m in (0, 1, 3):
+        if m in (0, 1, 3, 5):
             rec["tflops"] = 2.0 * rate / 1e12
         if m == 4:
             rec["pairs_per_s"] = rate

@@ -406,6 +406,9 @@ const char* lsl_version(void);
  *   mode 3  FP64 multiply-add
  *   mode 4  the field kernel's per-pair term and compensated add, from 64
  *           staged struts in LDS                   -> 1 lane-op = 1 pair
+ *   mode 5  FP32 multiply-add, three-operand form with register operands
+ *           (v_fma_f32)
+ *   mode 6  FP32 clamp (v_med3_f32 with a negated bound)
  * The probe allocates and frees its own small device buffers and
  * synchronizes the stream.  LSL_EINVAL for a bad mode or iters < 1.
  * ------------------------------------------------------------------------- */

@@ -23,6 +23,8 @@ __global__ __launch_bounds__(256) void k_probe(float* out, const float* bv, int 
             if (MODE == 0) a[q] = __builtin_fmaf(b, c, a[q]);             // v_fmac_f32, VGPR operands
             if (MODE == 1) a[q] = __builtin_fmaf(a[q], sb, sc);           // v_fma_f32, SGPR operands
             if (MODE == 2) a[q] = __builtin_amdgcn_sqrtf(a[q]);           // v_sqrt_f32
+            if (MODE == 5) a[q] = __builtin_fmaf(a[q], b, c);             // v_fma_f32, VGPR operands
+            if (MODE == 6) a[q] = __builtin_amdgcn_fmed3f(a[q], -b, b);   // v_med3_f32 (a clamp)
         }
     }
     float s = 0.0f;
@@ -77,8 +79,8 @@ extern "C" lsl_status lsl_probe_valu(int32_t mode, int32_t iters, float* ms, dou
                                      void* stream) {
     using namespace lsl;
     set_error("");
-    if (mode < 0 || mode > 4 || iters < 1 || !ms || !lane_ops) {
-        set_error("lsl_probe_valu: mode in [0, 4], iters >= 1, ms and lane_ops required");
+    if (mode < 0 || mode > 6 || iters < 1 || !ms || !lane_ops) {
+        set_error("lsl_probe_valu: mode in [0, 6], iters >= 1, ms and lane_ops required");
         return LSL_EINVAL;
     }
     hipStream_t st = (hipStream_t)stream;
@@ -108,6 +110,8 @@ extern "C" lsl_status lsl_probe_valu(int32_t mode, int32_t iters, float* ms, dou
         if (mode == 2) k_probe<2><<<blocks, 256, 0, st>>>((float*)buf, bv, iters, 0.9999f, 1e-4f);
         if (mode == 3) k_probe_f64<<<blocks, 256, 0, st>>>((double*)buf, iters, 0.9999, 1e-4);
         if (mode == 4) k_probe_term<<<blocks, 256, 0, st>>>((float*)buf, iters);
+        if (mode == 5) k_probe<5><<<blocks, 256, 0, st>>>((float*)buf, bv, iters, 0.9999f, 1e-4f);
+        if (mode == 6) k_probe<6><<<blocks, 256, 0, st>>>((float*)buf, bv, iters, 0.9999f, 1e-4f);
         err = hipGetLastError();
     }
     if (err == hipSuccess) err = hipEventRecord(e1, st);
