@@ -16,6 +16,8 @@
  * and 5); each plane is sampled at pixel centres
  * (x0 + (i + 1/2) dx, y0 + (j + 1/2) dy), i < W, j < H, giving a field image,
  * a binary image (Sec. 4) and its marching-squares contours (Sec. 4).
+ * Two kernel variants (per-strut supports, a compact Gaussian) are selected
+ * in lsl_lattice; zero-initialised, it describes the paper's method.
  *
  * Conventions for every call:
  *  - Pointers are DEVICE pointers unless marked [host].  The caller owns every
@@ -184,7 +186,8 @@ lsl_status lattice_bins_export(lattice_bins* bins, int32_t g, int64_t* offsets,
                                int32_t* ids, void* stream);
 
 /* The edge list: original ids of the binned struts in ascending (z of the
- * lower end, id) order, [n_binned] int32.  Stream-ordered. */
+ * lower end, id) order (with per-strut supports: (first slab, z of the lower
+ * end, id)), [n_binned] int32.  Stream-ordered. */
 lsl_status lattice_bins_order(const lattice_bins* bins, int32_t* order,
                               void* stream);
 
