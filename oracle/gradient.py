@@ -103,15 +103,18 @@ def field_vjp(points, G, nodes, edges, weight, R, struts=None):
 
 
 def soft_occupancy_grad(g, target, C: float, tau: float):
-    """G = dL/dg for L = sum (sigmoid((g - C)/tau) - target)^2."""
-    g = np.asarray(g, dtype=np.float64)
-    s = 1.0 / (1.0 + np.exp(-(g - C) / tau))
-    return 2.0 * (s - target) * s * (1.0 - s) / tau
+    """G = dL/dg for L = sum (sigmoid((g - C)/tau) - target)^2, with the
+    sigmoid's derivative s (1 - s) written sigmoid(z) sigmoid(-z) (the same
+    value, without losing 1 - s to cancellation where s rounds to 1)."""
+    from scipy.special import expit
+    z = (np.asarray(g, dtype=np.float64) - C) / tau
+    s = expit(z)
+    return 2.0 * (s - target) * s * expit(-z) / tau
 
 
 def soft_occupancy_loss(g, target, C: float, tau: float) -> float:
-    g = np.asarray(g, dtype=np.float64)
-    s = 1.0 / (1.0 + np.exp(-(g - C) / tau))
+    from scipy.special import expit
+    s = expit((np.asarray(g, dtype=np.float64) - C) / tau)
     return float(np.sum((s - target) ** 2))
 
 

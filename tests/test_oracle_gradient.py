@@ -97,3 +97,27 @@ def test_mirror_symmetry_of_gradients():
     assert gw[0] == pytest.approx(gw[1], rel=1e-12)
     np.testing.assert_allclose(gn[0] * [-1, 1, 1], gn[2], rtol=1e-10, atol=1e-14)
     np.testing.assert_allclose(gn[1] * [-1, 1, 1], gn[3], rtol=1e-10, atol=1e-14)
+
+
+def test_soft_occupancy_loss_pins():
+    """The per-pixel soft-occupancy loss: its gradient against central
+    differences, equality with the voxel-density loss of one-sample voxels
+    (a separate route), and the exp(-|z|) tails of the gradient."""
+    from oracle import density as D
+    rng = np.random.default_rng(8)
+    g = rng.uniform(0.7, 1.3, size=(3, 5, 7))
+    t = rng.uniform(0.0, 1.0, size=g.shape)
+    tau, h = 0.05, 1e-6
+    Gr = G.soft_occupancy_grad(g, t, 1.0, tau)
+    for _ in range(20):
+        k, y, x = (int(rng.integers(n)) for n in g.shape)
+        p, q = g.copy(), g.copy()
+        p[k, y, x] += h
+        q[k, y, x] -= h
+        fd = (G.soft_occupancy_loss(p, t, 1.0, tau) - G.soft_occupancy_loss(q, t, 1.0, tau)) / (2 * h)
+        assert Gr[k, y, x] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+    loss, _, grad = D.density_loss(g, t, 1.0, tau, 1, 1, 1)
+    assert G.soft_occupancy_loss(g, t, 1.0, tau) == pytest.approx(loss, rel=1e-14)
+    assert np.allclose(Gr, grad, rtol=1e-13, atol=0)
+    deep = G.soft_occupancy_grad(np.array([1.0 + 70 * tau]), np.array([0.0]), 1.0, tau)[0]
+    assert deep == pytest.approx(2.0 * np.exp(-70.0) / tau, rel=1e-12)
