@@ -223,19 +223,13 @@ def main():
                                         segs=segs, offsets=offsets)
         return bb
 
-    if target is not None:
-        # loss constants: L = sum (sigmoid((g - C)/tau) - target)^2
-        c0 = torch.tensor(-lat.C / tau, dtype=dtype, device=dev)
-        tneg = target * (-2.0 / tau)
+    # L = sum (sigmoid((g - C)/tau) - target)^2 and dL/dg in one native pass
+    G = torch.empty_like(field) if target is not None else None
+    loss_dev = torch.empty(1, dtype=torch.float64, device=dev)
 
     def fwd_bwd_step():
         bb = fwd_step()
-        # dL/dg = (2/tau) (s - target) s (1 - s), s = sigmoid((g - C)/tau), in
-        # five elementwise passes
-        s_ = torch.add(c0, field, alpha=1.0 / tau).sigmoid_()
-        w_ = torch.addcmul(s_, s_, s_, value=-1.0)
-        G = torch.add(tneg, s_, alpha=2.0 / tau).mul_(w_)
-        del s_, w_
+        api.slice_occupancy_loss(bb, field, target, tau, grad_field=G, loss=loss_dev)
         api.slice_field_backward(bb, 0, S, G, grad_weight, grad_nodes)
         return bb
 

@@ -301,6 +301,24 @@ lsl_status slice_density_loss(const lattice_bins* bins, int32_t nk, const void* 
                               double* loss, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * slice_occupancy_loss -- a per-pixel soft-occupancy loss of a sliced field
+ * and its gradient, the input of slice_field_backward (the radius tuning of
+ * Sec. 5.3 needs a differentiable stand-in for the inside test).
+ *
+ * field, target: [nk][H][W] of the lattice dtype.  With s = sigmoid((g - C)
+ * / tau), tau > 0: loss = sum over pixels of (s - target)^2 (one float64 on
+ * the device), grad_field = dL/dg = 2 (s - target) s (1 - s) / tau
+ * ([nk][H][W], lattice dtype).  Either output may be NULL.  One pass over
+ * field and target; the sum has a fixed order (bitwise repeatable).
+ * Stream-ordered; shares the scratch of slice_density_loss (it grows,
+ * synchronising `stream`, when a call needs more).  LSL_EINVAL on nk < 1 or
+ * tau <= 0.
+ * ------------------------------------------------------------------------- */
+lsl_status slice_occupancy_loss(const lattice_bins* bins, int32_t nk, const void* field,
+                                const void* target, double tau, void* grad_field,
+                                double* loss, void* stream);
+
+/* ---------------------------------------------------------------------------
  * slice_field_backward -- gradient of a loss of the sliced field.
  *
  * Given grad_field = dL/dg at the pixels of planes k0 .. k0+nk-1

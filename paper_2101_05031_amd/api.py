@@ -245,6 +245,25 @@ def slice_density_loss(bins: Bins, field, target, tau: float, vx: int, vy: int, 
     return loss, soft, grad_field
 
 
+def slice_occupancy_loss(bins: Bins, field, target, tau: float, grad_field=None, loss=None,
+                         want_grad: bool = True, stream=None):
+    """sum over pixels of (sigmoid((g - C)/tau) - target)^2 and dL/dg, for
+    field and target [nk, H, W] of the lattice dtype -> (loss float64 [1] on
+    the device, dL/dg or None)."""
+    _check_field(bins, field)
+    if (tuple(target.shape) != tuple(field.shape) or target.dtype != field.dtype
+            or not target.is_contiguous()):
+        raise ValueError("target must be a contiguous tensor like field")
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    if grad_field is None and want_grad:
+        grad_field = torch.empty_like(field)
+    N.check(N.lib().slice_occupancy_loss(bins.handle, field.shape[0], _ptr(field), _ptr(target),
+                                         float(tau), _ptr(grad_field), _ptr(loss),
+                                         _stream(stream)), "slice_occupancy_loss")
+    return loss, grad_field
+
+
 def slice_field_backward(bins: Bins, k0: int, nk: int, grad_field, grad_weight=None,
                          grad_nodes=None, accumulate: bool = False, want_nodes: bool = True,
                          stream=None):

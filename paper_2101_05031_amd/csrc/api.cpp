@@ -1064,6 +1064,30 @@ lsl_status slice_density(const lattice_bins* b, int32_t nk, const void* field, i
     return launch_density(b->dtype, a, field, b->C, density, S(stream));
 }
 
+lsl_status slice_occupancy_loss(const lattice_bins* cb, int32_t nk, const void* field,
+                                const void* target, double tau, void* grad_field, double* loss,
+                                void* stream) {
+    set_error("");
+    LSL_CHECK(cb != nullptr, "bins handle is NULL");
+    LSL_CHECK(nk >= 1, "nk must be >= 1");
+    LSL_CHECK(field != nullptr && target != nullptr, "field and target are required");
+    LSL_CHECK(std::isfinite(tau) && tau > 0.0, "tau must be finite and > 0");
+    lattice_bins* b = const_cast<lattice_bins*>(cb);   // scratch only
+    hipStream_t st = S(stream);
+    const size_t n = (size_t)nk * (size_t)b->grid.W * (size_t)b->grid.H;
+    const size_t need = occupancy_blocks(n);
+    if (need > b->dscratch_elems) {
+        LSL_HIP(hipStreamSynchronize(st));
+        b->release(b->dscratch);
+        b->dscratch = nullptr;
+        b->dscratch_elems = 0;
+        LSL_TRY(b->alloc_t(&b->dscratch, need));
+        b->dscratch_elems = need;
+    }
+    return launch_occupancy_loss(b->dtype, field, target, n, b->C, tau, grad_field, loss,
+                                 b->dscratch, st);
+}
+
 lsl_status slice_density_loss(const lattice_bins* cb, int32_t nk, const void* field, int32_t vx,
                               int32_t vy, int32_t vz, const float* target, double tau,
                               float* soft_density, void* grad_field, double* loss,

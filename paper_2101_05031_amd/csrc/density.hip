@@ -1,5 +1,7 @@
-// Per-voxel density of the sliced solid (Sec. 5, Eq. 9) and a smooth
-// voxel-density loss for the radius adjustment of Sec. 5.3.
+// Per-voxel density of the sliced solid (Sec. 5, Eq. 9), a smooth
+// voxel-density loss for the radius adjustment of Sec. 5.3, and the per-pixel
+// soft-occupancy loss of a sliced field (the same loss with one-sample voxels,
+// without the per-voxel pass).
 //
 // The density of a voxel is the fraction of its samples inside the solid,
 // g >= C, the samples being the pixel centres of the slice planes (a
@@ -51,6 +53,20 @@ __device__ __forceinline__ double sigm_prime(double z) {
     const double e = exp(-fabs(z));
     const double d = 1.0 + e;
     return e / (d * d);
+}
+
+// sigmoid(z) and its derivative from one exponential
+__device__ __forceinline__ void sigm_both(float z, float& s, float& sp) {
+    const float e = __expf(-fabsf(z));
+    const float r = __builtin_amdgcn_rcpf(1.0f + e);
+    s = z >= 0.0f ? r : e * r;
+    sp = e * r * r;
+}
+__device__ __forceinline__ void sigm_both(double z, double& s, double& sp) {
+    const double e = exp(-fabs(z));
+    const double d = 1.0 + e;
+    s = z >= 0.0 ? 1.0 / d : e / d;
+    sp = e / (d * d);
 }
 
 struct Box {
@@ -233,6 +249,55 @@ __global__ __launch_bounds__(kDThreads) void k_density_grad(const T* field, Dens
     }
 }
 
+// Per-pixel soft-occupancy loss: L = sum_p (s_p - t_p)^2, s = sigmoid((g - C)
+// / tau), and dL/dg = 2 (s - t) s' / tau, in one pass over field and target.
+// A fixed grid walks the pixels with a fixed stride, four loads in flight per
+// thread; each block writes its sum of squares, so the total has a fixed order.
+constexpr int kOccUnroll = 4;
+
+template <typename T>
+__global__ __launch_bounds__(kDThreads) void k_occupancy_loss(const T* field, const T* target,
+                                                              size_t n, T C, T inv_tau,
+                                                              T two_over_tau, T* grad,
+                                                              double* part) {
+    __shared__ double sm[kDThreads];
+    double acc = 0.0;
+    const size_t stride = (size_t)gridDim.x * kDThreads;
+    for (size_t i0 = (size_t)blockIdx.x * kDThreads + threadIdx.x; i0 < n;
+         i0 += kOccUnroll * stride) {
+        T g[kOccUnroll], t[kOccUnroll];
+#pragma unroll
+        for (int q = 0; q < kOccUnroll; ++q) {
+            const size_t i = i0 + (size_t)q * stride;
+            g[q] = i < n ? field[i] : C;
+            t[q] = i < n ? target[i] : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < kOccUnroll; ++q) {
+            const size_t i = i0 + (size_t)q * stride;
+            if (i < n) {
+                T sv, sp;
+                sigm_both((g[q] - C) * inv_tau, sv, sp);
+                const T r = sv - t[q];
+                if (grad) __builtin_nontemporal_store(two_over_tau * r * sp, grad + i);
+                acc += (double)r * (double)r;
+            }
+        }
+    }
+    const double tot = block_total(acc, sm);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+template <typename T>
+lsl_status occupancy_t(const void* field, const void* target, size_t n, double C, double tau,
+                       void* grad, double* loss, double* part, uint32_t nb, hipStream_t st) {
+    k_occupancy_loss<T><<<nb, kDThreads, 0, st>>>((const T*)field, (const T*)target, n, (T)C,
+                                                  (T)(1.0 / tau), (T)(2.0 / tau), (T*)grad, part);
+    if (loss) k_loss_final<<<1, kDThreads, 0, st>>>(part, nb, loss);
+    LSL_HIP(hipGetLastError());
+    return LSL_OK;
+}
+
 template <typename T>
 lsl_status density_t(const DensityArgs& a, const void* field, double C, float* out,
                      hipStream_t st) {
@@ -297,6 +362,20 @@ lsl_status launch_density(int dtype, const DensityArgs& a, const void* field, do
                           float* out, hipStream_t st) {
     return dtype == LSL_F32 ? density_t<float>(a, field, C, out, st)
                             : density_t<double>(a, field, C, out, st);
+}
+
+uint32_t occupancy_blocks(size_t n) {
+    const size_t b = (n + (size_t)kDThreads * kOccUnroll - 1) / ((size_t)kDThreads * kOccUnroll);
+    return (uint32_t)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
+}
+
+lsl_status launch_occupancy_loss(int dtype, const void* field, const void* target, size_t n,
+                                 double C, double tau, void* grad, double* loss, double* part,
+                                 hipStream_t st) {
+    const uint32_t nb = occupancy_blocks(n);
+    return dtype == LSL_F32 ? occupancy_t<float>(field, target, n, C, tau, grad, loss, part, nb, st)
+                            : occupancy_t<double>(field, target, n, C, tau, grad, loss, part, nb,
+                                                  st);
 }
 
 lsl_status launch_density_loss(int dtype, const DensityArgs& a, const void* field, double C,

@@ -251,5 +251,11 @@ lsl_status launch_density(int dtype, const DensityArgs& a, const void* field, do
 lsl_status launch_density_loss(int dtype, const DensityArgs& a, const void* field, double C,
                                double tau, const float* target, float* soft, void* grad,
                                double* loss, double* scratch, hipStream_t st);
+// Per-pixel soft-occupancy loss over n values; part holds occupancy_blocks(n)
+// doubles.
+uint32_t occupancy_blocks(size_t n);
+lsl_status launch_occupancy_loss(int dtype, const void* field, const void* target, size_t n,
+                                 double C, double tau, void* grad, double* loss, double* part,
+                                 hipStream_t st);
 
 }  // namespace lsl

@@ -162,3 +162,30 @@ def test_match_density_reduces_the_loss():
     w2, _ = tuning.match_density(n, e, w, lat.R, lat.C, grid, target, vx, vy, vz,
                                  iters=12, lr=lr, w_min=w_min)
     assert torch.equal(w1, w2)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_occupancy_loss_matches_oracle(dtype):
+    """The per-pixel soft-occupancy loss (slice_occupancy_loss) against the
+    oracle's (oracle/gradient.py), on the GPU's own field."""
+    from oracle import gradient as OG
+    lat, grid = small_kuhn(dtype)
+    b = bin_lattice(lat, grid)
+    f = api.slice_field(b, 2, 20)
+    rng = np.random.default_rng(12)
+    t = rng.uniform(0.0, 1.0, size=tuple(f.shape)).astype(dtype)
+    loss, g = api.slice_occupancy_loss(b, f, torch.from_numpy(t).cuda(), 0.05)
+    fh = f.cpu().numpy().astype(np.float64)
+    C = c_in(lat, dtype)
+    rl = OG.soft_occupancy_loss(fh, t.astype(np.float64), C, 0.05)
+    rg = OG.soft_occupancy_grad(fh, t.astype(np.float64), C, 0.05)
+    f32 = dtype == np.float32
+    assert loss.item() == pytest.approx(rl, rel=1e-5 if f32 else 1e-12)
+    gh = g.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(gh - rg)) <= (1e-4 if f32 else 1e-10) * np.abs(rg).max()
+    l2, g2 = api.slice_occupancy_loss(b, f, torch.from_numpy(t).cuda(), 0.05)
+    assert torch.equal(loss, l2) and torch.equal(g, g2)
+    # the same loss as the voxel-density loss with one-sample voxels
+    lv, _, gv = api.slice_density_loss(b, f, torch.from_numpy(t.astype(np.float32)).cuda(), 0.05,
+                                       1, 1, 1)
+    assert lv.item() == pytest.approx(rl, rel=1e-5)         # (float32 targets there)
