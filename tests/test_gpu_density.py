@@ -62,6 +62,12 @@ def test_density_constant_fields_and_errors():
     assert st == N.LSL_EINVAL
     with pytest.raises(ValueError):
         api.slice_density_loss(b, f, t[:1], 0.05, 4, 4, 4)
+    st = N.lib().slice_occupancy_loss(b.handle, 5, api._ptr(f), api._ptr(f), -1.0, None, None,
+                                      api._stream())
+    assert st == N.LSL_EINVAL
+    st = N.lib().slice_occupancy_loss(b.handle, 0, api._ptr(f), api._ptr(f), 0.05, None, None,
+                                      api._stream())
+    assert st == N.LSL_EINVAL
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
