@@ -52,13 +52,18 @@ KERNEL_SOURCES = {
 
 
 def kernel_hash(name: str) -> str:
-    """Hash of the sources a kernel is built from (to tell whether a stored
-    profile still describes the current kernel)."""
+    """Hash of the code a kernel is built from, comments and whitespace left
+    out (to tell whether a stored profile still describes the current
+    kernel)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES[name]:
-        with open(os.path.join(CSRC, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(CSRC, f), "r", encoding="utf-8") as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

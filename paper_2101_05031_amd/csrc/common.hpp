@@ -16,7 +16,8 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kBlockPix = 8;       // a wave evaluates one 8x8 pixel block
 
 // ---------------------------------------------------------------------------
-// Per-strut records, in edge-list order (ascending z of the lower end).
+// Per-strut records, in edge-list order (ascending z of the lower end; with
+// per-strut supports, ascending first slab, then z).
 // ---------------------------------------------------------------------------
 // One strut: its ends a = v_s and b = v_e as given (the kernels form the
 // direction and length in float64), the folded weight wq = r / R^4 (the

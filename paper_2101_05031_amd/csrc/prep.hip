@@ -1,6 +1,7 @@
 // Strut preparation: validation, slab/tile ranges of each strut's swept box,
-// sort keys of the edge list (ascending z of the lower end, Sec. 4) and the
-// histograms the slab-group plan is made from.
+// sort keys of the edge list (ascending z of the lower end, Sec. 4; with
+// per-strut supports the first slab is a major key) and the histograms the
+// slab-group plan is made from.
 #include "kernels.hpp"
 
 namespace lsl {
