@@ -247,6 +247,22 @@ struct lattice_bins {
             }
     }
     size_t esize() const { return dtype == LSL_F64 ? 8 : 4; }
+    // Grows library scratch *p (capacity *cap elements) to `need` elements:
+    // waits for the work queued on `st` (it may still use the old buffer),
+    // releases it and allocates the new one.  `in_graphs`: the buffer's address
+    // is baked into captured graphs, which are then dropped.
+    template <typename T>
+    lsl_status grow(T** p, size_t* cap, size_t need, hipStream_t st, bool in_graphs) {
+        if (need <= *cap) return LSL_OK;
+        LSL_HIP(hipStreamSynchronize(st));
+        release(*p);
+        *p = nullptr;
+        *cap = 0;
+        LSL_TRY(alloc_t(p, need));
+        *cap = need;
+        if (in_graphs) drop_graphs();
+        return LSL_OK;
+    }
     void drop_graphs() {
         for (auto& g : graphs)
             for (auto& x : g.exec)
@@ -495,16 +511,7 @@ size_t blk_words(const lattice_bins* b, int32_t nk) {
 
 // library scratch for the block-major binary images of nk planes
 lsl_status ensure_cbits(lattice_bins* b, int32_t nk, hipStream_t st) {
-    const size_t nbits = blk_words(b, nk);
-    if (nbits <= b->cbits_elems) return LSL_OK;
-    LSL_HIP(hipStreamSynchronize(st));
-    b->release(b->cbits);
-    b->cbits = nullptr;
-    b->cbits_elems = 0;
-    LSL_TRY(b->alloc_t(&b->cbits, nbits));
-    b->cbits_elems = nbits;
-    b->drop_graphs();
-    return LSL_OK;
+    return b->grow(&b->cbits, &b->cbits_elems, blk_words(b, nk), st, true);
 }
 
 }  // namespace
@@ -965,16 +972,8 @@ lsl_status slice_contours(const lattice_bins* cb, int32_t nk, const void* field,
     LSL_CHECK(capacity == 0 || segs != nullptr, "segs is NULL");
     lattice_bins* b = const_cast<lattice_bins*>(cb);   // scratch only
     hipStream_t st = S(stream);
-    const size_t need = contour_tmp_elems(nk, b->grid.W, b->grid.H);
-    if (need > b->ctmp_elems) {
-        LSL_HIP(hipStreamSynchronize(st));
-        b->release(b->ctmp);
-        b->ctmp = nullptr;
-        b->ctmp_elems = 0;
-        LSL_TRY(b->alloc_t(&b->ctmp, need));
-        b->ctmp_elems = need;
-        b->drop_graphs();
-    }
+    LSL_TRY(b->grow(&b->ctmp, &b->ctmp_elems, contour_tmp_elems(nk, b->grid.W, b->grid.H), st,
+                    true));
     LSL_TRY(ensure_cbits(b, nk, st));
     // the binary images (block-major), then marching squares on them
     const uint64_t* img = (const uint64_t*)b->cbits;
@@ -1010,16 +1009,8 @@ lsl_status slice_polylines(const lattice_bins* cb, int32_t nk, const void* field
     LSL_CHECK((chain == nullptr) == (rank == nullptr), "chain and rank go together");
     lattice_bins* b = const_cast<lattice_bins*>(cb);   // scratch only
     hipStream_t st = S(stream);
-    const size_t need = contour_tmp_elems(nk, b->grid.W, b->grid.H);
-    if (need > b->ctmp_elems) {
-        LSL_HIP(hipStreamSynchronize(st));
-        b->release(b->ctmp);
-        b->ctmp = nullptr;
-        b->ctmp_elems = 0;
-        LSL_TRY(b->alloc_t(&b->ctmp, need));
-        b->ctmp_elems = need;
-        b->drop_graphs();
-    }
+    LSL_TRY(b->grow(&b->ctmp, &b->ctmp_elems, contour_tmp_elems(nk, b->grid.W, b->grid.H), st,
+                    true));
     LSL_TRY(ensure_cbits(b, nk, st));
     const uint64_t* img = (const uint64_t*)b->cbits;
     LSL_TRY(launch_bits_blk(b->dtype, field, nk, b->grid.W, b->grid.H, b->C,
@@ -1042,14 +1033,8 @@ lsl_status slice_polylines(const lattice_bins* cb, int32_t nk, const void* field
     for (int32_t k = 0; k < nk; ++k) longest = std::max<int64_t>(longest, h_off[k + 1] - h_off[k]);
     int32_t rounds = 1;
     while (((int64_t)1 << (rounds - 1)) < longest) ++rounds;
-    const size_t ps = polyline_scratch_elems((uint64_t)tot);
-    if (ps > b->pscratch_elems) {
-        b->release(b->pscratch);
-        b->pscratch = nullptr;
-        b->pscratch_elems = 0;
-        LSL_TRY(b->alloc_t(&b->pscratch, ps));
-        b->pscratch_elems = ps;
-    }
+    LSL_TRY(b->grow(&b->pscratch, &b->pscratch_elems, polyline_scratch_elems((uint64_t)tot), st,
+                    false));
     return launch_polylines(img, field, b->dtype, b->C, nk, b->grid.W, b->grid.H, b->ctmp, offsets,
                             (uint64_t)tot, rounds, segs, b->pscratch, chain, rank, st);
 }
@@ -1076,14 +1061,7 @@ lsl_status slice_occupancy_loss(const lattice_bins* cb, int32_t nk, const void* 
     hipStream_t st = S(stream);
     const size_t n = (size_t)nk * (size_t)b->grid.W * (size_t)b->grid.H;
     const size_t need = occupancy_blocks(n);
-    if (need > b->dscratch_elems) {
-        LSL_HIP(hipStreamSynchronize(st));
-        b->release(b->dscratch);
-        b->dscratch = nullptr;
-        b->dscratch_elems = 0;
-        LSL_TRY(b->alloc_t(&b->dscratch, need));
-        b->dscratch_elems = need;
-    }
+    LSL_TRY(b->grow(&b->dscratch, &b->dscratch_elems, need, st, false));
     return launch_occupancy_loss(b->dtype, field, target, n, b->C, tau, grad_field, loss,
                                  b->dscratch, st);
 }
@@ -1101,14 +1079,7 @@ lsl_status slice_density_loss(const lattice_bins* cb, int32_t nk, const void* fi
     DensityArgs a{};
     LSL_TRY(density_plan(nk, b->grid.W, b->grid.H, vx, vy, vz, &a));
     const size_t need = density_scratch_elems(a);
-    if (need > b->dscratch_elems) {
-        LSL_HIP(hipStreamSynchronize(st));
-        b->release(b->dscratch);
-        b->dscratch = nullptr;
-        b->dscratch_elems = 0;
-        LSL_TRY(b->alloc_t(&b->dscratch, need));
-        b->dscratch_elems = need;
-    }
+    LSL_TRY(b->grow(&b->dscratch, &b->dscratch_elems, need, st, false));
     return launch_density_loss(b->dtype, a, field, b->C, tau, target, soft_density, grad_field,
                                loss, b->dscratch, st);
 }
@@ -1363,16 +1334,8 @@ lsl_status slice_batch(lattice_bins* b, int32_t k0, int32_t nk, void* field, uin
         b->queue_cap = max_items;
         b->drop_graphs();
     }
-    const size_t ct = contour_tmp_elems((int32_t)max_planes, b->grid.W, b->grid.H);
-    if (b->ctmp_elems < ct) {
-        LSL_HIP(hipStreamSynchronize(st));
-        b->release(b->ctmp);
-        b->ctmp = nullptr;
-        b->ctmp_elems = 0;
-        LSL_TRY(b->alloc_t(&b->ctmp, ct));
-        b->ctmp_elems = ct;
-        b->drop_graphs();
-    }
+    LSL_TRY(b->grow(&b->ctmp, &b->ctmp_elems,
+                    contour_tmp_elems((int32_t)max_planes, b->grid.W, b->grid.H), st, true));
     LSL_TRY(ensure_cbits(b, (int32_t)max_planes, st));
     uint32_t* counter = b->queue_buf + 4 * b->queue_cap;
     unsigned long long* base = (unsigned long long*)(counter + 32);
