@@ -12,6 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblsl.so")
+TOOL = os.path.join(HERE, "lsl_slice")
 SOURCES = ["primitives.hip", "prep.hip", "bin.hip", "field.hip", "contours.hip",
            "backward.hip", "batch.hip", "probe.hip", "support.hip", "density.hip",
            "api.cpp", "autotune.cpp"]
@@ -79,6 +80,16 @@ def build(verbose: bool = True) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
     os.replace(tmp, LIB)
+    # lsl_slice: a command-line slicer on the C ABI alone
+    tool = os.path.join(HERE, "lsl_slice")
+    cmd = [hipcc(), "-O2", "-std=c++17", f"--offload-arch={ARCH}",
+           "-Wno-unused-command-line-argument", "-I", INCLUDE,
+           os.path.join(HERE, "tools", "lsl_slice.cpp"), "-L", HERE, "-llsl",
+           "-Wl,-rpath,$ORIGIN", "-o", tool + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"tool build failed: {' '.join(cmd)}\n{r.stderr}")
+    os.replace(tool + ".tmp", tool)
     if verbose:
         print(f"built {LIB}")
     return LIB
