@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 FLOP_PER_USEFUL_PAIR = 36          # see the field kernel's op count
 PEAK_FP32_VECTOR = 157.3e12        # MI355X published FP32 vector peak
+PEAK_FP64_VECTOR = 78.6e12         # MI355X published FP64 vector peak
 HBM_PEAK = 8.0e12
 
 
@@ -334,7 +335,7 @@ def main():
     # the field kernel against its own per-pair sequence on staged data
     # (lsl_probe_valu mode 4), measured here on the same GPU
     inner = None
-    if field_ms > 0:
+    if field_ms > 0 and dtype == torch.float32 and lat.kernel == "quartic":
         best = min((api.probe_valu(4, 256) for _ in range(3)), key=lambda r: r["ms"])
         ceiling = best["lane_ops"] / (best["ms"] * 1e-3)
         evaluated = stats["candidates"] / (field_ms * 1e-3)
@@ -343,6 +344,8 @@ def main():
                  "useful_fraction": stats["useful"] / max(stats["candidates"], 1)}
     useful = stats["useful"]
     value = useful / t_fwd
+    # the vector peak of the field's arithmetic type
+    peak = PEAK_FP64_VECTOR if dtype == torch.float64 else PEAK_FP32_VECTOR
     field_s = field_ms * 1e-3
     achieved = useful * FLOP_PER_USEFUL_PAIR / field_s if field_s > 0 else None
     traffic = None
@@ -403,13 +406,12 @@ def main():
             "bound": "alu",
             "kernel": "k_persistent (field)",
             "achieved": None if achieved is None else achieved / 1e12,
-            "peak": PEAK_FP32_VECTOR / 1e12,
+            "peak": peak / 1e12,
             "unit": "TFLOP/s",
-            "frac": None if achieved is None else achieved / PEAK_FP32_VECTOR,
+            "frac": None if achieved is None else achieved / peak,
             # the same with every evaluated pair counted (counter view)
             "frac_executed": (None if field_s <= 0 else
-                              stats["candidates"] * FLOP_PER_USEFUL_PAIR / field_s /
-                              PEAK_FP32_VECTOR),
+                              stats["candidates"] * FLOP_PER_USEFUL_PAIR / field_s / peak),
             "traffic": traffic,
             "field_ms_per_launch": field_ms,
             "flop_per_useful_pair": FLOP_PER_USEFUL_PAIR,
