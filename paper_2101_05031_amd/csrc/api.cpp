@@ -152,6 +152,7 @@ struct lattice_bins {
     void* rec = nullptr;
     uint32_t* perm = nullptr;
     SRange* ranges = nullptr;
+    PRange* pranges = nullptr;
     void* w = nullptr;
     int2* ends = nullptr;
 
@@ -454,6 +455,7 @@ FieldArgs field_args(const lattice_bins* b, int32_t k0, int32_t nk, void* field)
     a.z0 = b->grid.z0;
     a.dz = b->grid.dz;
     a.R = b->R;
+    a.pranges = b->pranges;
     a.strut_R = b->strut_R ? 1 : 0;
     a.kernel = b->kernel;
     if (b->kernel == LSL_KERNEL_GAUSS) {
@@ -580,10 +582,11 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
     uint32_t* ks0 = nullptr;
     uint32_t *cnt = nullptr, *stmp = nullptr;
     SRange* rid = nullptr;
+    PRange* prid = nullptr;
     unsigned long long* diff = nullptr;
     const size_t En = std::max<size_t>(E, 1);
     if ((s = b->alloc_t(&klo, En)) || (s = b->alloc_t(&vals, En)) || (s = b->alloc_t(&ka, En)) ||
-        (s = b->alloc_t(&va, En)) || (s = b->alloc_t(&rid, En)) ||
+        (s = b->alloc_t(&va, En)) || (s = b->alloc_t(&rid, En)) || (s = b->alloc_t(&prid, En)) ||
         (s = b->alloc_t(&cnt, 2 * (size_t)ns + 4)) || (s = b->alloc_t(&diff, (size_t)ns + 1)) ||
         (s = b->alloc_t(&stmp, radix_tmp_elems(En))))
         return fail(s);
@@ -620,6 +623,7 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
     pa.key_hi = khi;
     pa.vals = vals;
     pa.ranges = rid;
+    pa.pranges = prid;
     pa.cnt_lo = cnt_lo;
     pa.cnt_hi = cnt_hi;
     pa.pair_diff = diff;
@@ -695,6 +699,7 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
     if ((s = b->alloc(&b->rec, nb * (L->dtype == LSL_F64 ? sizeof(StrutRec<double>)
                                                          : sizeof(StrutRec<float>)))) ||
         (s = b->alloc_t(&b->perm, nb)) || (s = b->alloc_t(&b->ranges, nb)) ||
+        (s = b->alloc_t(&b->pranges, nb)) ||
         (s = b->alloc(&b->w, nb * b->esize())) || (s = b->alloc_t(&b->ends, nb)))
         return fail(s);
     if (b->n_binned) {
@@ -709,6 +714,7 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
         ga.weight = L->weight;
         ga.perm = b->perm;
         ga.ranges_by_id = rid;
+        ga.pranges_by_id = prid;
         ga.n_binned = b->n_binned;
         ga.R = L->R;
         ga.support = L->support;
@@ -716,6 +722,7 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
         ga.sigma = L->sigma;
         ga.rec = b->rec;
         ga.ranges = b->ranges;
+        ga.pranges = b->pranges;
         ga.w = b->w;
         ga.ends = b->ends;
         if ((s = launch_gather(L->dtype, ga, st))) return fail(s);
@@ -726,7 +733,7 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
         return fail(LSL_EDEVICE);
     }
     for (void* p : {(void*)klo, (void*)khi, (void*)vals, (void*)ka, (void*)va, (void*)rid,
-                    (void*)cnt, (void*)diff, (void*)stmp, (void*)ks0})
+                    (void*)prid, (void*)cnt, (void*)diff, (void*)stmp, (void*)ks0})
         b->release(p);
 
     // ---- resident-group buffers sized for the largest group

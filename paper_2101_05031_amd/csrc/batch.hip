@@ -37,6 +37,8 @@ template <typename T, int SZ, int K, bool SR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_persistent(FieldArgs a, const uint32_t* queue,
                                                     uint32_t n_items, uint32_t* counter) {
     __shared__ Stage<T> stage[4][kWave];
+    __shared__ T pend[4][fieldk::pend_elems<T, SZ>()];
+    __shared__ double line[4][fieldk::kLineVals * kWave];
     __shared__ uint32_t s_item;
     const int wv = threadIdx.x >> 6;
     const int nsub = a.tile / kBlockPix;
@@ -52,7 +54,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         const int ty = (int)(t % (uint32_t)a.nty);
         t /= (uint32_t)a.nty;
         for (int sub = wv; sub < nsub * nsub; sub += 4)
-            fieldk::field_block<T, SZ, false, K, SR>(a, a.s_lo + (int)t, tx, ty, sub, stage[wv]);
+            fieldk::field_block<T, SZ, false, K, SR>(a, a.s_lo + (int)t, tx, ty, sub, stage[wv],
+                                                    pend[wv], line[wv]);
     }
 }
 

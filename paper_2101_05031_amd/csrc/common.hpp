@@ -35,6 +35,13 @@ struct SRange {
     int32_t s0, s1;
 };
 
+// The pixel columns, rows and planes of the same box (inclusive; the
+// binning's integers, from which the tile and slab ranges follow).
+struct PRange {
+    uint16_t i0, i1, j0, j1;
+    int32_t k0, k1;
+};
+
 // One staged (strut, plane) pair as a wave reads it from LDS: everything a
 // pixel needs, expressed around the 8x8 block centre c of that plane.
 //   m = F - c with F the foot of c on the strut's line; tc = (c - a).u

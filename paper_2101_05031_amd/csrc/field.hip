@@ -24,10 +24,13 @@
 //   S1 = ca^2 + ca cb + cb^2,  S2 = (ca^2 + cb^2) S1 - (ca cb)^2,
 //   ca, cb = alpha, beta clamped to [-sqrt(H), sqrt(H)].
 //
-// Terms outside the support come out as exact zeros (cb - ca = 0).  float32
-// sums are compensated: s' = s + t, e += t - (s' - s); a zero term leaves
-// both unchanged, so the result does not depend on which zero terms a list
-// holds.
+// Terms outside the support come out as exact zeros (cb - ca = 0).  A strut
+// is a candidate of a block and plane only where it passes the distance test
+// and its binned pixel and plane ranges cover them, so every tile size, slab
+// depth and group split hands the block the same candidates in the same
+// order.  Sums are compensated, s' = s + g, e += g - (s' - s): float32 adds
+// each run of four consecutive candidates plainly, ((t0 + t1) + t2) + t3, and
+// compensates once per run; float64 compensates every term.
 #include "field_block.hpp"
 
 namespace lsl {
@@ -36,6 +39,8 @@ namespace {
 template <typename T, int SZ, bool STATS, int K, bool SR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_field(FieldArgs a, uint32_t n_items) {
     __shared__ Stage<T> stage[4][kWave];
+    __shared__ T pend[4][fieldk::pend_elems<T, SZ>()];
+    __shared__ double line[4][fieldk::kLineVals * kWave];
     const int wv = threadIdx.x >> 6;
     const uint32_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const uint32_t item = blk * 4u + (uint32_t)wv;
@@ -49,7 +54,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     t /= (uint32_t)a.ntx;
     const int ty = (int)(t % (uint32_t)a.nty);
     t /= (uint32_t)a.nty;
-    fieldk::field_block<T, SZ, STATS, K, SR>(a, a.s_lo + (int)t, tx, ty, sub, stage[wv]);
+    fieldk::field_block<T, SZ, STATS, K, SR>(a, a.s_lo + (int)t, tx, ty, sub, stage[wv],
+                                                    pend[wv], line[wv]);
 }
 
 // Block-major binary image of a field: one wave takes 8 rows x 64 columns

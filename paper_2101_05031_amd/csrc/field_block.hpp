@@ -38,7 +38,7 @@ struct Num<double> {
     static __device__ __forceinline__ double exp_(double x) { return exp(x); }
 };
 
-// One (pixel, strut) term of the field, added to the compensated sum (s, c).
+// One (pixel, strut) term of the field.
 template <typename T>
 __device__ __forceinline__ T eval_term(const Stage<T>& e, T dX, T dY, T d2) {
     using N = Num<T>;
@@ -86,13 +86,41 @@ __device__ __forceinline__ void comp_add(T t, T& s, T& c) {
     s = sn;
 }
 
+// Terms per compensated add.  float32 adds each run of four consecutive
+// candidates of a (block, plane) plainly, ((t0 + t1) + t2) + t3, and
+// compensates once per run; float64 compensates every term.  Runs are counted
+// over the whole candidate sequence of the (block, plane), across the 64-entry
+// chunks of the bucket list: a run left open at the end of a chunk waits in
+// LDS (`pend`, [SZ][64] per wave) for the next one.
+template <typename T>
+struct Group {
+    static constexpr int n = 1;
+};
+template <>
+struct Group<float> {
+    static constexpr int n = 4;
+};
+template <typename T, int SZ>
+constexpr int pend_elems() {
+    return Group<T>::n > 1 ? SZ * kWave : 1;
+}
+
+// Between the planes of a chunk each lane keeps six float64 values of its
+// strut's line (a_z, the xy part of tc, c - a in x and y, u_x, u_y) in LDS,
+// [kLineVals][64] per wave, instead of in registers across the evaluation
+// loops: 12 registers fewer per lane, and with the stage and the open runs
+// a workgroup of four waves stays under 32 KB of LDS (five per CU).
+constexpr int kLineVals = 6;
+
 // One wave evaluates the 8x8 block `sub` of tile (tx, ty) over the planes of
-// `slab` that lie in [k0, k0+nk); `stage` is the wave's 64-entry LDS area.
-// K: LSL_KERNEL_QUARTIC or LSL_KERNEL_GAUSS; SR: per-strut supports (in the
-// record's pad) instead of one support R.
+// `slab` that lie in [k0, k0+nk); `stage` is the wave's 64-entry LDS area,
+// `pend` its pend_elems<T, SZ>() open-run sums and `line` its
+// kLineVals * 64 line values.  K: LSL_KERNEL_QUARTIC or LSL_KERNEL_GAUSS;
+// SR: per-strut supports (in the record's pad) instead of one support R.
 template <typename T, int SZ, bool STATS, int K, bool SR>
 __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx, int ty, int sub,
-                                            Stage<T>* stage) {
+                                            Stage<T>* stage, T* pend, double* line) {
+    constexpr int G = Group<T>::n;
     const int lane = lane_id();
     const uint32_t n_binned = a.n_binned, n_pairs = a.n_pairs;
     const int nsub = a.tile / kBlockPix;
@@ -126,9 +154,17 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
     const uint64_t lt = lanes_below(lane);
     const T gk1 = (T)a.gk1, gk2 = (T)a.gk2, gc0 = (T)a.gc0;
 
+    // the block's pixel columns and rows (for the range test)
+    const int ie = i0 + 7 < a.W - 1 ? i0 + 7 : a.W - 1;
+    const int je = j0 + 7 < a.H - 1 ? j0 + 7 : a.H - 1;
+
     T acc_s[SZ], acc_c[SZ];
+    int open[SZ];                       // terms in each plane's open run (wave-uniform)
 #pragma unroll
-    for (int k = 0; k < SZ; ++k) acc_s[k] = acc_c[k] = T(0);
+    for (int k = 0; k < SZ; ++k) {
+        acc_s[k] = acc_c[k] = T(0);
+        open[k] = 0;
+    }
     unsigned long long n_cand = 0, n_useful = 0;
 
     const StrutRec<T>* recs = (const StrutRec<T>*)a.rec;
@@ -138,15 +174,41 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
         uint32_t p = valid ? a.ids[idx] : 0u;
         valid = valid && p < n_binned;
         const StrutRec<T> r = recs[valid ? p : 0u];
+        // The strut is a candidate of this block and plane only where its
+        // binned pixel and plane ranges cover them: then every tile size,
+        // slab depth and group split hands the block the same candidates in
+        // the same order, and the runs of four are the same.
+        uint32_t zmask = 0u;            // bit k: plane kb + k within the strut's planes
+        {
+            const PRange pr = a.pranges[valid ? p : 0u];
+            valid = valid && (int)pr.i0 <= ie && (int)pr.i1 >= i0 && (int)pr.j0 <= je &&
+                    (int)pr.j1 >= j0;
+            const int klo = pr.k0 - kb > 0 ? pr.k0 - kb : 0;
+            const int khi = pr.k1 - kb < SZ - 1 ? pr.k1 - kb : SZ - 1;
+            zmask = klo <= khi ? (2u << khi) - (1u << klo) : 0u;
+        }
         const double ax = (double)r.ax, ay = (double)r.ay, az = (double)r.az;
+        double* cl = line + lane;
         const Line ln = strut_line(r);
-        const double L = ln.L, ux = ln.ux, uy = ln.uy, uz = ln.uz;
-        const T uxT = (T)ux, uyT = (T)uy;
-        const double wx = cx - ax, wy = cy - ay;
-        const double txy = fma(wx, ux, wy * uy);
+        const double L = ln.L, uz = ln.uz;
+        const T uxT = (T)ln.ux, uyT = (T)ln.uy;
+        {
+            const double wx = cx - ax, wy = cy - ay;
+            cl[0 * kWave] = az;
+            cl[1 * kWave] = fma(wx, ln.ux, wy * ln.uy);
+            cl[2 * kWave] = wx;
+            cl[3 * kWave] = wy;
+            cl[4 * kWave] = ln.ux;
+            cl[5 * kWave] = ln.uy;
+        }
 #pragma unroll
         for (int k = 0; k < SZ; ++k) {
             if (k < nvalid) {
+                // the line is read back from LDS for each plane (the empty
+                // asm keeps the compiler from holding it in registers)
+                asm volatile("" ::: "memory");
+                const double az = cl[0 * kWave], txy = cl[1 * kWave], wx = cl[2 * kWave],
+                             wy = cl[3 * kWave], ux = cl[4 * kWave], uy = cl[5 * kWave];
                 const double z = a.z0 + ((double)(kb + k) + 0.5) * a.dz;
                 const double wz = z - az;
                 const double tc = fma(wz, uz, txy);
@@ -162,7 +224,7 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
                     thr2 = thr * thr;
                     R2 = Rs * Rs;
                 }
-                const bool pass = valid && fma(ex, ex, m2) < thr2;
+                const bool pass = valid && ((zmask >> k) & 1u) && fma(ex, ex, m2) < thr2;
                 const uint64_t mask = ballot64(pass);
                 if (mask == 0ull) continue;
                 if (pass) {
@@ -180,12 +242,42 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
                 __builtin_amdgcn_wave_barrier();
                 const int n = __popcll(mask);
                 T s_ = acc_s[k], c_ = acc_c[k];
-                for (int j = 0; j < n; ++j) {
-                    const T term = K == LSL_KERNEL_GAUSS
-                                       ? eval_term_gauss<T>(stage[j], dX, dY, d2, gk1, gk2, gc0)
-                                       : eval_term<T>(stage[j], dX, dY, d2);
-                    comp_add(term, s_, c_);
-                    if (STATS) n_useful += term > T(0) ? 1ull : 0ull;
+                auto term_at = [&](int j) -> T {
+                    const T t = K == LSL_KERNEL_GAUSS
+                                    ? eval_term_gauss<T>(stage[j], dX, dY, d2, gk1, gk2, gc0)
+                                    : eval_term<T>(stage[j], dX, dY, d2);
+                    if (STATS) n_useful += t > T(0) ? 1ull : 0ull;
+                    return t;
+                };
+                if (G == 1) {
+                    for (int j = 0; j < n; ++j) comp_add(term_at(j), s_, c_);
+                } else {
+                    T* pk = pend + k * kWave + lane;
+                    int q = open[k];
+                    int j = 0;
+                    if (q != 0) {               // complete the run left open
+                        T g = *pk;
+                        for (; j < n && q < G; ++j, ++q) g += term_at(j);
+                        if (q == G) {
+                            comp_add(g, s_, c_);
+                            q = 0;
+                        } else {
+                            *pk = g;
+                        }
+                    }
+#pragma unroll 1
+                    for (; j + G <= n; j += G) {
+                        T g = term_at(j);
+#pragma unroll
+                        for (int i = 1; i < G; ++i) g += term_at(j + i);
+                        comp_add(g, s_, c_);
+                    }
+                    if (j < n) {                // open a run with the rest
+                        T g = term_at(j);
+                        for (q = 1, ++j; j < n; ++j, ++q) g += term_at(j);
+                        *pk = g;
+                    }
+                    open[k] = q;
                 }
                 if (STATS) n_cand += pix ? (unsigned long long)n : 0ull;
                 acc_s[k] = s_;
@@ -193,6 +285,12 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
                 __builtin_amdgcn_wave_barrier();
             }
         }
+    }
+
+    if (G > 1) {
+#pragma unroll
+        for (int k = 0; k < SZ; ++k)
+            if (open[k] != 0) comp_add(pend[k * kWave + lane], acc_s[k], acc_c[k]);
     }
 
     if (STATS) {

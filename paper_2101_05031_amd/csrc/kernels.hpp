@@ -20,6 +20,7 @@ struct PrepArgs {
     uint32_t* key_hi;                 // float64 lattices only
     uint32_t* vals;                   // edge ids
     SRange* ranges;
+    PRange* pranges;
     // plan histograms
     uint32_t* cnt_lo;                 // [n_slabs] struts whose first slab is s
     uint32_t* cnt_hi;                 // [n_slabs] struts whose last slab is s
@@ -40,6 +41,7 @@ struct GatherArgs {
     const void* weight;
     const uint32_t* perm;             // [n_binned] sorted position -> edge id
     const SRange* ranges_by_id;
+    const PRange* pranges_by_id;
     int64_t n_binned;
     double R;
     const void* support;              // per-strut supports or null
@@ -47,6 +49,7 @@ struct GatherArgs {
     double sigma;
     void* rec;                        // StrutRec<T> [n_binned]; pad holds R_j with supports
     SRange* ranges;                   // [n_binned]
+    PRange* pranges;                  // [n_binned]
     void* w;                          // T [n_binned]
     int2* ends;                       // [n_binned]
 };
@@ -109,6 +112,7 @@ struct FieldArgs {
     int32_t k0, nk;                   // planes written: [k0, k0+nk)
     int32_t W, H;
     double x0, y0, dx, dy, z0, dz, R;
+    const PRange* pranges;            // [n_binned] pixel and plane ranges of rec[]
     int32_t strut_R;                  // 1: strut j's support is rec[j].pad, else R
     int32_t kernel;                   // LSL_KERNEL_*
     double gk1, gk2, gc0;             // Gaussian: 1/(sigma sqrt 2), 1/(2 sigma^2), sigma sqrt(pi/2)

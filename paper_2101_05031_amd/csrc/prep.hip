@@ -65,6 +65,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
     const bool live = e < a.n_edges;
     bool binned = false;
     SRange rg{0, 0, 0, 0, 0, -1};
+    PRange pr{0, 0, 0, 0, 0, -1};
     uint32_t klo = 0xffffffffu, khi = 0xffffffffu;
     unsigned long long ntile = 0;
     if (live) {
@@ -109,6 +110,12 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
                                                 a.inv_dy, a.H);
                 if (rz.ok && rx.ok && ry.ok) {
                     binned = true;
+                    pr.i0 = (uint16_t)rx.i0;
+                    pr.i1 = (uint16_t)rx.i1;
+                    pr.j0 = (uint16_t)ry.i0;
+                    pr.j1 = (uint16_t)ry.i1;
+                    pr.k0 = rz.i0;
+                    pr.k1 = rz.i1;
                     rg.s0 = rz.i0 / a.slab;
                     rg.s1 = rz.i1 / a.slab;
                     rg.tx0 = (uint16_t)(rx.i0 / a.tile);
@@ -134,6 +141,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
         if (a.key_s0) a.key_s0[e] = binned ? (uint32_t)rg.s0 : (uint32_t)a.n_slabs;
         a.vals[e] = (uint32_t)e;
         a.ranges[e] = rg;
+        a.pranges[e] = pr;
     }
     // plan histograms: struts starting / ending in each slab, and a
     // difference array of (slab, tile) pairs
@@ -188,6 +196,7 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
     r.pad = a.support ? ((const T*)a.support)[e] : T(0);
     ((StrutRec<T>*)a.rec)[p] = r;
     a.ranges[p] = a.ranges_by_id[e];
+    a.pranges[p] = a.pranges_by_id[e];
     ((T*)a.w)[p] = (T)w;
     a.ends[p] = make_int2(ia, ib);
 }

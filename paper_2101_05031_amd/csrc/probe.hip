@@ -48,7 +48,8 @@ __global__ __launch_bounds__(256) void k_probe_f64(double* out, int iters, doubl
 }
 
 // The field kernel's per-pair sequence alone: 64 staged struts in LDS (as
-// the field kernel stages them), every lane one pixel of an 8x8 block.
+// the field kernel stages them), every lane one pixel of an 8x8 block, the
+// terms summed as the field kernel sums them (runs of Group<float>::n).
 __global__ __launch_bounds__(256) void k_probe_term(float* out, int iters) {
     __shared__ Stage<float> st[4][kWave];
     const int lane = lane_id(), wv = threadIdx.x >> 6;
@@ -66,9 +67,15 @@ __global__ __launch_bounds__(256) void k_probe_term(float* out, int iters) {
     const float dX = 0.05f * ((float)(lane & 7) - 3.5f), dY = 0.05f * ((float)(lane >> 3) - 3.5f);
     const float d2 = dX * dX + dY * dY;
     float s = 0.0f, c = 0.0f;
+    constexpr int G = fieldk::Group<float>::n;
+    static_assert(kWave % G == 0, "runs must tile the staged list");
     for (int i = 0; i < iters; ++i)
-        for (int j = 0; j < kWave; ++j)
-            fieldk::comp_add(fieldk::eval_term<float>(st[wv][j], dX, dY, d2), s, c);
+        for (int j = 0; j < kWave; j += G) {
+            float g = fieldk::eval_term<float>(st[wv][j], dX, dY, d2);
+#pragma unroll
+            for (int q = 1; q < G; ++q) g += fieldk::eval_term<float>(st[wv][j + q], dX, dY, d2);
+            fieldk::comp_add(g, s, c);
+        }
     out[blockIdx.x * 256 + threadIdx.x] = s + c;
 }
 

@@ -86,18 +86,22 @@ def test_field_matches_oracle(case):
 
 
 def test_field_independent_of_tiling_and_groups():
-    """The same struts reach each pixel in the same order whatever the tile,
-    slab or group split, so the float32 field is bitwise the same."""
+    """Each 8x8 block and plane gets the same candidate struts in the same
+    order whatever the tile, slab or group split (the candidate counts agree
+    exactly), so the float32 field, summed in runs of four candidates, is
+    bitwise the same."""
     lat, grid = small_kuhn()
-    base = None
+    base = base_stats = None
     for tile, slab, mp in [(16, 8, 0), (8, 1, 0), (32, 4, 0), (64, 16, 0), (16, 2, 2500)]:
         print(f"tiling tile={tile} slab={slab} max_pairs={mp}", flush=True)
         b = bin_lattice(lat, grid, tile=tile, slab=slab, max_pairs=mp)
         f = api.slice_field(b, 0, grid.n_slices).cpu().numpy()
+        st = api.slice_field_stats(b, 0, grid.n_slices)
         if base is None:
-            base = f
+            base, base_stats = f, st
         else:
             assert np.array_equal(f.view(np.uint32), base.view(np.uint32))
+            assert st == base_stats
 
 
 def test_field_partial_ranges_and_repeatability():

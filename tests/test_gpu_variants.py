@@ -46,6 +46,26 @@ def test_one_support_per_strut_is_bitwise_the_plain_path():
         assert torch.equal(fa.view(torch.int32), fb.view(torch.int32))
 
 
+def test_per_strut_supports_independent_of_tile_and_groups():
+    """With per-strut supports the edge-list order has the first slab as its
+    major key, so it is fixed once the slab depth is; then the tile size and
+    the group split leave every block's candidates and the field bitwise the
+    same."""
+    lat, grid = small_kuhn()
+    lat = synth.with_supports(lat)
+    base = base_stats = None
+    for tile, mp in ((16, 0), (8, 0), (32, 0), (64, 0), (16, 2500)):
+        print(f"per-strut supports tile={tile} slab=4 max_pairs={mp}", flush=True)
+        b = bin_lattice(lat, grid, tile=tile, slab=4, max_pairs=mp)
+        f = api.slice_field(b, 0, grid.n_slices).cpu().numpy()
+        st = api.slice_field_stats(b, 0, grid.n_slices)
+        if base is None:
+            base, base_stats = f, st
+        else:
+            assert np.array_equal(f.view(np.uint32), base.view(np.uint32))
+            assert st == base_stats
+
+
 @pytest.mark.parametrize("dtype,tile,slab,max_pairs", [
     (np.float32, 16, 8, 0), (np.float32, 8, 3, 2500), (np.float64, 32, 4, 0)])
 def test_per_strut_supports_match_oracle(dtype, tile, slab, max_pairs):
