@@ -300,10 +300,10 @@ def slice_batch(bins: Bins, k0: int, nk: int, field=None, bits=None, capacity: i
 
 def slice_autotune(nodes, edges, weight, R: float, C: float, grid, cache_path: str | None = None,
                    tile: int = 0, slab: int = 0, support=None, kernel: str = "quartic",
-                   sigma: float | None = None, stream=None) -> dict:
+                   sigma: float | None = None, max_pairs: int = 0, stream=None) -> dict:
     L = _lattice_struct(nodes, edges, weight, R, C, support, kernel, sigma)
     g = _grid_struct(grid)
-    p = N.LslBinParams(int(tile), int(slab), 0)
+    p = N.LslBinParams(int(tile), int(slab), int(max_pairs))
     path = cache_path.encode() if cache_path else None
     N.check(N.lib().slice_autotune(byref(L), byref(g), byref(p), path, _stream(stream)),
             "slice_autotune")

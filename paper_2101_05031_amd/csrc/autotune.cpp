@@ -1,6 +1,6 @@
 // slice_autotune: picks the tile edge and slab depth for a lattice and grid
-// by binning with each candidate and timing the field on a few sampled plane
-// windows.  The field does not depend on the choice (every pixel sees the
+// by binning with each candidate (all slab groups, as one pass over the planes
+// bins them) and timing the field on a few sampled plane windows.  The field does not depend on the choice (every pixel sees the
 // same struts in the same order), so only speed is compared.  Results are
 // cached in a small JSON file keyed by the problem's shape.
 #include <hip/hip_runtime.h>
@@ -155,12 +155,27 @@ extern "C" lsl_status slice_autotune(const lsl_lattice* L, const lsl_grid* G,
                 }
                 field_s += best_ms * 1e-3;
             }
+            // a pass over all planes bins every group after the first once,
+            // each from its predecessor's active struts: time that sequence
+            double groups_s = 0;
+            lsl_bins_info inf{};
+            if (rs == LSL_OK) rs = lattice_bins_info(b, &inf);
+            if (rs == LSL_OK && inf.n_groups > 1) {
+                rs = lattice_bins_export(b, 0, nullptr, nullptr, stream);
+                if (rs == LSL_OK && hipStreamSynchronize(st) != hipSuccess) rs = LSL_EDEVICE;
+                const auto g0 = std::chrono::steady_clock::now();
+                for (int g = 1; g < inf.n_groups && rs == LSL_OK; ++g)
+                    rs = lattice_bins_export(b, g, nullptr, nullptr, stream);
+                if (rs == LSL_OK && hipStreamSynchronize(st) != hipSuccess) rs = LSL_EDEVICE;
+                groups_s =
+                    std::chrono::duration<double>(std::chrono::steady_clock::now() - g0).count();
+            }
             lattice_bins_free(b);
             if (rs != LSL_OK) {
                 result = rs;
                 break;
             }
-            const double score = field_s / (nwin * win) * G->n_slices + bin_s;
+            const double score = field_s / (nwin * win) * G->n_slices + bin_s + groups_s;
             if (score < best) {
                 best = score;
                 bt = t;

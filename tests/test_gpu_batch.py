@@ -106,6 +106,14 @@ def test_autotune_choice_and_cache(tmp_path):
     f0 = api.slice_field(b0, 0, grid.n_slices)
     f1 = api.slice_field(b1, 0, grid.n_slices)
     assert torch.equal(f0.view(torch.int32), f1.view(torch.int32))
+    # candidates with several slab groups: the later groups' binning is
+    # timed too
+    assert bin_lattice(lat, grid, tile=16, slab=4, max_pairs=20000).info()["n_groups"] > 1
+    p4 = api.slice_autotune(n, e, w, lat.R, lat.C, grid, max_pairs=20000)
+    assert p4["tile"] in (16, 32) and p4["slab"] in (4, 8, 16)
+    b4 = bin_lattice(lat, grid, tile=p4["tile"], slab=p4["slab"], max_pairs=20000)
+    f4 = api.slice_field(b4, 0, grid.n_slices)
+    assert torch.equal(f4.view(torch.int32), f0.view(torch.int32))
 
 
 @pytest.mark.parametrize("name,k0,nk", [("B3", 1000, 8), ("S5", 2000, 4)])
