@@ -8,10 +8,13 @@
 //
 //   tc = (c - a).u,  m = a + tc u - c  (m is orthogonal to u),
 //
-// and drops the strut for that plane when the exact distance from c to the
-// segment is at least R + r_block (no pixel of the block can then be within
-// R).  The surviving struts are compacted into LDS with a ballot/mbcnt
-// prefix.  For a pixel p = c + d (d in the plane, |d| <= r_block) the
+// and drops the strut for that plane when no pixel of the block can be within
+// R of the segment: with F* the segment's point nearest to c, D = |F* - c| and
+// n = (F* - c)/D, the segment lies in n.(x - F*) >= 0, so a pixel c + d is at
+// least D - n.d >= D - (3.5 dx |n_x| + 3.5 dy |n_y|) from it (the block is
+// flat, so struts passing above or below it are dropped sooner than by a
+// bounding circle).  The surviving struts are compacted into LDS with a
+// ballot/mbcnt prefix.  For a pixel p = c + d (d in the plane) the
 // arclength coordinates of the strut ends with origin at the foot of p are
 //
 //   alpha = -tc - d.u,   beta = (L - tc) - d.u,

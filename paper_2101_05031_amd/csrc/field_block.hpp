@@ -146,10 +146,11 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
     const T dX = (T)(((double)lx - 3.5) * a.dx);
     const T dY = (T)(((double)ly - 3.5) * a.dy);
     const T d2 = dX * dX + dY * dY;
-    const double rb = 3.5 * sqrt(a.dx * a.dx + a.dy * a.dy);
-    // one support: the cull radius of a block and R^2 are uniform
-    const double thr_u = (a.R + rb) * (1.0 + 1e-7);
-    const double thr2_u = thr_u * thr_u;
+    // half extents of the block's pixel centres about c
+    const double hx = 3.5 * a.dx, hy = 3.5 * a.dy;
+    // one support: the (slightly widened) cull radius and R^2 are uniform
+    const double Rc_u = a.R * (1.0 + 1e-7);
+    const double Rc2_u = Rc_u * Rc_u;
     const double R2_u = a.R * a.R;
     const uint64_t lt = lanes_below(lane);
     const T gk1 = (T)a.gk1, gk2 = (T)a.gk2, gc0 = (T)a.gc0;
@@ -214,17 +215,25 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
                 const double tc = fma(wz, uz, txy);
                 const double mx = fma(tc, ux, -wx), my = fma(tc, uy, -wy), mz = fma(tc, uz, -wz);
                 const double m2 = fma(mx, mx, fma(my, my, mz * mz));
-                const double ex = tc < 0.0 ? -tc : (tc > L ? tc - L : 0.0);
+                // e = F* - c, F* the point of the segment nearest to c, and
+                // D = |e|.  The segment lies in the half-space n.(x - F*) >= 0
+                // (n = e / D), so a pixel c + d of the block is at least
+                // D - n.d >= D - (hx |e_x| + hy |e_y|) / D from it: the strut
+                // reaches no pixel when D^2 - hx |e_x| - hy |e_y| >= R D.
+                const double dt = fmin(fmax(tc, 0.0), L) - tc;
+                const double ex = fma(dt, ux, mx), ey = fma(dt, uy, my);
+                const double D2 = fma(dt, dt, m2);
+                const double q = D2 - fma(hx, fabs(ex), hy * fabs(ey));
                 // per-strut supports: the strut's cull radius and R^2, formed
                 // here to keep no doubles live across the evaluation loop
-                double thr2 = thr2_u, R2 = R2_u;
+                double Rc2 = Rc2_u, R2 = R2_u;
                 if (SR) {
                     const double Rs = (double)r.pad;
-                    const double thr = (Rs + rb) * (1.0 + 1e-7);
-                    thr2 = thr * thr;
+                    const double Rc = Rs * (1.0 + 1e-7);
+                    Rc2 = Rc * Rc;
                     R2 = Rs * Rs;
                 }
-                const bool pass = valid && ((zmask >> k) & 1u) && fma(ex, ex, m2) < thr2;
+                const bool pass = valid && ((zmask >> k) & 1u) && (q <= 0.0 || q * q < Rc2 * D2);
                 const uint64_t mask = ballot64(pass);
                 if (mask == 0ull) continue;
                 if (pass) {
