@@ -216,10 +216,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
     const T dY = (T)(((double)ly - 3.5) * a.dy);
     const T d2 = dX * dX + dY * dY;
     const T dX2 = dX + dX, dY2 = dY + dY;
-    const double rb = 3.5 * sqrt(a.dx * a.dx + a.dy * a.dy);
-    // one support: the cull radius of a block and R^2 are uniform
-    const double thr_u = (a.R + rb) * (1.0 + 1e-7);
-    const double thr2_u = thr_u * thr_u;
+    // half extents of a block's pixel centres about its centre
+    const double hx = 3.5 * a.dx, hy = 3.5 * a.dy;
+    // one support: the (slightly widened) cull radius and R^2 are uniform
+    const double Rc_u = a.R * (1.0 + 1e-7);
+    const double Rc2_u = Rc_u * Rc_u;
     const double R2_u = a.R * a.R;
     const uint64_t lt = lanes_below(lane);
     const int own = deposit_owner(lane);
@@ -271,16 +272,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
                     const double mx = fma(tc, ux, -wx), my = fma(tc, uy, -wy),
                                  mz = fma(tc, uz, -wz);
                     const double m2 = fma(mx, mx, fma(my, my, mz * mz));
-                    const double ex = tc < 0.0 ? -tc : (tc > L ? tc - L : 0.0);
+                    // the field kernel's reach test: with e = F* - c (F* the
+                    // segment's point nearest to c), no pixel of the block is
+                    // within R when D^2 - hx |e_x| - hy |e_y| >= R D
+                    const double dt = fmin(fmax(tc, 0.0), L) - tc;
+                    const double ex = fma(dt, ux, mx), ey = fma(dt, uy, my);
+                    const double D2 = fma(dt, dt, m2);
+                    const double q = D2 - fma(hx, fabs(ex), hy * fabs(ey));
                     // per-strut supports: the strut's cull radius and R^2
-                    double thr2 = thr2_u, R2 = R2_u;
+                    double Rc2 = Rc2_u, R2 = R2_u;
                     if (SR) {
                         const double Rs = (double)r.pad;
-                        const double thr = (Rs + rb) * (1.0 + 1e-7);
-                        thr2 = thr * thr;
+                        const double Rc = Rs * (1.0 + 1e-7);
+                        Rc2 = Rc * Rc;
                         R2 = Rs * Rs;
                     }
-                    if (valid && fma(ex, ex, m2) < thr2) {
+                    if (valid && (q <= 0.0 || q * q < Rc2 * D2)) {
                         planes |= 1u << k;
                         BPlane<T> P;
                         P.mx = (T)mx;
