@@ -71,6 +71,9 @@ class Bins:
     def __init__(self, handle: int, dtype, grid, R: float, C: float, n_nodes: int,
                  n_edges: int):
         self.handle = c_void_p(handle)
+        # held here so that a handle collected at interpreter exit, after the
+        # module's globals are gone, is still freed
+        self._free = N.lib().lattice_bins_free
         self.dtype = dtype
         self.grid = grid
         self.R, self.C = R, C
@@ -78,8 +81,9 @@ class Bins:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
-            N.lib().lattice_bins_free(h)
+        free = getattr(self, "_free", None)
+        if h is not None and h.value and free is not None:
+            free(h)
             self.handle = None
 
     def info(self) -> dict:
