@@ -88,7 +88,9 @@ __device__ __forceinline__ void comp_add(T t, T& s, T& c) {
 
 // Terms per compensated add.  float32 adds each run of four consecutive
 // candidates of a (block, plane) plainly, ((t0 + t1) + t2) + t3, and
-// compensates once per run; float64 compensates every term.  Runs are counted
+// compensates once per run; float64 compensates every term, and so does the
+// Gaussian term (two erf and one exp per pair dwarf the sum, and the runs'
+// extra registers would spill).  Runs are counted
 // over the whole candidate sequence of the (block, plane), across the 64-entry
 // chunks of the bucket list: a run left open at the end of a chunk waits in
 // LDS (`pend`, [SZ][64] per wave) for the next one.
@@ -120,7 +122,7 @@ constexpr int kLineVals = 6;
 template <typename T, int SZ, bool STATS, int K, bool SR>
 __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx, int ty, int sub,
                                             Stage<T>* stage, T* pend, double* line) {
-    constexpr int G = Group<T>::n;
+    constexpr int G = K == LSL_KERNEL_GAUSS ? 1 : Group<T>::n;
     const int lane = lane_id();
     const uint32_t n_binned = a.n_binned, n_pairs = a.n_pairs;
     const int nsub = a.tile / kBlockPix;
