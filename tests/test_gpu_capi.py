@@ -58,6 +58,15 @@ def test_tool_rejects_bad_input(tmp_path):
     r = subprocess.run([B.TOOL, str(bad), str(tmp_path / "o.bin"), "0", "1"],
                        capture_output=True, text=True, timeout=60)
     assert r.returncode == 2 and "header" in r.stderr
+    # a plane range outside the grid
+    lat = synth.kuhn_lattice(2, 10.0, seed=1, dtype=np.float32)
+    grid = synth.grid_for(lat, 40, 40, 3, dz=1.0)
+    good = tmp_path / "lat.bin"
+    write_lattice(good, lat, grid)
+    for k0, nk in (("2", "5"), ("-1", "1"), ("0", "0")):
+        r = subprocess.run([B.TOOL, str(good), str(tmp_path / "o.bin"), k0, nk],
+                           capture_output=True, text=True, timeout=60)
+        assert r.returncode == 1 and "planes" in r.stderr
 
 
 @pytest.mark.gpu
