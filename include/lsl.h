@@ -27,8 +27,8 @@
  *    the device synchronise that stream; this is stated per call.
  *  - Errors are returned, never thrown, and leave outputs unspecified.
  *    lsl_last_error() gives a message for the calling thread's last error.
- *  - dtype LSL_F32 computes in float32 (compensated sums), LSL_F64 in
- *    float64.  Field, weight and gradient arrays use the lattice's dtype.
+ *  - dtype LSL_F32 computes in float32 (compensated sums of runs of terms),
+ *    LSL_F64 in float64.  Field, weight and gradient arrays use the lattice's dtype.
  *  - Image layout: [slice][row j][column i], i fastest.
  *  - A handle may be used by one stream at a time.
  */
@@ -198,8 +198,12 @@ lsl_status lattice_bins_order(const lattice_bins* bins, int32_t* order,
  * field: [nk][H][W] of the lattice dtype (required).  bits: optional
  * [nk][H][ceil(W/32)] uint32, bit (i % 32) of word i/32 set where
  * field >= C (the binary image of Sec. 4).  Per pixel the sum runs over the
- * struts of its tile's bucket in edge-list order; terms outside the support
- * are exactly zero.  float32 sums are compensated.  Builds missing groups
+ * struts that can reach the pixel's 8x8 block in that plane, in edge-list
+ * order; terms outside the support are exactly zero.  float32 sums add runs
+ * of four consecutive terms and compensate once per run (the Gaussian
+ * variant and float64 compensate every term); the candidates of a block and
+ * plane, hence the field's bits, do not depend on the tile, slab depth or
+ * group split.  Builds missing groups
  * (stream-ordered, no synchronisation).  Errors: LSL_EINVAL (range outside
  * [0, n_slices)), LSL_ENOMEM, LSL_EDEVICE.
  * ------------------------------------------------------------------------- */
