@@ -31,10 +31,12 @@ constexpr uint64_t kCol0 = 0x0101010101010101ull;   // column 0 of every row
 constexpr uint64_t kCol7 = 0x8080808080808080ull;   // column 7 of every row
 
 // Per case: number of segments and up to two segments as
-// (x0, y0, x1, y1) in half units of the cell.
-__constant__ int8_t kSegCount[16] = {0, 1, 1, 1, 1, 2, 1, 1, 1, 1, 2, 1, 1, 1, 1, 0};
+// (x0, y0, x1, y1) in half units of the cell.  The tables are folded at
+// compile time into register constants (kSegCountBits, kSegWord), so a
+// lane's lookup by its own case is arithmetic, not a memory load.
+constexpr int8_t kSegCountT[16] = {0, 1, 1, 1, 1, 2, 1, 1, 1, 1, 2, 1, 1, 1, 1, 0};
 // edge midpoints in half units: B=(1,0) E=(2,1) T=(1,2) L=(0,1)
-__constant__ int8_t kSeg[16][2][4] = {
+constexpr int8_t kSegT[16][2][4] = {
     {{0, 0, 0, 0}, {0, 0, 0, 0}},
     {{1, 0, 0, 1}, {0, 0, 0, 0}},   // 1: B -> L
     {{2, 1, 1, 0}, {0, 0, 0, 0}},   // 2: E -> B
@@ -52,6 +54,37 @@ __constant__ int8_t kSeg[16][2][4] = {
     {{0, 1, 1, 0}, {0, 0, 0, 0}},   // 14: L -> B
     {{0, 0, 0, 0}, {0, 0, 0, 0}},
 };
+
+// 2 bits per case: the segment count
+constexpr uint32_t seg_count_bits() {
+    uint32_t r = 0;
+    for (int c = 0; c < 16; ++c) r |= (uint32_t)kSegCountT[c] << (2 * c);
+    return r;
+}
+// cases 4w .. 4w+3, 16 bits each: segment s in bits 8s .. 8s+7, its
+// coordinates (each 0, 1 or 2) in 2 bits apiece, x0 lowest
+constexpr uint64_t seg_word(int w) {
+    uint64_t r = 0;
+    for (int c = 0; c < 4; ++c)
+        for (int s = 0; s < 2; ++s)
+            for (int e = 0; e < 4; ++e)
+                r |= (uint64_t)kSegT[4 * w + c][s][e] << (16 * c + 8 * s + 2 * e);
+    return r;
+}
+constexpr uint32_t kSegCountBits = seg_count_bits();
+constexpr uint64_t kSegWord[4] = {seg_word(0), seg_word(1), seg_word(2), seg_word(3)};
+
+__device__ __forceinline__ int seg_count(int cs) { return (int)((kSegCountBits >> (2 * cs)) & 3u); }
+
+// segment s of case cs as (x0, y0, x1, y1) in half units
+__device__ __forceinline__ void seg_points(int cs, int s, int8_t g[4]) {
+    const int w = cs >> 2;
+    const uint64_t word = w == 0 ? kSegWord[0] : w == 1 ? kSegWord[1]
+                        : w == 2 ? kSegWord[2] : kSegWord[3];
+    const uint32_t b = (uint32_t)(word >> (16 * (cs & 3) + 8 * s)) & 0xffu;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) g[e] = (int8_t)((b >> (2 * e)) & 3u);
+}
 
 
 // The four corner masks of the 64 cells of block (bx, by) of one plane, with
@@ -233,12 +266,13 @@ __global__ __launch_bounds__(kMThreads) void k_strip_emit(const uint64_t* img, i
                     const int cs = (int)(((c.b0 >> bit) & 1ull) | (((c.b1 >> bit) & 1ull) << 1) |
                                          (((c.b2 >> bit) & 1ull) << 2) |
                                          (((c.b3 >> bit) & 1ull) << 3));
-                    const int n = kSegCount[cs];
+                    const int n = seg_count(cs);
                     const int ci = i0 + cc, cj = j0 + r;
                     const T* f = SUB ? (const T*)sp.field + k * (uint64_t)W * (uint64_t)H : nullptr;
                     for (int sg = 0; sg < n; ++sg) {
                         if ((int64_t)(o + sg) < capacity) {
-                            const int8_t* g = kSeg[cs][sg];
+                            int8_t g[4];
+                            seg_points(cs, sg, g);
                             uint32_t es = 0, ee = 0;
                             const float2 a = seg_end<SUB, T>(g, ci, cj, W, f, (T)sp.C, &es);
                             const float2 b = seg_end<SUB, T>(g + 2, ci, cj, W, f, (T)sp.C, &ee);
