@@ -154,7 +154,6 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
     const double Rc_u = a.R * (1.0 + 1e-7);
     const double Rc2_u = Rc_u * Rc_u;
     const double R2_u = a.R * a.R;
-    const uint64_t lt = lanes_below(lane);
     const T gk1 = (T)a.gk1, gk2 = (T)a.gk2, gc0 = (T)a.gc0;
 
     // the block's pixel columns and rows (for the range test)
@@ -194,7 +193,6 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
         double* cl = line + lane;
         const Line ln = strut_line(r);
         const double L = ln.L, uz = ln.uz;
-        const T uxT = (T)ln.ux, uyT = (T)ln.uy;
         {
             const double wx = cx - ax, wy = cy - ay;
             cl[0 * kWave] = az;
@@ -242,13 +240,16 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
                     Stage<T> s;
                     s.mx2 = (T)(2.0 * mx);
                     s.my2 = (T)(2.0 * my);
-                    s.ux = uxT;
-                    s.uy = uyT;
+                    s.ux = (T)ux;
+                    s.uy = (T)uy;
                     s.ntc = (T)(-tc);
                     s.nbtc = (T)(L - tc);
                     s.H0 = (T)(R2 - m2);
                     s.wq = r.wq;
-                    stage[__popcll(mask & lt)] = s;
+                    // rank among the passing lanes: set bits of mask below this lane
+                    const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                    stage[rank] = s;
                 }
                 __builtin_amdgcn_wave_barrier();
                 const int n = __popcll(mask);
