@@ -222,7 +222,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
     const double Rc_u = a.R * (1.0 + 1e-7);
     const double Rc2_u = Rc_u * Rc_u;
     const double R2_u = a.R * a.R;
-    const uint64_t lt = lanes_below(lane);
     const int own = deposit_owner(lane);
     const StrutRec<T>* recs = (const StrutRec<T>*)a.rec;
     const T* grad = (const T*)a.grad;
@@ -302,7 +301,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
             const uint64_t mask = ballot64(planes != 0u);
             if (mask == 0ull) continue;
             if (planes != 0u) {
-                const int q = __popcll(mask & lt);
+                const int q = (int)__builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
                 bs_ux[q] = (T)ux;
                 bs_uy[q] = (T)uy;
                 bs_uz[q] = (T)uz;
