@@ -366,8 +366,9 @@ lsl_status slice_batch(lattice_bins* bins, int32_t k0, int32_t nk, void* field,
  * slice_autotune -- choose tile and slab sizes by binning with each
  * candidate and timing the binning (to the end of its device work, after one
  * untimed warm-up binning), the binning of the later slab groups in order (as
- * one pass over all planes does it) and the field on sampled plane windows of
- * this lattice and grid (the field time scaled to all planes).  params is [host] in/out:
+ * one pass over all planes does it) and slice_batch's field launch on sampled
+ * plane windows of this lattice and grid (the field time scaled to all
+ * planes).  params is [host] in/out:
  * nonzero fields are kept, zero fields are filled.  cache_path (optional,
  * [host] C string) is a JSON file of earlier choices keyed by problem shape
  * and kernel variant;
