@@ -121,6 +121,11 @@ typedef struct lsl_bins_info {
     double last_group_bin_ms;   /* the same call's other stages, summed over its */
     double last_queue_ms;       /* slab groups: binning of groups not resident,  */
     double last_contour_ms;     /* work-queue build, binary image + contours     */
+    int32_t plane_group;    /* planes that share one reference plane in the
+                               float32 field kernel of the paper's kernel: 8
+                               when 7 dz |d| <= R^2 / 10 (d the farthest pixel
+                               of an 8x8 block from its centre, R the smallest
+                               support), else 1; 1 for other kernels          */
 } lsl_bins_info;
 
 /* ---------------------------------------------------------------------------

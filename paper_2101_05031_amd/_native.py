@@ -46,7 +46,8 @@ class LslBinsInfo(Structure):
                 ("tiles_x", c_int32), ("tiles_y", c_int32), ("n_slabs", c_int32),
                 ("n_groups", c_int32), ("current_group", c_int32),
                 ("last_field_ms", c_double), ("last_group_bin_ms", c_double),
-                ("last_queue_ms", c_double), ("last_contour_ms", c_double)]
+                ("last_queue_ms", c_double), ("last_contour_ms", c_double),
+                ("plane_group", c_int32)]
 
 
 class LslSupport(Structure):

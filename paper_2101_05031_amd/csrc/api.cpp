@@ -133,6 +133,7 @@ struct lattice_bins {
     uint32_t n_binned = 0;
     double R = 0, C = 0;
     bool strut_R = false;              // per-strut supports (in rec[].pad)
+    bool plane_ref = false;            // float32 field: every plane its own reference
     int32_t kernel = LSL_KERNEL_QUARTIC;
     double sigma = 0;
     lsl_grid grid{};
@@ -155,6 +156,7 @@ struct lattice_bins {
     PRange* pranges = nullptr;
     void* w = nullptr;
     int2* ends = nullptr;
+    double4* line = nullptr;          // direction and length per strut, float64
 
     // resident group
     uint32_t* active[2] = {nullptr, nullptr};
@@ -437,6 +439,7 @@ lsl_status ensure_group(lattice_bins* b, int g, hipStream_t st) {
 FieldArgs field_args(const lattice_bins* b, int32_t k0, int32_t nk, void* field) {
     FieldArgs a{};
     a.rec = b->rec;
+    a.line = b->line;
     a.offsets = b->offsets;
     a.ids = b->ids;
     a.n_binned = b->n_binned;
@@ -458,6 +461,7 @@ FieldArgs field_args(const lattice_bins* b, int32_t k0, int32_t nk, void* field)
     a.pranges = b->pranges;
     a.strut_R = b->strut_R ? 1 : 0;
     a.kernel = b->kernel;
+    a.plane_ref = b->plane_ref ? 1 : 0;
     if (b->kernel == LSL_KERNEL_GAUSS) {
         a.gk1 = 1.0 / (b->sigma * std::sqrt(2.0));
         a.gk2 = 1.0 / (2.0 * b->sigma * b->sigma);
@@ -596,7 +600,7 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
     if (L->support && (s = b->alloc_t(&ks0, 3 * En))) return fail(s);
     uint32_t* cnt_lo = cnt;
     uint32_t* cnt_hi = cnt + ns;
-    uint32_t* counters = cnt + 2 * ns;   // [0] n_binned, [1] err
+    uint32_t* counters = cnt + 2 * ns;   // [0] n_binned, [1] err, [2] ~smallest support
     if ((s = fill_u32(cnt, 0u, 2 * (size_t)ns + 4, st)) ||
         (s = fill_bytes0(diff, ((size_t)ns + 1) * 8, st)))
         return fail(s);
@@ -629,6 +633,7 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
     pa.pair_diff = diff;
     pa.n_binned = counters;
     pa.err = counters + 1;
+    pa.min_support = counters + 2;
     pa.support = L->support;
     pa.key_s0 = ks0;
     pa.max_r_over_sigma = L->kernel == LSL_KERNEL_GAUSS ? kMaxROverSigma : 0.0;
@@ -690,6 +695,22 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
         return fail(LSL_EINVAL);
     }
     b->n_binned = h_cnt[2 * ns];
+    {
+        // The float32 field kernel shares one reference plane among 8 planes
+        // when the shift it applies stays small against the support:
+        // 7 dz |d| <= R^2 / 10 for the farthest pixel d of an 8x8 block and
+        // the smallest support; otherwise every plane is its own reference.
+        double rmin = L->R;
+        const uint32_t inv = h_cnt[2 * ns + 2];
+        if (L->support && inv != 0u) {
+            const uint32_t bits = ~inv;
+            float f;
+            std::memcpy(&f, &bits, 4);
+            rmin = (double)f;
+        }
+        const double dmax = 3.5 * std::sqrt(G->dx * G->dx + G->dy * G->dy);
+        b->plane_ref = !(7.0 * G->dz * dmax <= 0.1 * rmin * rmin);
+    }
     std::vector<uint32_t> vlo(h_cnt.begin(), h_cnt.begin() + ns);
     std::vector<uint32_t> vhi(h_cnt.begin() + ns, h_cnt.begin() + 2 * ns);
     if ((s = plan_groups(b, vlo, vhi, h_diff))) return fail(s);
@@ -700,7 +721,8 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
                                                          : sizeof(StrutRec<float>)))) ||
         (s = b->alloc_t(&b->perm, nb)) || (s = b->alloc_t(&b->ranges, nb)) ||
         (s = b->alloc_t(&b->pranges, nb)) ||
-        (s = b->alloc(&b->w, nb * b->esize())) || (s = b->alloc_t(&b->ends, nb)))
+        (s = b->alloc(&b->w, nb * b->esize())) || (s = b->alloc_t(&b->ends, nb)) ||
+        (s = b->alloc_t(&b->line, nb)))
         return fail(s);
     if (b->n_binned) {
         he = hipMemcpyAsync(b->perm, perm_src, (size_t)b->n_binned * 4, hipMemcpyDeviceToDevice, st);
@@ -725,6 +747,7 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
         ga.pranges = b->pranges;
         ga.w = b->w;
         ga.ends = b->ends;
+        ga.line = b->line;
         if ((s = launch_gather(L->dtype, ga, st))) return fail(s);
     }
     he = hipStreamSynchronize(st);
@@ -874,6 +897,8 @@ lsl_status lattice_bins_info(const lattice_bins* b, lsl_bins_info* o) {
     o->last_group_bin_ms = b->last_group_bin_ms;
     o->last_queue_ms = b->last_queue_ms;
     o->last_contour_ms = b->last_contour_ms;
+    o->plane_group =
+        (b->dtype == LSL_F32 && b->kernel == LSL_KERNEL_QUARTIC && !b->plane_ref) ? 8 : 1;
     return LSL_OK;
 }
 

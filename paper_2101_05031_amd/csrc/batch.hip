@@ -6,7 +6,10 @@
 // order), and a grid sized to the GPU's occupancy pulls items from it with
 // one atomic counter until the queue is drained.  Every block leaves the loop
 // once the counter passes the item count, so the grid always drains.
+#include <type_traits>
+
 #include "field_block.hpp"
+#include "field_q32.hpp"
 
 namespace lsl {
 namespace {
@@ -33,12 +36,9 @@ __global__ void k_queue_keys(FieldArgs a, uint32_t n_items, uint32_t* keys, uint
     vals[it] = it;
 }
 
-template <typename T, int SZ, int K, bool SR>
+template <typename T, int SZ, int K, bool SR, bool PR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_persistent(FieldArgs a, const uint32_t* queue,
                                                     uint32_t n_items, uint32_t* counter) {
-    __shared__ Stage<T> stage[4][kWave];
-    __shared__ T pend[4][fieldk::pend_elems<T, SZ>()];
-    __shared__ double line[4][fieldk::kLineVals * kWave];
     __shared__ uint32_t s_item;
     const int wv = threadIdx.x >> 6;
     const int nsub = a.tile / kBlockPix;
@@ -53,9 +53,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         t /= (uint32_t)a.ntx;
         const int ty = (int)(t % (uint32_t)a.nty);
         t /= (uint32_t)a.nty;
-        for (int sub = wv; sub < nsub * nsub; sub += 4)
-            fieldk::field_block<T, SZ, false, K, SR>(a, a.s_lo + (int)t, tx, ty, sub, stage[wv],
-                                                    pend[wv], line[wv]);
+        if constexpr (std::is_same<T, float>::value && K == LSL_KERNEL_QUARTIC) {
+            __shared__ q32::Lds<SZ, PR> lds[4];
+            for (int sub = wv; sub < nsub * nsub; sub += 4)
+                q32::field_block<SZ, false, SR, PR>(a, a.s_lo + (int)t, tx, ty, sub, lds[wv]);
+        } else {
+            __shared__ Stage<T> stage[4][kWave];
+            __shared__ T pend[4][fieldk::pend_elems<T, SZ>()];
+            __shared__ double line[4][fieldk::kLineVals * kWave];
+            for (int sub = wv; sub < nsub * nsub; sub += 4)
+                fieldk::field_block<T, SZ, false, K, SR>(a, a.s_lo + (int)t, tx, ty, sub,
+                                                         stage[wv], pend[wv], line[wv]);
+        }
     }
 }
 
@@ -66,7 +75,7 @@ int blocks_t() {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per, k_persistent<T, SZ, LSL_KERNEL_QUARTIC, false>, 256, 0) !=
+            &per, k_persistent<T, SZ, LSL_KERNEL_QUARTIC, false, false>, 256, 0) !=
         hipSuccess)
         return 0;
     return cus * (per > 0 ? per : 1);
@@ -81,21 +90,30 @@ int blocks_dt(int slab) {
     return blocks_t<T, 16>();
 }
 
-template <typename T, int K, bool SR>
-lsl_status persistent_dtk(const BatchArgs& b, int n_blocks, hipStream_t st) {
+template <typename T, int K, bool SR, bool PR>
+lsl_status persistent_dtkp(const BatchArgs& b, int n_blocks, hipStream_t st) {
     const int s = b.f.slab;
     if (s <= 1)
-        k_persistent<T, 1, K, SR><<<n_blocks, 256, 0, st>>>(b.f, b.queue, b.n_items, b.counter);
+        k_persistent<T, 1, K, SR, PR><<<n_blocks, 256, 0, st>>>(b.f, b.queue, b.n_items, b.counter);
     else if (s <= 2)
-        k_persistent<T, 2, K, SR><<<n_blocks, 256, 0, st>>>(b.f, b.queue, b.n_items, b.counter);
+        k_persistent<T, 2, K, SR, PR><<<n_blocks, 256, 0, st>>>(b.f, b.queue, b.n_items, b.counter);
     else if (s <= 4)
-        k_persistent<T, 4, K, SR><<<n_blocks, 256, 0, st>>>(b.f, b.queue, b.n_items, b.counter);
+        k_persistent<T, 4, K, SR, PR><<<n_blocks, 256, 0, st>>>(b.f, b.queue, b.n_items, b.counter);
     else if (s <= 8)
-        k_persistent<T, 8, K, SR><<<n_blocks, 256, 0, st>>>(b.f, b.queue, b.n_items, b.counter);
+        k_persistent<T, 8, K, SR, PR><<<n_blocks, 256, 0, st>>>(b.f, b.queue, b.n_items, b.counter);
     else
-        k_persistent<T, 16, K, SR><<<n_blocks, 256, 0, st>>>(b.f, b.queue, b.n_items, b.counter);
+        k_persistent<T, 16, K, SR, PR><<<n_blocks, 256, 0, st>>>(b.f, b.queue, b.n_items,
+                                                                 b.counter);
     LSL_HIP(hipGetLastError());
     return LSL_OK;
+}
+
+template <typename T, int K, bool SR>
+lsl_status persistent_dtk(const BatchArgs& b, int n_blocks, hipStream_t st) {
+    if constexpr (std::is_same<T, float>::value && K == LSL_KERNEL_QUARTIC) {
+        if (b.f.plane_ref) return persistent_dtkp<T, K, SR, true>(b, n_blocks, st);
+    }
+    return persistent_dtkp<T, K, SR, false>(b, n_blocks, st);
 }
 
 template <typename T>

@@ -34,16 +34,16 @@
 // order.  Sums are compensated, s' = s + g, e += g - (s' - s): float32 adds
 // each run of four consecutive candidates plainly, ((t0 + t1) + t2) + t3, and
 // compensates once per run; float64 compensates every term.
+#include <type_traits>
+
 #include "field_block.hpp"
+#include "field_q32.hpp"
 
 namespace lsl {
 namespace {
 
-template <typename T, int SZ, bool STATS, int K, bool SR>
+template <typename T, int SZ, bool STATS, int K, bool SR, bool PR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_field(FieldArgs a, uint32_t n_items) {
-    __shared__ Stage<T> stage[4][kWave];
-    __shared__ T pend[4][fieldk::pend_elems<T, SZ>()];
-    __shared__ double line[4][fieldk::kLineVals * kWave];
     const int wv = threadIdx.x >> 6;
     const uint32_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const uint32_t item = blk * 4u + (uint32_t)wv;
@@ -57,8 +57,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     t /= (uint32_t)a.ntx;
     const int ty = (int)(t % (uint32_t)a.nty);
     t /= (uint32_t)a.nty;
-    fieldk::field_block<T, SZ, STATS, K, SR>(a, a.s_lo + (int)t, tx, ty, sub, stage[wv],
-                                                    pend[wv], line[wv]);
+    if constexpr (std::is_same<T, float>::value && K == LSL_KERNEL_QUARTIC) {
+        __shared__ q32::Lds<SZ, PR> lds[4];
+        q32::field_block<SZ, STATS, SR, PR>(a, a.s_lo + (int)t, tx, ty, sub, lds[wv]);
+    } else {
+        __shared__ Stage<T> stage[4][kWave];
+        __shared__ T pend[4][fieldk::pend_elems<T, SZ>()];
+        __shared__ double line[4][fieldk::kLineVals * kWave];
+        fieldk::field_block<T, SZ, STATS, K, SR>(a, a.s_lo + (int)t, tx, ty, sub, stage[wv],
+                                                 pend[wv], line[wv]);
+    }
 }
 
 // Block-major binary image of a field: one wave takes 8 rows x 64 columns
@@ -88,15 +96,24 @@ __global__ __launch_bounds__(256) void k_bits_blk(const T* field, int32_t nk, in
     if (lane < 8 && c * 8 + lane < nbx) out[kb * (uint64_t)nbx + (uint64_t)(c * 8 + lane)] = word;
 }
 
-template <typename T, int SZ, int K, bool SR>
-lsl_status launch_tk(const FieldArgs& a, bool stats, uint32_t n_items, hipStream_t st) {
+template <typename T, int SZ, int K, bool SR, bool PR>
+lsl_status launch_tkp(const FieldArgs& a, bool stats, uint32_t n_items, hipStream_t st) {
     const unsigned blocks = (n_items + 3u) / 4u;
     if (stats)
-        k_field<T, SZ, true, K, SR><<<blocks, 256, 0, st>>>(a, n_items);
+        k_field<T, SZ, true, K, SR, PR><<<blocks, 256, 0, st>>>(a, n_items);
     else
-        k_field<T, SZ, false, K, SR><<<blocks, 256, 0, st>>>(a, n_items);
+        k_field<T, SZ, false, K, SR, PR><<<blocks, 256, 0, st>>>(a, n_items);
     LSL_HIP(hipGetLastError());
     return LSL_OK;
+}
+
+// The per-plane reference form exists for the float32 quartic kernel only.
+template <typename T, int SZ, int K, bool SR>
+lsl_status launch_tk(const FieldArgs& a, bool stats, uint32_t n_items, hipStream_t st) {
+    if constexpr (std::is_same<T, float>::value && K == LSL_KERNEL_QUARTIC) {
+        if (a.plane_ref) return launch_tkp<T, SZ, K, SR, true>(a, stats, n_items, st);
+    }
+    return launch_tkp<T, SZ, K, SR, false>(a, stats, n_items, st);
 }
 
 template <typename T, int SZ>

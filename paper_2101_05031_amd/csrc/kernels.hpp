@@ -27,6 +27,7 @@ struct PrepArgs {
     unsigned long long* pair_diff;    // [n_slabs + 1] difference array of pairs
     uint32_t* n_binned;
     uint32_t* err;                    // bit 0 index, 1 weight, 2 node, 3 support, 4 sigma
+    uint32_t* min_support;            // ~(float bits) of the smallest binned support, max-reduced
     // variants
     const void* support;              // [n_edges] per-strut supports, or null (R for all)
     uint32_t* key_s0;                 // [n_edges] first slab (n_slabs if not binned), or null
@@ -52,6 +53,7 @@ struct GatherArgs {
     PRange* pranges;                  // [n_binned]
     void* w;                          // T [n_binned]
     int2* ends;                       // [n_binned]
+    double4* line;                    // [n_binned] (u_x, u_y, u_z, L) of each strut, float64
 };
 lsl_status launch_gather(int dtype, const GatherArgs& a, hipStream_t st);
 lsl_status launch_gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t* dst,
@@ -103,6 +105,7 @@ lsl_status group_emi(const EmiArgs& a, hipStream_t st);
 // ---------------------------------------------------------------- field.hip
 struct FieldArgs {
     const void* rec;
+    const double4* line;              // [n_binned] direction and length of rec[] (float64)
     const uint32_t* offsets;
     const uint32_t* ids;
     uint32_t n_binned, n_pairs;       // bounds of rec[] and ids[]
@@ -116,6 +119,8 @@ struct FieldArgs {
     int32_t strut_R;                  // 1: strut j's support is rec[j].pad, else R
     int32_t kernel;                   // LSL_KERNEL_*
     double gk1, gk2, gc0;             // Gaussian: 1/(sigma sqrt 2), 1/(2 sigma^2), sigma sqrt(pi/2)
+    int32_t plane_ref;                // float32 quartic: 1 = every plane is its own
+                                      // reference plane (field_q32.hpp), 0 = groups of 8
     void* field;                      // [nk][H][W] or null (not written)
     uint64_t* bits_blk;               // [nk][ceil(H/8)][ceil(W/8)] or null: field >= C,
                                       // one word per 8x8 block (bit 8*row+col)

@@ -68,6 +68,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
     PRange pr{0, 0, 0, 0, 0, -1};
     uint32_t klo = 0xffffffffu, khi = 0xffffffffu;
     unsigned long long ntile = 0;
+    float rs_binned = 0.0f;             // the support of a binned strut
     if (live) {
         const int32_t ia = a.edges[2 * e], ib = a.edges[2 * e + 1];
         const T* nd = (const T*)a.nodes;
@@ -110,6 +111,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
                                                 a.inv_dy, a.H);
                 if (rz.ok && rx.ok && ry.ok) {
                     binned = true;
+                    rs_binned = (float)Rs;
                     pr.i0 = (uint16_t)rx.i0;
                     pr.i1 = (uint16_t)rx.i1;
                     pr.j0 = (uint16_t)ry.i0;
@@ -142,6 +144,16 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
         a.vals[e] = (uint32_t)e;
         a.ranges[e] = rg;
         a.pranges[e] = pr;
+    }
+    // the smallest support of a binned strut (positive floats order as their
+    // bits; the complement turns the minimum into a maximum from zero)
+    if (a.support && a.min_support) {
+        uint32_t inv = binned ? ~__float_as_uint(rs_binned) : 0u;
+        for (int d = 32; d >= 1; d >>= 1) {
+            const uint32_t o = (uint32_t)__shfl_xor((int)inv, d, kWave);
+            inv = inv > o ? inv : o;
+        }
+        if ((threadIdx.x & (kWave - 1)) == 0 && inv != 0u) atomicMax(a.min_support, inv);
     }
     // plan histograms: struts starting / ending in each slab, and a
     // difference array of (slab, tile) pairs
@@ -199,6 +211,8 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
     a.pranges[p] = a.pranges_by_id[e];
     ((T*)a.w)[p] = (T)w;
     a.ends[p] = make_int2(ia, ib);
+    const Line ln = strut_line(r);
+    a.line[p] = make_double4(ln.ux, ln.uy, ln.uz, ln.L);
 }
 
 __global__ void k_gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t* dst, size_t n) {
