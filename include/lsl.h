@@ -61,7 +61,8 @@ typedef struct lsl_lattice {
     const void* nodes;      /* [n_nodes][3] positions v_i, finite                */
     const int32_t* edges;   /* [n_edges][2] node indices (v_s, v_e), in range    */
     const void* weight;     /* [n_edges] r_j of Eq. (6), finite, >= 0;
-                               0 marks an absent strut (never binned)            */
+                               0 marks an absent strut (never binned) unless
+                               keep_zero_weight is set                          */
     double R;               /* kernel support of Eq. (5), finite, > 0            */
     double C;               /* iso-value, finite, > 0                            */
     /* Variants beyond the paper's single quartic kernel (zero-initialise for
@@ -76,6 +77,13 @@ typedef struct lsl_lattice {
                                with, shifted and cut at the same support)     */
     double sigma;           /* LSL_KERNEL_GAUSS only: width, finite, > 0, with
                                every support <= 12 sigma                       */
+    int32_t keep_zero_weight; /* 0: a strut of weight 0 is absent (not binned;
+                               slice_field_backward reports dL/dr_j = 0 for
+                               it).  1: it is binned like the others -- its
+                               terms are exact zeros, so the field is the same
+                               -- and slice_field_backward returns the true
+                               dL/dr_j = sum_p G(p) I_j(p) (Eq. 6 is linear in
+                               r_j), which gradient steps on the weights need */
 } lsl_lattice;
 
 enum { LSL_KERNEL_QUARTIC = 0, LSL_KERNEL_GAUSS = 1 };

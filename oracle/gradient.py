@@ -92,8 +92,8 @@ def field_vjp(points, G, nodes, edges, weight, R, struts=None):
     gn = np.zeros((len(nodes64), 3))
     ids = range(len(edges)) if struts is None else struts
     for i in ids:
-        if w[i] == 0.0:
-            continue
+        # a weight of 0 has the same derivative as any other: Eq. (6) is
+        # linear in r_i (its node terms carry the factor r_i = 0)
         ia, ib = int(edges[i, 0]), int(edges[i, 1])
         I, dA, dB = strut_partials(P, nodes64[ia], nodes64[ib], support_of(R, i))
         gw[i] = np.dot(G, I)
@@ -118,11 +118,15 @@ def soft_occupancy_loss(g, target, C: float, tau: float) -> float:
     return float(np.sum((s - target) ** 2))
 
 
-def slice_vjp(nodes, edges, weight, R, grid, ks, G):
+def slice_vjp(nodes, edges, weight, R, grid, ks, G, struts=None):
     """field_vjp over the pixel centres of planes ks with G [len(ks), H, W]:
     each active strut (Eq. 8) is evaluated over the window of pixels its
-    support can reach (outside it every term and partial is exactly zero)."""
+    support can reach (outside it every term and partial is exactly zero).
+    `struts` restricts the sum to a subset of ids: the weight gradient of
+    those struts is then exact, and a node's gradient is exact when every
+    strut at the node is in the subset."""
     from .slicer import active_set, strut_z_range, _pixel_window
+    keep = None if struts is None else set(int(i) for i in struts)
     nodes64 = np.asarray(nodes, dtype=np.float64)
     w = np.asarray(weight, dtype=np.float64)
     gw = np.zeros(len(edges))
@@ -133,7 +137,7 @@ def slice_vjp(nodes, edges, weight, R, grid, ks, G):
         z = float(grid.slice_z(k))
         Gk = np.asarray(G[kk], dtype=np.float64)
         for i in active_set(zlo, zhi, R, z):
-            if w[i] == 0.0:
+            if struts is not None and i not in keep:
                 continue
             ia, ib = int(edges[i, 0]), int(edges[i, 1])
             a, b = nodes64[ia], nodes64[ib]

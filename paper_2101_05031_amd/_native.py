@@ -25,7 +25,7 @@ class LslLattice(Structure):
     _fields_ = [("n_nodes", c_int64), ("n_edges", c_int64), ("dtype", c_int32),
                 ("nodes", c_void_p), ("edges", c_void_p), ("weight", c_void_p),
                 ("R", c_double), ("C", c_double), ("support", c_void_p),
-                ("kernel", c_int32), ("sigma", c_double)]
+                ("kernel", c_int32), ("sigma", c_double), ("keep_zero_weight", c_int32)]
 
 
 class LslGrid(Structure):

@@ -118,10 +118,14 @@ class Bins:
 
 def lattice_bin(nodes, edges, weight, R: float, C: float, grid, *, tile: int = 0,
                 slab: int = 0, max_pairs: int = 0, support=None, kernel: str = "quartic",
-                sigma: float | None = None, stream=None) -> Bins:
+                sigma: float | None = None, keep_zero_weight: bool = False,
+                stream=None) -> Bins:
     """Bin a lattice for slicing.  support: optional per-strut supports [E]
-    (then R is unused); kernel: "quartic" (Eq. 5) or "gauss" (width sigma)."""
+    (then R is unused); kernel: "quartic" (Eq. 5) or "gauss" (width sigma);
+    keep_zero_weight: bin struts of weight 0 as well, so that the adjoint
+    gives their weights' gradient (otherwise they are absent)."""
     L = _lattice_struct(nodes, edges, weight, R, C, support, kernel, sigma)
+    L.keep_zero_weight = 1 if keep_zero_weight else 0
     g = _grid_struct(grid)
     p = N.LslBinParams(int(tile), int(slab), int(max_pairs))
     h = c_void_p()

@@ -134,6 +134,8 @@ struct lattice_bins {
     double R = 0, C = 0;
     bool strut_R = false;              // per-strut supports (in rec[].pad)
     bool plane_ref = false;            // float32 field: every plane its own reference
+    int32_t wexp = 0;                  // float32 field: sums times 2^(5 wexp)
+    float* rho = nullptr;              // float32 field: per-strut length scale
     int32_t kernel = LSL_KERNEL_QUARTIC;
     double sigma = 0;
     lsl_grid grid{};
@@ -440,6 +442,8 @@ FieldArgs field_args(const lattice_bins* b, int32_t k0, int32_t nk, void* field)
     FieldArgs a{};
     a.rec = b->rec;
     a.line = b->line;
+    a.rho = b->rho;
+    a.wexp = b->wexp;
     a.offsets = b->offsets;
     a.ids = b->ids;
     a.n_binned = b->n_binned;
@@ -600,7 +604,8 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
     if (L->support && (s = b->alloc_t(&ks0, 3 * En))) return fail(s);
     uint32_t* cnt_lo = cnt;
     uint32_t* cnt_hi = cnt + ns;
-    uint32_t* counters = cnt + 2 * ns;   // [0] n_binned, [1] err, [2] ~smallest support
+    uint32_t* counters = cnt + 2 * ns;   // [0] n_binned, [1] err, [2] ~smallest support,
+                                         // [3] largest r R
     if ((s = fill_u32(cnt, 0u, 2 * (size_t)ns + 4, st)) ||
         (s = fill_bytes0(diff, ((size_t)ns + 1) * 8, st)))
         return fail(s);
@@ -634,10 +639,12 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
     pa.n_binned = counters;
     pa.err = counters + 1;
     pa.min_support = counters + 2;
+    pa.max_wr = counters + 3;
     pa.support = L->support;
     pa.key_s0 = ks0;
     pa.max_r_over_sigma = L->kernel == LSL_KERNEL_GAUSS ? kMaxROverSigma : 0.0;
     pa.sigma = L->sigma;
+    pa.keep_zero = L->keep_zero_weight ? 1 : 0;
     if ((s = launch_prep(L->dtype, pa, st))) return fail(s);
 
     // edge list: stable sort by the lower end's z (64-bit keys in two passes)
@@ -710,6 +717,13 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
         }
         const double dmax = 3.5 * std::sqrt(G->dx * G->dx + G->dy * G->dy);
         b->plane_ref = !(7.0 * G->dz * dmax <= 0.1 * rmin * rmin);
+        // the float32 kernel works in units of R / rho_j, rho_j = (r_j R_j)^(1/5)
+        // / 2^wexp <= 1 for every strut, and scales its sums by 2^(5 wexp)
+        const uint32_t wbits = h_cnt[2 * ns + 3];
+        float wmax = 0.0f;
+        std::memcpy(&wmax, &wbits, 4);
+        b->wexp = wmax > 0.0f ? (int32_t)std::ceil(0.2 * std::log2((double)wmax)) : 0;
+        while (b->wexp < 64 && std::pow((double)wmax, 0.2) > std::ldexp(1.0, b->wexp)) ++b->wexp;
     }
     std::vector<uint32_t> vlo(h_cnt.begin(), h_cnt.begin() + ns);
     std::vector<uint32_t> vhi(h_cnt.begin() + ns, h_cnt.begin() + 2 * ns);
@@ -722,7 +736,7 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
         (s = b->alloc_t(&b->perm, nb)) || (s = b->alloc_t(&b->ranges, nb)) ||
         (s = b->alloc_t(&b->pranges, nb)) ||
         (s = b->alloc(&b->w, nb * b->esize())) || (s = b->alloc_t(&b->ends, nb)) ||
-        (s = b->alloc_t(&b->line, nb)))
+        (s = b->alloc_t(&b->line, nb)) || (s = b->alloc_t(&b->rho, nb)))
         return fail(s);
     if (b->n_binned) {
         he = hipMemcpyAsync(b->perm, perm_src, (size_t)b->n_binned * 4, hipMemcpyDeviceToDevice, st);
@@ -748,6 +762,8 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
         ga.w = b->w;
         ga.ends = b->ends;
         ga.line = b->line;
+        ga.rho = b->rho;
+        ga.wexp = b->wexp;
         if ((s = launch_gather(L->dtype, ga, st))) return fail(s);
     }
     he = hipStreamSynchronize(st);

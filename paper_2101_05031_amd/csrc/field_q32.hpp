@@ -10,27 +10,34 @@
 // each candidate strut, every lane forms what does not depend on the plane
 // once, then adds the strut's term to each plane the strut reaches.
 //
-// Lengths are in units of the strut's support R (hats below).  For a pixel
-// p = c + d of plane k (c the block centre, d in the plane), with t measured
-// along the strut's direction u from the foot of p on the line,
+// Lengths are in units of R_j / rho_j (hats below), R_j the strut's support
+// and rho_j = (r_j R_j)^(1/5) / 2^e with one e per lattice chosen so that
+// rho_j <= 1.  In those units the strut's term r_j/R_j^4 * integral(...) is
+// the bare integral times 2^(5e): the closed form is homogeneous of degree 5
+// in length, so the weight folds into the unit, and the sums are scaled by
+// the power of two once at the end (exactly).  For a pixel p = c + d of
+// plane k (c the block centre, d in the plane), with t measured along the
+// strut's direction u from the foot of p on the line,
 //
-//   alpha = A_k - d.u / R,  beta = alpha + L / R,
-//   H     = 1 - dist(p, line)^2 / R^2
-//         = G_k + E + kappa_k * c1 * (d.u / R),
+//   alpha = (A_r - d.u^) - kappa_k dz^ u_z,  beta = (B_r - d.u^) - kappa_k dz^ u_z,
+//   H     = rho^2 (1 - dist(p, line)^2 / R^2)
+//         = G_k + E + kappa_k * c1 * (d.u^),
 //
-// where A_k = -tc_k / R, G_k = 1 - |m_k|^2 / R^2 (m_k = F_k - c, F_k the foot
-// of c on the line at plane k), E = (2 m_r.d - |d|^2) / R^2 + (d.u / R)^2 at
-// a reference plane r, kappa_k = k - r and c1 = 2 dz u_z / R: from plane r
-// to plane k the foot offset moves by (k - r) dz (u_z u - e_z), so 2 m.d
-// grows by 2 (k - r) dz u_z (d.u) while everything else in H is formed per
-// plane in float64.  The reference planes are the multiples of 8
-// (r = 8 floor(k / 8)), so a plane's value does not depend on how planes are
-// grouped into slabs.  The shift costs accuracy once 7 dz |d| is no longer
-// small against R^2 (the pieces of H grow while H stays below 1): the
-// library then uses every plane as its own reference (kappa = 0, E per
-// plane; PLANE_REF below), a choice made once per lattice and grid, so the
-// field stays the same under every tiling.  H = 1 at the axis, so the clamp
-// to [0, 1] is the max(H, 0) the square root needs.
+// where r is a reference plane and kappa_k = k - r, A_r = -tc_r^ and
+// B_r = L^ - tc_r^ (tc the position of the foot of c along the strut; each
+// rounded once from float64, so that long struts lose nothing to
+// cancellation), G_k = rho^2 - |m_k^|^2 (m_k = F_k - c, F_k the foot of c on
+// the line at plane k, formed per plane in float64), E = 2 m_r^.d^ - |d^|^2 +
+// (d.u^)^2 and c1 = 2 dz^ u_z: from plane r to plane k the foot moves by
+// (k - r) dz u_z along the strut and the foot offset by (k - r) dz (u_z u -
+// e_z), so 2 m.d grows by 2 (k - r) dz u_z (d.u).  The reference planes are the multiples of 8 (r = 8 floor(k / 8)),
+// so a plane's value does not depend on how planes are grouped into slabs.
+// The shift costs accuracy once 7 dz |d| is no longer small against R^2 (the
+// pieces of H grow while H stays small): the library then uses every plane as
+// its own reference (kappa = 0, E, A, B per plane; PLANE_REF below), a choice made
+// once per lattice and grid, so the field stays the same under every tiling.
+// H <= rho^2 <= 1, so the clamp to [0, 1] is the max(H, 0) the square root
+// needs.
 //
 // The term: with h = sqrt(H), ca, cb = alpha, beta clamped to [-h, h],
 // s = ca + cb, D = cb - ca (the clamped interval, centre s/2, half-width D/2),
@@ -39,17 +46,17 @@
 //   Q = (H - s^2/4 - D^2/12)^2 + D^2 (s^2/12 + D^2/180),
 //
 // (expand (H - (s/2 + x)^2)^2 and integrate over x in [-D/2, D/2]; every
-// piece is a square or a product of squares, so nothing cancels), times the
-// folded weight w R (r / R^4 and the R^5 of the unit change).  An interval
-// outside the support gives D = 0: an exact zero.
+// piece is a square or a product of squares, so nothing cancels).  An
+// interval outside the support gives D = 0: an exact zero.
 //
-// Sums: each plane's candidates are added in runs of four consecutive
-// candidates, g = fma(wD, Q, g), and each run is added to a compensated sum
+// Sums: each plane's candidates are added in runs of eight consecutive
+// candidates, g = fma(D, Q, g), and each run is added to a compensated sum
 // (s' = s + g, e += g - (s' - s)).  A strut is a candidate of a block and
-// plane exactly when it is one in field_block.hpp, and the strut order is
-// the bucket list's (edge-list) order, so every tile size, slab depth and
-// group split gives a pixel the same terms in the same runs: the field is
-// bitwise the same.
+// plane when its binned pixel and plane ranges cover them and the reach test
+// passes -- a function of the strut, the block and the plane alone -- and
+// the strut order is the bucket list's (edge-list) order, so every tile size,
+// slab depth and group split gives a pixel the same terms in the same runs:
+// the field is bitwise the same.
 #pragma once
 
 #include <type_traits>
@@ -59,37 +66,32 @@
 namespace lsl {
 namespace q32 {
 
-constexpr int kRun = 4;         // terms per compensated add
+constexpr int kRun = 8;         // terms per compensated add
 
-// Per-wave LDS of the staging.  pl: per plane, per staged lane, (A_k, G_k)
-// (with PLANE_REF also the plane's own 2 m_x, 2 m_y scaled); em: per
-// reference group, per staged lane, (2 m_x, 2 m_y) scaled; e0, e1: per staged
-// lane, the strut's plane-independent values; cand: the lanes of the
-// compacted candidates.
+// Per-wave LDS of the staging, indexed by the staged lane (bucket entry).
+// Shared reference planes: pg, per plane G_k; gr, per reference group
+// (A_r, B_r, 2 m_r,x^, 2 m_r,y^) with m^ = m / unit^2.  Every plane its own
+// reference: pl (A_k, B_k, G_k, -) and pm (2 m_k,x^, 2 m_k,y^) per plane.
+// e: (u_x^, u_y^, c1, 1 / unit^2); dl: -dz^ u_z; cand: the compacted
+// candidates, lane | plane mask << 8.
 template <int SZ, bool PLANE_REF>
 struct Lds;
 template <int SZ>
 struct Lds<SZ, false> {
-    float2 pl[SZ][kWave];
-    float2 em[SZ >= 16 ? 3 : (SZ >= 2 ? 2 : 1)][kWave];
-    float4 e0[kWave];           // u_x / R, u_y / R, w R, L / R
-    float4 e1[kWave];           // c1, 1 / R^2, plane mask (bits), -
+    float pg[SZ][kWave];
+    float4 gr[SZ >= 16 ? 3 : (SZ >= 2 ? 2 : 1)][kWave];
+    float4 e[kWave];
+    float dl[kWave];
     uint32_t cand[kWave];
 };
 template <int SZ>
 struct Lds<SZ, true> {
     float4 pl[SZ][kWave];
-    float4 e0[kWave];
-    float4 e1[kWave];
+    float2 pm[SZ][kWave];
+    float4 e[kWave];
+    float dl[kWave];
     uint32_t cand[kWave];
 };
-
-// Reference groups of a slab of SZ planes starting at plane kb: at most
-// three (depth 16 not aligned to 8).
-template <int SZ>
-constexpr int max_groups() {
-    return SZ >= 16 ? 3 : (SZ >= 2 ? 2 : 1);
-}
 
 // (float)k for k in 0..7, formed with integer operations so that a uniform
 // k stays in a scalar register (the float conversion is a vector operation)
@@ -117,7 +119,8 @@ __device__ __forceinline__ void comp_add(float g, float& s, float& c) {
     s = sn;
 }
 
-// PLANE_REF: every plane is its own reference (see above).
+// One wave: the 8x8 block `sub` of tile (tx, ty) over the planes of `slab`
+// in [k0, k0+nk).  PLANE_REF: every plane is its own reference (see above).
 template <int SZ, bool STATS, bool SR, bool PLANE_REF>
 __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx, int ty, int sub,
                                             Lds<SZ, PLANE_REF>& L) {
@@ -144,8 +147,8 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
     const bool pix = pi < a.W && pj < a.H;
     const double cx = a.x0 + ((double)i0 + 4.0) * a.dx;     // centre of the 8x8 centres
     const double cy = a.y0 + ((double)j0 + 4.0) * a.dy;
-    // d in grid units; the strut's values carry its 1/R (so one support given
-    // per strut is bitwise the same computation as the one support R)
+    // d in grid units; the strut's values carry its length unit (so one
+    // support given per strut is bitwise the same computation as one R)
     const double dXd = ((double)lx - 3.5) * a.dx, dYd = ((double)ly - 3.5) * a.dy;
     const float dX = (float)dXd, dY = (float)dYd;
     const float nd2 = (float)(-(dXd * dXd + dYd * dYd));
@@ -183,7 +186,10 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
         const double4 ln = a.line[valid ? p : 0u];
         const double ax = (double)r.ax, ay = (double)r.ay, az = (double)r.az;
         const double Rs = SR ? (double)r.pad : a.R;
-        const double iR = 1.0 / Rs, iR2 = iR * iR;
+        // lengths in units of R / rho (rho <= 1: the weight folded into the
+        // closed form, which scales with the fifth power of length)
+        const double rho = (double)a.rho[valid ? p : 0u];
+        const double iR = rho / Rs, iR2 = iR * iR;
         // the reach test below runs in float32 against a support widened by
         // 1e-5 relative, far above its rounding, so it never drops a strut
         // that reaches a pixel
@@ -220,7 +226,8 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
                 mxr = (float)mx;
                 myr = (float)my;
                 if constexpr (!PLANE_REF)
-                    L.em[g - gb][lane] = make_float2((float)(2.0 * mx * iR2),
+                    L.gr[g - gb][lane] = make_float4((float)(-tcr * iR), (float)((ln.w - tcr) * iR),
+                                                     (float)(2.0 * mx * iR2),
                                                      (float)(2.0 * my * iR2));
             }
             // plane ka from the reference: tc and |m|^2 (m is orthogonal to u,
@@ -242,73 +249,79 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
             const uint32_t pass = ((zmask >> k) & 1u) &
                                   ((uint32_t)(q <= 0.0f) | (uint32_t)(q * q < Rc2f * D2));
             pmask |= pass << k;
-            if constexpr (PLANE_REF)
-                L.pl[k][lane] = make_float4((float)(-tc * iR), (float)(1.0 - m2 * iR2),
-                                            (float)(2.0 * mxd * iR2), (float)(2.0 * myd * iR2));
-            else
-                L.pl[k][lane] = make_float2((float)(-tc * iR), (float)(1.0 - m2 * iR2));
+            const float G = (float)(rho * rho - m2 * iR2);
+            if constexpr (PLANE_REF) {
+                L.pl[k][lane] = make_float4((float)(-tc * iR), (float)((ln.w - tc) * iR), G, 0.0f);
+                L.pm[k][lane] = make_float2((float)(2.0 * mxd * iR2), (float)(2.0 * myd * iR2));
+            } else {
+                L.pg[k][lane] = G;
+            }
         }
-        L.e0[lane] = make_float4((float)(ln.x * iR), (float)(ln.y * iR),
-                                 (float)((double)r.wq * (Rs * Rs) * (Rs * Rs) * Rs),
-                                 (float)(ln.w * iR));
-        L.e1[lane] = make_float4((float)(2.0 * a.dz * ln.z * iR), (float)iR2,
-                                 __uint_as_float(pmask), 0.0f);
+        L.e[lane] = make_float4((float)(ln.x * iR), (float)(ln.y * iR),
+                                (float)(2.0 * a.dz * ln.z * iR), (float)iR2);
+        L.dl[lane] = (float)(-a.dz * ln.z * iR);
         const uint64_t cm = ballot64(pmask != 0u);
         if (pmask != 0u) {
             const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
                 (uint32_t)(cm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)cm, 0u));
-            L.cand[rank] = (uint32_t)lane;
+            L.cand[rank] = (uint32_t)lane | (pmask << 8);
         }
         __builtin_amdgcn_wave_barrier();
         const int n = __popcll(cm);
 
         // ------------------------------------------------------- evaluation
         // The next candidate's values are read while this one is evaluated.
-        uint32_t e = L.cand[0];
-        float4 E0 = L.e0[e], E1 = L.e1[e];
+        uint32_t c = L.cand[0];
+        float4 E = L.e[c & 63u];
+        float nD = L.dl[c & 63u];
 #pragma unroll 1
         for (int j = 0; j < n; ++j) {
-            float2 AG[SZ];
+            const uint32_t e = c & 63u;
+            const uint32_t mask = __builtin_amdgcn_readfirstlane(c >> 8);
+            float Gk[SZ];
             if constexpr (!PLANE_REF) {
                 for_planes<0, SZ>([&](auto kc) {
                     constexpr int k = decltype(kc)::value;
-                    AG[k] = L.pl[k][e];
+                    Gk[k] = L.pg[k][e];
                 });
             }
-            const uint32_t en = L.cand[j + 1 < n ? j + 1 : j];
-            const float4 E0n = L.e0[en], E1n = L.e1[en];
-            const uint32_t mask = __builtin_amdgcn_readfirstlane(__float_as_uint(E1.z));
-            const float du = __builtin_fmaf(dX, E0.x, dY * E0.y);      // d.u / R
-            const float P1 = E1.x * du;
-            const float ndd = nd2 * E1.y;                               // -|d|^2 / R^2
-            float Eg = 0.0f;
+            const uint32_t cn = L.cand[j + 1 < n ? j + 1 : j];
+            const float4 En = L.e[cn & 63u];
+            const float nDn = L.dl[cn & 63u];
+            const float du = __builtin_fmaf(dX, E.x, dY * E.y);        // d.u^
+            const float P1 = E.z * du;
+            const float ndd = nd2 * E.w;                                // -|d^|^2
+            float Eg = 0.0f, ar = 0.0f, br = 0.0f;
             int gcur = -1;
             for_planes<0, SZ>([&](auto kc) {
                 constexpr int k = decltype(kc)::value;
                 if (!((mask >> k) & 1u)) return;
-                float A_k, H;
+                float al, be, H;
                 if constexpr (PLANE_REF) {
                     const float4 P = L.pl[k][e];
-                    A_k = P.x;
+                    const float2 M = L.pm[k][e];
+                    al = P.x - du;
+                    be = P.y - du;
                     H = __builtin_amdgcn_fmed3f(
                         __builtin_fmaf(du, du,
-                                       __builtin_fmaf(P.z, dX, __builtin_fmaf(P.w, dY, ndd + P.y))),
+                                       __builtin_fmaf(M.x, dX, __builtin_fmaf(M.y, dY, ndd + P.z))),
                         0.0f, 1.0f);
                 } else {
                     const int g = ((kb + k) >> 3) - gb;
                     if (g != gcur) {
-                        const float2 M = L.em[g][e];
+                        const float4 Rg = L.gr[g][e];
+                        ar = Rg.x - du;
+                        br = Rg.y - du;
                         Eg = __builtin_fmaf(du, du,
-                                            __builtin_fmaf(M.x, dX, __builtin_fmaf(M.y, dY, ndd)));
+                                            __builtin_fmaf(Rg.z, dX, __builtin_fmaf(Rg.w, dY, ndd)));
                         gcur = g;
                     }
-                    A_k = AG[k].x;
-                    H = __builtin_amdgcn_fmed3f(
-                        __builtin_fmaf(kappa((kb + k) & 7), P1, AG[k].y + Eg), 0.0f, 1.0f);
+                    const float kap = kappa((kb + k) & 7);
+                    al = __builtin_fmaf(kap, nD, ar);
+                    be = __builtin_fmaf(kap, nD, br);
+                    H = __builtin_amdgcn_fmed3f(__builtin_fmaf(kap, P1, Gk[k] + Eg), 0.0f, 1.0f);
                 }
                 const float h = __builtin_amdgcn_sqrtf(H);
-                const float al = A_k - du;
-                const float be = al + E0.w;
                 const float ca = __builtin_amdgcn_fmed3f(al, -h, h);
                 const float cb = __builtin_amdgcn_fmed3f(be, -h, h);
                 const float s = ca + cb, D = cb - ca;
@@ -316,21 +329,20 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
                 const float A = __builtin_fmaf(D2, -1.0f / 12.0f, __builtin_fmaf(s2, -0.25f, H));
                 const float V = __builtin_fmaf(s2, 1.0f / 12.0f, D2 * (1.0f / 180.0f));
                 const float Q = __builtin_fmaf(A, A, D2 * V);
-                const float wD = E0.z * D;
                 if (STATS) {
                     n_cand += pix ? 1ull : 0ull;
-                    n_useful += (pix && wD * Q > 0.0f) ? 1ull : 0ull;
+                    n_useful += (pix && D * Q > 0.0f) ? 1ull : 0ull;
                 }
-                run[k] = __builtin_fmaf(wD, Q, run[k]);
+                run[k] = __builtin_fmaf(D, Q, run[k]);
                 if (++open[k] == kRun) {
                     comp_add(run[k], acc_s[k], acc_c[k]);
                     run[k] = 0.0f;
                     open[k] = 0;
                 }
             });
-            e = en;
-            E0 = E0n;
-            E1 = E1n;
+            c = cn;
+            E = En;
+            nD = nDn;
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -360,7 +372,7 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
             constexpr int k = decltype(kc)::value;
             if (k < nvalid)
                 out[((size_t)(kb + k - a.k0) * (size_t)a.H + (size_t)pj) * (size_t)a.W + (size_t)pi] =
-                    acc_s[k] + acc_c[k];
+                    __builtin_ldexpf(acc_s[k] + acc_c[k], 5 * a.wexp);
         });
     }
     if (a.bits_blk) {
@@ -369,7 +381,8 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
         for_planes<0, SZ>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
             if (k < nvalid) {
-                const uint64_t m = ballot64(pix && acc_s[k] + acc_c[k] >= C);
+                const uint64_t m =
+                    ballot64(pix && __builtin_ldexpf(acc_s[k] + acc_c[k], 5 * a.wexp) >= C);
                 if (lane == 0)
                     a.bits_blk[((size_t)(kb + k - a.k0) * nby + (size_t)(j0 >> 3)) * nbx +
                                (size_t)(i0 >> 3)] = m;

@@ -28,11 +28,13 @@ struct PrepArgs {
     uint32_t* n_binned;
     uint32_t* err;                    // bit 0 index, 1 weight, 2 node, 3 support, 4 sigma
     uint32_t* min_support;            // ~(float bits) of the smallest binned support, max-reduced
+    uint32_t* max_wr;                 // float bits of the largest r R of a binned strut, max-reduced
     // variants
     const void* support;              // [n_edges] per-strut supports, or null (R for all)
     uint32_t* key_s0;                 // [n_edges] first slab (n_slabs if not binned), or null
     double max_r_over_sigma;          // > 0: reject supports above this many sigma
     double sigma;
+    int32_t keep_zero;                // 1: bin struts of weight 0 too
 };
 lsl_status launch_prep(int dtype, const PrepArgs& a, hipStream_t st);
 
@@ -54,6 +56,8 @@ struct GatherArgs {
     void* w;                          // T [n_binned]
     int2* ends;                       // [n_binned]
     double4* line;                    // [n_binned] (u_x, u_y, u_z, L) of each strut, float64
+    float* rho;                       // [n_binned] (r R)^(1/5) / 2^wexp (float32 field kernel)
+    int32_t wexp;
 };
 lsl_status launch_gather(int dtype, const GatherArgs& a, hipStream_t st);
 lsl_status launch_gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t* dst,
@@ -106,6 +110,8 @@ lsl_status group_emi(const EmiArgs& a, hipStream_t st);
 struct FieldArgs {
     const void* rec;
     const double4* line;              // [n_binned] direction and length of rec[] (float64)
+    const float* rho;                 // [n_binned] length scale of rec[] (float32 kernel)
+    int32_t wexp;                     // the float32 kernel's sums times 2^(5 wexp) are the field
     const uint32_t* offsets;
     const uint32_t* ids;
     uint32_t n_binned, n_pairs;       // bounds of rec[] and ids[]

@@ -69,6 +69,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
     uint32_t klo = 0xffffffffu, khi = 0xffffffffu;
     unsigned long long ntile = 0;
     float rs_binned = 0.0f;             // the support of a binned strut
+    float wr_binned = 0.0f;             // and its weight times its support
     if (live) {
         const int32_t ia = a.edges[2 * e], ib = a.edges[2 * e + 1];
         const T* nd = (const T*)a.nodes;
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
             if (!isfinite(ax) || !isfinite(ay) || !isfinite(az) || !isfinite(bx) ||
                 !isfinite(by) || !isfinite(bz)) {
                 atomicOr(a.err, 4u);
-            } else if (w != T(0) && !(ax == bx && ay == by && az == bz)) {
+            } else if ((w != T(0) || a.keep_zero) && !(ax == bx && ay == by && az == bz)) {
                 const AxisRange rz = axis_range(fmin(az, bz) - Rs, fmax(az, bz) + Rs, a.z0,
                                                 a.inv_dz, a.S);
                 const AxisRange rx = axis_range(fmin(ax, bx) - Rs, fmax(ax, bx) + Rs, a.x0,
@@ -112,6 +113,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
                 if (rz.ok && rx.ok && ry.ok) {
                     binned = true;
                     rs_binned = (float)Rs;
+                    wr_binned = (float)((double)w * Rs);
                     pr.i0 = (uint16_t)rx.i0;
                     pr.i1 = (uint16_t)rx.i1;
                     pr.j0 = (uint16_t)ry.i0;
@@ -154,6 +156,15 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
             inv = inv > o ? inv : o;
         }
         if ((threadIdx.x & (kWave - 1)) == 0 && inv != 0u) atomicMax(a.min_support, inv);
+    }
+    // the largest r R of a binned strut (the float32 field kernel's scale)
+    if (a.max_wr) {
+        uint32_t v = binned ? __float_as_uint(wr_binned) : 0u;
+        for (int d = 32; d >= 1; d >>= 1) {
+            const uint32_t o = (uint32_t)__shfl_xor((int)v, d, kWave);
+            v = v > o ? v : o;
+        }
+        if ((threadIdx.x & (kWave - 1)) == 0 && v != 0u) atomicMax(a.max_wr, v);
     }
     // plan histograms: struts starting / ending in each slab, and a
     // difference array of (slab, tile) pairs
@@ -213,6 +224,9 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
     a.ends[p] = make_int2(ia, ib);
     const Line ln = strut_line(r);
     a.line[p] = make_double4(ln.ux, ln.uy, ln.uz, ln.L);
+    // lengths of the float32 field kernel are in units of R / rho, which
+    // folds the weight into the closed form's degree-5 scaling
+    a.rho[p] = (float)(pow(w * Rs, 0.2) * ldexp(1.0, -a.wexp));
 }
 
 __global__ void k_gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t* dst, size_t n) {

@@ -53,8 +53,9 @@ def match_density(nodes, edges, weight, R: float, C: float, grid, target, vx: in
     history = []
 
     def evaluate(w, want_grad):
+        # struts at weight 0 stay binned: their gradient can move them back up
         bins = api.lattice_bin(nodes, edges, w, R, C, grid, tile=tile, slab=slab,
-                               support=support, stream=stream)
+                               support=support, keep_zero_weight=True, stream=stream)
         field = api.slice_field(bins, k0, nk, stream=stream)
         loss, _, gfield = api.slice_density_loss(bins, field, target, tau, vx, vy, vz,
                                                  want_grad=want_grad, stream=stream)

@@ -87,7 +87,12 @@ def test_backward_absent_struts_get_zero():
 
 def test_autograd_soft_occupancy_loss():
     """The differentiable slice loss through torch.autograd matches the
-    oracle's gradient of the same loss."""
+    oracle's gradient of the same loss.  The adjoint itself is held to 1e-4:
+    against the oracle's VJP of the loss gradient at the GPU's own field.  End
+    to end (the oracle's field and loss gradient) the sigmoid of width tau
+    turns the field's float32 rounding (~1e-6 C) into a relative change of
+    dL/dg of up to ~1e-6 C / tau^2 around the iso-surface, so the weights'
+    and nodes' gradients are held to 1e-3 there."""
     lat, grid = small_case()
     tau = 0.05
     ks = range(2, 10)
@@ -98,58 +103,136 @@ def test_autograd_soft_occupancy_loss():
     f = sf_fn(n, w, e, lat.R, lat.C, grid, ks.start, len(ks))
     loss = soft_occupancy_loss(f, torch.from_numpy(target).cuda(), lat.C, tau)
     loss.backward()
+    # the adjoint, at the GPU's field
+    G_own = OG.soft_occupancy_grad(f.detach().cpu().numpy().astype(np.float64), target,
+                                   lat.C, tau)
+    ow, on = OG.slice_vjp(lat.nodes, lat.edges, lat.weight, lat.R, grid, ks, G_own)
+    grad_close(w.grad.cpu().numpy(), ow, 1e-4, "autograd dL/dr at the GPU field")
+    grad_close(n.grad.cpu().numpy(), on, 1e-4, "autograd dL/dv at the GPU field")
+    # end to end
     g_ref = np.stack([OS.slice_field(lat.nodes, lat.edges, lat.weight, lat.R, grid, k) for k in ks])
     G = OG.soft_occupancy_grad(g_ref, target, lat.C, tau)
-    assert float(loss) == pytest.approx(OG.soft_occupancy_loss(g_ref, target, lat.C, tau),
+    assert float(loss.detach()) == pytest.approx(OG.soft_occupancy_loss(g_ref, target, lat.C, tau),
                                         rel=1e-4)
     rw, rn = OG.slice_vjp(lat.nodes, lat.edges, lat.weight, lat.R, grid, ks, G)
     grad_close(w.grad.cpu().numpy(), rw, 1e-3, "autograd dL/dr")
     grad_close(n.grad.cpu().numpy(), rn, 1e-3, "autograd dL/dv")
 
 
-def _local_loss_change(lat, grid, ks, target, tau, param, h, shift_nodes=None):
+def test_zero_weight_struts_keep_their_gradient():
+    """With keep_zero_weight (what the autograd Function and the density
+    matching use), struts of weight 0 are binned, the field is unchanged, and
+    dL/dr for them is the oracle's sum of G I (Eq. 6 is linear in r)."""
+    lat, grid = small_case()
+    lat.weight = lat.weight.copy()
+    lat.weight[::7] = 0
+    ks = range(3, 7)
+    G = np.random.default_rng(23).normal(size=(len(ks), grid.H, grid.W)).astype(np.float32)
+    b0 = bin_lattice(lat, grid)
+    b1 = bin_lattice(lat, grid, keep_zero_weight=True)
+    assert b1.info()["n_binned"] > b0.info()["n_binned"]
+    f0 = api.slice_field(b0, ks.start, len(ks)).cpu().numpy()
+    f1 = api.slice_field(b1, ks.start, len(ks)).cpu().numpy()
+    assert np.abs(f1 - f0).max() <= 1e-5 * max(float(np.abs(f0).max()), lat.C)
+    gw, gn = api.slice_field_backward(b1, ks.start, len(ks), torch.from_numpy(G).cuda())
+    rw, rn = OG.slice_vjp(lat.nodes, lat.edges, lat.weight, lat.R, grid, ks, G)
+    assert np.abs(rw[::7]).max() > 0
+    grad_close(gw.cpu().numpy(), rw, 1e-4, "dL/dr with zero weights kept")
+    grad_close(gn.cpu().numpy(), rn, 1e-4, "dL/dv with zero weights kept")
+
+
+def test_m1_adjoint_sampled():
+    """The benchmark's lattice (Kuhn 52^3, 1,008,748 struts, 2048^2) in its
+    launch configuration (tile 32, slab 8): the adjoint over a 16-plane window
+    with random dL/dg, for 200 sampled struts' dL/dr and 12 sampled nodes'
+    dL/dv against the oracle's VJP restricted to those struts."""
+    lat, grid = synth.config("M1")
+    k0, nk = 496, 16
+    ks = range(k0, k0 + nk)
+    print(f"M1 adjoint: E={lat.n_edges}, planes {k0}..{k0 + nk - 1}", flush=True)
+    G = np.random.default_rng(29).normal(size=(nk, grid.H, grid.W)).astype(np.float32)
+    b = bin_lattice(lat, grid, tile=32, slab=8)
+    gw, gn = api.slice_field_backward(b, k0, nk, torch.from_numpy(G).cuda())
+    gw = gw.cpu().numpy()
+    gn = gn.cpu().numpy()
+    zlo, zhi = OS.strut_z_range(lat.nodes, lat.edges)
+    z0, z1 = grid.slice_z(k0), grid.slice_z(k0 + nk - 1)
+    live = np.nonzero((zlo - lat.R <= z1) & (zhi + lat.R >= z0))[0]
+    rng = np.random.default_rng(31)
+    sw = np.sort(rng.choice(live, size=200, replace=False))
+    # nodes whose every strut lies in the window's active set
+    zn = lat.nodes[:, 2].astype(np.float64)
+    mid = np.nonzero(np.abs(zn - 0.5 * (z0 + z1)) < 0.2)[0]
+    sn = np.sort(rng.choice(mid, size=12, replace=False))
+    inc = np.nonzero(np.isin(lat.edges[:, 0], sn) | np.isin(lat.edges[:, 1], sn))[0]
+    print(f"M1 adjoint: oracle over {len(sw)} + {len(inc)} struts", flush=True)
+    rw, _ = OG.slice_vjp(lat.nodes, lat.edges, lat.weight, lat.R, grid, ks, G, struts=sw)
+    _, rn = OG.slice_vjp(lat.nodes, lat.edges, lat.weight, lat.R, grid, ks, G, struts=inc)
+    per, norm = grad_close(gw[sw], rw[sw], 1e-4, "M1 dL/dr")
+    print(f"M1 dL/dr: per-parameter {per:.2e}, normwise {norm:.2e}", flush=True)
+    per, norm = grad_close(gn[sn], rn[sn], 1e-4, "M1 dL/dv")
+    print(f"M1 dL/dv: per-parameter {per:.2e}, normwise {norm:.2e}", flush=True)
+
+
+def _local_loss_change(lat, grid, ks, target, tau, param, h):
     """Oracle, float64: L(theta + h) - L(theta - h) for one parameter, summed
     over the pixels the perturbed struts can reach (elsewhere the field, and
     so each pixel's loss term, does not change).  param = ('w', i) or
-    ('v', node, axis)."""
+    ('v', node, axis).  The field of the other struts is formed once per
+    plane, each strut over the pixels its box covers."""
     nodes = lat.nodes.astype(np.float64)
     w = lat.weight.astype(np.float64)
+    R = lat.R
     if param[0] == "w":
         touched = np.array([param[1]])
     else:
         touched = np.nonzero((lat.edges[:, 0] == param[1]) | (lat.edges[:, 1] == param[1]))[0]
-    R = lat.R
     zlo, zhi = OS.strut_z_range(nodes, lat.edges)
+    tz0 = zlo[touched].min() - R - 2 * h
+    tz1 = zhi[touched].max() + R + 2 * h
+    ends = nodes[lat.edges[touched].ravel(), :2]
+    lo = ends.min(0) - R - 2 * h
+    hi = ends.max(0) + R + 2 * h
+    ix0 = max(int(np.floor((lo[0] - grid.x0) / grid.dx - 0.5)) - 1, 0)
+    ix1 = min(int(np.ceil((hi[0] - grid.x0) / grid.dx - 0.5)) + 1, grid.W - 1)
+    iy0 = max(int(np.floor((lo[1] - grid.y0) / grid.dy - 0.5)) - 1, 0)
+    iy1 = min(int(np.ceil((hi[1] - grid.y0) / grid.dy - 0.5)) + 1, grid.H - 1)
+    if ix0 > ix1 or iy0 > iy1:
+        return 0.0
+    X, Y = np.meshgrid(grid.pixel_x()[ix0:ix1 + 1], grid.pixel_y()[iy0:iy1 + 1], indexing="xy")
     total = 0.0
-    tz0 = min(zlo[i] for i in touched) - R - 2 * h
-    tz1 = max(zhi[i] for i in touched) + R + 2 * h
     for kk, k in enumerate(ks):
         z = float(grid.slice_z(k))
         if not (tz0 <= z <= tz1):
             continue                   # no perturbed strut reaches this plane
-        # pixels the touched struts can reach at either perturbed position
-        lo = np.full(2, np.inf)
-        hi = np.full(2, -np.inf)
-        for i in touched:
-            for v in lat.edges[i]:
-                lo = np.minimum(lo, nodes[v, :2] - R - 2 * h)
-                hi = np.maximum(hi, nodes[v, :2] + R + 2 * h)
-        ix0 = max(int(np.floor((lo[0] - grid.x0) / grid.dx - 0.5)) - 1, 0)
-        ix1 = min(int(np.ceil((hi[0] - grid.x0) / grid.dx - 0.5)) + 1, grid.W - 1)
-        iy0 = max(int(np.floor((lo[1] - grid.y0) / grid.dy - 0.5)) - 1, 0)
-        iy1 = min(int(np.ceil((hi[1] - grid.y0) / grid.dy - 0.5)) + 1, grid.H - 1)
-        if ix0 > ix1 or iy0 > iy1:
-            continue
-        X, Y = np.meshgrid(grid.pixel_x()[ix0:ix1 + 1], grid.pixel_y()[iy0:iy1 + 1], indexing="xy")
         P = np.stack([X, Y, np.full_like(X, z)], -1).reshape(-1, 3)
-        # struts that can reach these pixels
+        # pixels within reach of a perturbed strut
+        near_px = np.zeros(len(P), bool)
+        for i in touched:
+            a, b = nodes[lat.edges[i, 0]], nodes[lat.edges[i, 1]]
+            d = b - a
+            t = np.clip(((P - a) @ d) / (d @ d), 0.0, 1.0)
+            q = P - (a + t[:, None] * d)
+            near_px |= np.einsum("ij,ij->i", q, q) < (R + 2 * h) ** 2
+        if not near_px.any():
+            continue
+        P = P[near_px]
+        tg = target[kk, iy0:iy1 + 1, ix0:ix1 + 1].reshape(-1)[near_px].astype(np.float64)
+        # the other struts that can reach these pixels, summed once
         act = OS.active_set(zlo - 2 * h, zhi + 2 * h, R, z)
-        a = nodes[lat.edges[act, 0]]
-        b = nodes[lat.edges[act, 1]]
-        near = ((np.minimum(a[:, 0], b[:, 0]) - R <= hi[0]) & (np.maximum(a[:, 0], b[:, 0]) + R >= lo[0]) &
-                (np.minimum(a[:, 1], b[:, 1]) - R <= hi[1]) & (np.maximum(a[:, 1], b[:, 1]) + R >= lo[1]))
-        act = act[near]
-        tg = target[kk, iy0:iy1 + 1, ix0:ix1 + 1].reshape(-1).astype(np.float64)
+        A = nodes[lat.edges[act, 0]]
+        B = nodes[lat.edges[act, 1]]
+        pl, ph = P[:, :2].min(0), P[:, :2].max(0)
+        near = ((np.minimum(A[:, 0], B[:, 0]) - R <= ph[0]) & (np.maximum(A[:, 0], B[:, 0]) + R >= pl[0]) &
+                (np.minimum(A[:, 1], B[:, 1]) - R <= ph[1]) & (np.maximum(A[:, 1], B[:, 1]) + R >= pl[1]))
+        base = np.setdiff1d(act[near], touched)
+        g0 = np.zeros(len(P))
+        for i in base:
+            a, b = nodes[lat.edges[i, 0]], nodes[lat.edges[i, 1]]
+            sel = ((P[:, 0] >= min(a[0], b[0]) - R) & (P[:, 0] <= max(a[0], b[0]) + R) &
+                   (P[:, 1] >= min(a[1], b[1]) - R) & (P[:, 1] <= max(a[1], b[1]) + R))
+            if sel.any():
+                g0[sel] += w[i] * OF.strut_integral(P[sel], a, b, R)
         vals = []
         for sgn in (+1.0, -1.0):
             nd = nodes.copy()
@@ -158,8 +241,9 @@ def _local_loss_change(lat, grid, ks, target, tau, param, h, shift_nodes=None):
                 ww[param[1]] += sgn * h
             else:
                 nd[param[1], param[2]] += sgn * h
-            g = OF.field_at(P, nd, lat.edges, ww, R, struts=act)
-            vals.append(OG.soft_occupancy_loss(g, tg, lat.C, tau))
+            I = OF.strut_integral(P[:, None, :], nd[lat.edges[touched, 0]][None],
+                                  nd[lat.edges[touched, 1]][None], R)
+            vals.append(OG.soft_occupancy_loss(g0 + I @ ww[touched], tg, lat.C, tau))
         total += vals[0] - vals[1]
     return total
 
@@ -205,6 +289,7 @@ def test_d4_gradients_vs_finite_differences():
     got = np.array(got)
     ref = np.array(ref)
     per = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
-    print(f"D4 FD: worst per-parameter {per.max():.2e}, median {np.median(per):.2e}", flush=True)
-    assert np.median(per) < 1e-4
-    assert per.max() < 2e-3
+    norm = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"D4 FD: worst per-parameter {per.max():.2e}, median {np.median(per):.2e}, "
+          f"normwise {norm:.2e}", flush=True)
+    assert per.max() <= 1e-4 and norm <= 1e-4
