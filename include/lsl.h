@@ -336,6 +336,21 @@ lsl_status slice_occupancy_loss(const lattice_bins* bins, int32_t nk, const void
                                 double* loss, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * slice_occupancy_loss_static -- slice_occupancy_loss for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same arguments, kernels and results,
+ * with the per-block partial sums in a static device array of the library
+ * (8192 doubles, 64 KB per GPU, held until the process ends) instead of the
+ * handle's growable scratch.  Allocates nothing and never synchronises.
+ * Calls that overlap on one GPU share the array and race.  LSL_ECAPACITY if
+ * a call would need more partial sums than the array holds (the loss uses at
+ * most 8192 blocks, so none does); otherwise as slice_occupancy_loss.
+ * ------------------------------------------------------------------------- */
+lsl_status slice_occupancy_loss_static(const lattice_bins* bins, int32_t nk, const void* field,
+                                       const void* target, double tau, void* grad_field,
+                                       double* loss, void* stream);
+
+/* ---------------------------------------------------------------------------
  * slice_field_backward -- gradient of a loss of the sliced field.
  *
  * Given grad_field = dL/dg at the pixels of planes k0 .. k0+nk-1

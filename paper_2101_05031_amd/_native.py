@@ -80,6 +80,8 @@ SIGNATURES = {
                                      c_void_p]),
     "slice_occupancy_loss": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_double,
                                        c_void_p, c_void_p, c_void_p]),
+    "slice_occupancy_loss_static": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_double,
+                                              c_void_p, c_void_p, c_void_p]),
     "slice_field_backward": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p,
                                        c_void_p, c_int32, c_void_p]),
     "slice_batch": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p,

@@ -112,6 +112,38 @@ class DeviceCache {
     bool enabled_ = true;
 };
 
+// ---------------------------------------------------------------------------
+// Static device scratch for slice_occupancy_loss_static, the entry point
+// that allocates nothing: the per-block partial sums of the loss (at most
+// occupancy_blocks(n) <= 8192 doubles, 64 KB) live in this file-scope array,
+// one copy per GPU for the life of the process.  In host code `scratch`
+// names a host-side stand-in, so kernels get the device address that
+// hipGetSymbolAddress returns, taken once per device on its first use.
+// Calls that overlap on one GPU share the array and race.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticScratchElems = 8192;
+static __device__ __align__(256) double scratch[kStaticScratchElems];
+
+lsl_status static_scratch(double** out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double* addr[kMaxDevices] = {};
+    int dev = 0;
+    LSL_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("static scratch: device index out of range");
+        return LSL_EINTERNAL;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        LSL_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        addr[dev] = (double*)p;
+    }
+    *out = addr[dev];
+    return LSL_OK;
+}
+
 }  // namespace lsl
 
 using namespace lsl;
@@ -1112,6 +1144,28 @@ lsl_status slice_occupancy_loss(const lattice_bins* cb, int32_t nk, const void* 
     LSL_TRY(b->grow(&b->dscratch, &b->dscratch_elems, need, st, false));
     return launch_occupancy_loss(b->dtype, field, target, n, b->C, tau, grad_field, loss,
                                  b->dscratch, st);
+}
+
+lsl_status slice_occupancy_loss_static(const lattice_bins* cb, int32_t nk, const void* field,
+                                       const void* target, double tau, void* grad_field,
+                                       double* loss, void* stream) {
+    set_error("");
+    LSL_CHECK(cb != nullptr, "bins handle is NULL");
+    LSL_CHECK(nk >= 1, "nk must be >= 1");
+    LSL_CHECK(field != nullptr && target != nullptr, "field and target are required");
+    LSL_CHECK(std::isfinite(tau) && tau > 0.0, "tau must be finite and > 0");
+    const size_t n = (size_t)nk * (size_t)cb->grid.W * (size_t)cb->grid.H;
+    const size_t need = occupancy_blocks(n);
+    if (need > kStaticScratchElems) {
+        set_error("slice_occupancy_loss_static: " + std::to_string(need) +
+                  " partial sums exceed the static scratch of " +
+                  std::to_string(kStaticScratchElems));
+        return LSL_ECAPACITY;
+    }
+    double* part = nullptr;
+    LSL_TRY(static_scratch(&part));
+    return launch_occupancy_loss(cb->dtype, field, target, n, cb->C, tau, grad_field, loss,
+                                 part, S(stream));
 }
 
 lsl_status slice_density_loss(const lattice_bins* cb, int32_t nk, const void* field, int32_t vx,
