@@ -166,6 +166,7 @@ struct lattice_bins {
     double R = 0, C = 0;
     bool strut_R = false;              // per-strut supports (in rec[].pad)
     bool plane_ref = false;            // float32 field: every plane its own reference
+    bool wide = false;                 // float32 adjoint: 16x16-pixel regions
     int32_t wexp = 0;                  // float32 field: sums times 2^(5 wexp)
     float* rho = nullptr;              // float32 field: per-strut length scale
     int32_t kernel = LSL_KERNEL_QUARTIC;
@@ -749,6 +750,11 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
         }
         const double dmax = 3.5 * std::sqrt(G->dx * G->dx + G->dy * G->dy);
         b->plane_ref = !(7.0 * G->dz * dmax <= 0.1 * rmin * rmin);
+        // the float32 adjoint measures pixel offsets from the centre of a
+        // 16x16 region when the farthest one, 7.5 |(dx, dy)|, stays within
+        // the smallest support (the rounding of H grows with |d| / R), else
+        // from the centre of each 8x8 block
+        b->wide = 7.5 * std::sqrt(G->dx * G->dx + G->dy * G->dy) <= rmin;
         // the float32 kernel works in units of R / rho_j, rho_j = (r_j R_j)^(1/5)
         // / 2^wexp <= 1 for every strut, and scales its sums by 2^(5 wexp)
         const uint32_t wbits = h_cnt[2 * ns + 3];
@@ -1246,6 +1252,9 @@ BackArgs back_args(const lattice_bins* b, int g, int32_t k0, int32_t nk, int s_l
     a.emi = b->emi;
     a.grad = grad;
     a.partial = b->partial;
+    a.line = b->line;
+    a.plane_ref = b->plane_ref ? 1 : 0;
+    a.wide = b->wide ? 1 : 0;
     return a;
 }
 
@@ -1392,6 +1401,7 @@ lsl_status slice_field_backward(lattice_bins* b, int32_t k0, int32_t nk, const v
             r.w = b->w;
             r.R = b->R;
             r.strut_R = b->strut_R ? 1 : 0;
+            r.normalized = b->dtype == LSL_F32 ? 1 : 0;
             r.acc = b->acc;
             return launch_reduce(b->dtype, r, b->ranges, G.sa, s_lo, s_hi, (uint32_t)G.pairs,
                                  b->n_binned, st);

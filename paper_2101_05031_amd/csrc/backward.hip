@@ -44,6 +44,7 @@
 // per-strut sums then run over each strut's pairs in emission order
 // (slab, tile), and the nodes gather their struts' gradients through a node
 // -> strut incidence list.  Every reduction has a fixed order.
+#include "field_q32.hpp"
 #include "kernels.hpp"
 
 namespace lsl {
@@ -393,6 +394,442 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
     }
 }
 
+// ---------------------------------------------------------------------------
+// float32 path
+// ---------------------------------------------------------------------------
+// One wave takes one (tile, slab) bucket, as above, but walks the tile in
+// regions of 2x2 8x8 sub-blocks (16x16 pixels, one pixel of each sub-block
+// per lane) -- or of one 8x8 block when the pixels are coarse against the
+// smallest support (see below) -- and the slab in windows of at most 8
+// planes.  For 64 bucket entries at a time (one per lane), each region and
+// each window:
+//
+//  * staging, per entry: the strut's line around the region centre c
+//    (float64), its values per plane, and the reach test of the field kernel
+//    for every (sub-block, plane), in float32 against the support widened by
+//    1e-5 relative (so that no strut that reaches a pixel is dropped; one
+//    that does not adds exact zeros);
+//  * evaluation, per entry that reaches the region: every lane adds its
+//    pixels' terms over the (sub-block, plane) pairs the strut reaches, and
+//    the wave sums the nine pixel sums once per (strut, region).
+//
+// Lengths are in units of the strut's support R (hats): H^ = 1 - |q_perp|^2
+// / R^2 <= 1, the ends alpha^ = A_k - d.u^ and beta^ = B_k - d.u^ (A_k =
+// -tc_k / R, B_k = (L - tc_k) / R).  As in the field kernel, a reference
+// plane r carries the strut's values and from plane r to plane k the foot
+// moves by (k - r) dz u_z along the strut:  A_k = A_r - (k - r) dz^ u_z and
+// H^_k = G_k + E + (k - r) c1 (d.u^), with G_k = 1 - |m_k|^2 / R^2 (per
+// plane, from float64), E = 2 m_r^.d^ - |d^|^2 + (d.u^)^2 and c1 = 2 dz^ u_z.
+// Here r is the middle of the planes of the window that the strut reaches,
+// so the shifts stay small and m_r is of the size of R.  For a coarse plane
+// pitch (the field kernel's rule) every plane carries its own A_k, B_k and
+// m_k instead.  With s = ca + cb and D = cb - ca of the clamped ends, A' =
+// H^ - s^2/4 - D^2/12:
+//
+//   I / R        = D Q,            Q = A'^2 + D^2 (s^2/12 + D^2/180)
+//   phi(alpha)   = (H^ - ca^2)^2,  phi(beta) = (H^ - cb^2)^2
+//   J R          = 2 D A'          (the H-derivative of the integral; the
+//                                   clamped ends add nothing, the integrand
+//                                   vanishes there)
+//   K            = phi(beta) - phi(alpha) + 4 alpha^ D A'
+//
+// (K and phi are dimensionless; the loop keeps 16 D Q and 4 D A', whose
+// powers of two are taken out before the wave sums.)  The q_perp weights
+// follow from q_perp = m_k - d + (d.u) u with m_k = m_r + (k - r) dm: each
+// lane keeps, per (strut, region), sum G K, sum (k - r) G K, and the sums
+// of G K over each sub-block times the pixel's d_x, d_y and d.u (likewise
+// for J), and forms its three components once before the wave sums.  The
+// partials are then (sum G I / R, sum G phi(alpha), sum G phi(beta), sum G K
+// q_perp, sum G J R q_perp): k_reduce scales them by R.
+//
+// The rounding of H^ grows with |d| / R (its pieces 2 m^.d^ and |d^|^2 grow
+// while H^ <= 1), so the 16x16 regions are used only while their farthest
+// pixel, 7.5 |(dx, dy)| from the centre, stays within the smallest support;
+// otherwise d is measured from each 8x8 block's centre, as in the field
+// kernel.
+namespace b32 {
+
+template <int SZ, bool PR>
+struct Lds;
+template <int SZ>
+struct Lds<SZ, false> {
+    float pg[SZ][kWave];         // per plane: G_k
+    float4 gr[kWave];            // A_0, B_0, 2 m_0,x / R^2, 2 m_0,y / R^2
+    float4 e[kWave];             // u_x / R, u_y / R, c1, 1 / R^2
+    float dl[kWave];             // -dz u_z / R
+    float4 m0[kWave];            // m_0 (x, y, z), R
+    float4 u4[kWave];            // u (x, y, z), dz u_z
+    float rk[kWave];             // the reference plane r (window index)
+    uint32_t mask[kWave];        // reach bits: sub-block s, plane k at bit s SZ + k
+    uint32_t cand[kWave];
+    float slot[kWave][kParts];
+};
+template <int SZ>
+struct Lds<SZ, true> {
+    float4 pl[SZ][kWave];        // per plane: A_k, B_k, G_k, 2 m_k,x / R^2
+    float pmy[SZ][kWave];        // per plane: 2 m_k,y / R^2
+    float4 e[kWave];
+    float4 m0[kWave];
+    float4 u4[kWave];
+    float rk[kWave];
+    uint32_t mask[kWave];
+    uint32_t cand[kWave];
+    float slot[kWave][kParts];
+};
+
+template <int SZ, bool SR, bool PR, int NS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_backward32(
+    BackArgs a, uint32_t n_items) {
+    constexpr int kSub = NS * NS;             // 8x8 sub-blocks of a region
+    constexpr int kEdge = 8 * NS;             // region edge in pixels
+    __shared__ Lds<SZ, PR> L;
+    const int lane = lane_id();
+    const uint32_t item = xcd_remap(blockIdx.x, gridDim.x);
+    if (item >= n_items) return;
+    uint32_t t = item;
+    const int tx = (int)(t % (uint32_t)a.ntx);
+    t /= (uint32_t)a.ntx;
+    const int ty = (int)(t % (uint32_t)a.nty);
+    t /= (uint32_t)a.nty;
+    const int slab = a.s_lo + (int)t;
+    int kb = slab * a.slab, ke = kb + a.slab;
+    if (kb < a.k0) kb = a.k0;
+    if (ke > a.k0 + a.nk) ke = a.k0 + a.nk;
+    const uint32_t bucket = ((uint32_t)(slab - a.group_s0) * (uint32_t)a.nty + (uint32_t)ty) *
+                                (uint32_t)a.ntx + (uint32_t)tx;
+    uint32_t beg = a.offsets[bucket], end = a.offsets[bucket + 1];
+    if (end > a.n_pairs) end = a.n_pairs;
+    if (beg >= end) return;
+
+    const int lx = lane & 7, ly = lane >> 3;
+    // the lane's pixel of sub-block s = sx + NS sy lies at d = ((8 sx + lx +
+    // 1/2 - kEdge/2) dx, (8 sy + ly + 1/2 - kEdge/2) dy) from the region centre
+    const double dxa = ((double)lx + 0.5 - 0.5 * kEdge) * a.dx, dxb = dxa + 8.0 * a.dx;
+    const double dya = ((double)ly + 0.5 - 0.5 * kEdge) * a.dy, dyb = dya + 8.0 * a.dy;
+    const float Dx[2] = {(float)dxa, (float)dxb};
+    const float Dy[2] = {(float)dya, (float)dyb};
+    float nd2[kSub];
+    for (int s = 0; s < kSub; ++s) {
+        const double ex = (s % NS) ? dxb : dxa, ey = (s / NS) ? dyb : dya;
+        nd2[s] = (float)(-(ex * ex + ey * ey));
+    }
+    const float hxf = (float)(3.5 * a.dx), hyf = (float)(3.5 * a.dy);
+    const float dzf = (float)a.dz;
+    const int nreg = a.tile >= kEdge ? a.tile / kEdge : 1;
+    const int ti1 = (tx + 1) * a.tile < a.W ? (tx + 1) * a.tile : a.W;
+    const int tj1 = (ty + 1) * a.tile < a.H ? (ty + 1) * a.tile : a.H;
+    const int own = deposit_owner(lane);
+    const StrutRec<float>* recs = (const StrutRec<float>*)a.rec;
+    const float* grad = (const float*)a.grad;
+    float* part = (float*)a.partial;
+
+    for (uint32_t cbase = beg; cbase < end; cbase += kWave) {
+        const int nent = (int)((end - cbase) < (uint32_t)kWave ? (end - cbase) : (uint32_t)kWave);
+        for (int q = lane; q < kWave * kParts; q += kWave) (&L.slot[0][0])[q] = 0.0f;
+        const uint32_t idx = cbase + (uint32_t)lane;
+        bool valid = idx < end;
+        const uint32_t pid = valid ? a.ids[idx] : 0u;
+        valid = valid && pid < a.n_binned;
+        const uint32_t p = valid ? pid : 0u;
+
+        for (int rg = 0; rg < nreg * nreg; ++rg) {
+            const int i0 = tx * a.tile + (rg % nreg) * kEdge;
+            const int j0 = ty * a.tile + (rg / nreg) * kEdge;
+            if (i0 >= ti1 || j0 >= tj1) continue;
+            uint32_t sub_ok = 0u;
+            for (int s = 0; s < kSub; ++s)
+                if (i0 + 8 * (s % NS) < ti1 && j0 + 8 * (s / NS) < tj1) sub_ok |= 1u << s;
+            const double cx = a.x0 + ((double)i0 + 0.5 * kEdge) * a.dx;
+            const double cy = a.y0 + ((double)j0 + 0.5 * kEdge) * a.dy;
+
+            for (int w0 = kb; w0 < ke; w0 += SZ) {
+                const int nw = ke - w0 < SZ ? ke - w0 : SZ;
+                // ------------------------------------------------ staging
+                {
+                    // read the entry afresh for every region and window: what
+                    // follows from it would otherwise stay in registers
+                    // through the evaluation
+                    uint32_t pr = p;
+                    asm volatile("" : "+v"(pr));
+                    const StrutRec<float> r = recs[pr];
+                    const double4 ln = a.line[pr];
+                    const double Rs = SR ? (double)r.pad : a.R;
+                    const double iR = 1.0 / Rs, iR2 = iR * iR;
+                    const float Rc2f = (float)(Rs * Rs * (1.0 + 2e-5));
+                    const double wx = cx - (double)r.ax, wy = cy - (double)r.ay;
+                    const double txy = fma(wx, ln.x, wy * ln.y);
+                    const double wz = a.z0 + ((double)w0 + 0.5) * a.dz - (double)r.az;
+                    const double tc0 = fma(wz, ln.z, txy);
+                    const double mx = fma(tc0, ln.x, -wx), my = fma(tc0, ln.y, -wy),
+                                 mz = fma(tc0, ln.z, -wz);
+                    const double m20 = fma(mx, mx, fma(my, my, mz * mz));
+                    const double dzuz = a.dz * ln.z;
+                    // m_k = m_0 + k dz (u_z u - e_z) is orthogonal to u:
+                    // |m_k|^2 = |m_0|^2 - 2 k dz m_0,z + k^2 dz^2 (1 - u_z^2)
+                    const double c1d = -2.0 * a.dz * mz, c2 = a.dz * a.dz * (1.0 - ln.z * ln.z);
+                    // sub-block centres c + delta_s: the foot moves by
+                    // delta.u along u, the offset m by (delta.u) u - delta
+                    float dus[kSub], cxs[kSub], cys[kSub], css[kSub], tdx[kSub], tdy[kSub];
+                    for (int s = 0; s < kSub; ++s) {
+                        const double ddx = (8.0 * (s % NS) + 4.0 - 0.5 * kEdge) * a.dx;
+                        const double ddy = (8.0 * (s / NS) + 4.0 - 0.5 * kEdge) * a.dy;
+                        const double du = fma(ddx, ln.x, ddy * ln.y);
+                        dus[s] = (float)du;
+                        cxs[s] = (float)fma(du, ln.x, -ddx);
+                        cys[s] = (float)fma(du, ln.y, -ddy);
+                        css[s] = (float)(ddx * ddx + ddy * ddy - du * du);
+                        tdx[s] = (float)(-2.0 * ddx);
+                        tdy[s] = (float)(-2.0 * ddy);
+                    }
+                    const float uxf = (float)ln.x, uyf = (float)ln.y, Lf = (float)ln.w;
+                    const float mxf0 = (float)mx, myf0 = (float)my;
+                    const float vxf = (float)(dzuz * ln.x), vyf = (float)(dzuz * ln.y);
+                    uint32_t mask = 0u;
+#pragma unroll 1
+                    for (int k = 0; k < nw; ++k) {
+                        const double kd = (double)k;
+                        const double tc = fma(kd, dzuz, tc0);
+                        const double m2 = fma(kd * kd, c2, fma(kd, c1d, m20));
+                        const float tcf = (float)tc, m2f = (float)m2, kf = (float)k;
+                        const float mxf = __builtin_fmaf(kf, vxf, mxf0);
+                        const float myf = __builtin_fmaf(kf, vyf, myf0);
+                        uint32_t bits = 0u;
+#pragma unroll
+                        for (int s = 0; s < kSub; ++s) {
+                            // e = F* - c_s, F* the segment's point nearest to
+                            // the sub-block centre; no pixel of the sub-block
+                            // is within R when D^2 - hx |e_x| - hy |e_y| >= R D
+                            const float tcs = tcf + dus[s];
+                            const float dt = __builtin_amdgcn_fmed3f(tcs, 0.0f, Lf) - tcs;
+                            const float ex = __builtin_fmaf(dt, uxf, mxf + cxs[s]);
+                            const float ey = __builtin_fmaf(dt, uyf, myf + cys[s]);
+                            const float m2s =
+                                __builtin_fmaf(tdx[s], mxf, __builtin_fmaf(tdy[s], myf, m2f + css[s]));
+                            const float D2 = __builtin_fmaf(dt, dt, m2s);
+                            const float q = D2 - __builtin_fmaf(hxf, fabsf(ex), hyf * fabsf(ey));
+                            const uint32_t pass =
+                                ((sub_ok >> s) & 1u) &
+                                ((uint32_t)(q <= 0.0f) | (uint32_t)(q * q < Rc2f * D2));
+                            bits |= pass << (s * SZ);
+                        }
+                        mask |= bits << k;
+                        const float G = (float)fma(-m2, iR2, 1.0);
+                        if constexpr (PR) {
+                            const double mxk = fma(kd, dzuz * ln.x, mx), myk = fma(kd, dzuz * ln.y, my);
+                            L.pl[k][lane] = make_float4((float)(-tc * iR), (float)((ln.w - tc) * iR), G,
+                                                        (float)(2.0 * mxk * iR2));
+                            L.pmy[k][lane] = (float)(2.0 * myk * iR2);
+                        } else {
+                            L.pg[k][lane] = G;
+                        }
+                    }
+                    if (!valid) mask = 0u;
+                    L.mask[lane] = mask;
+                    // the reference plane r: the middle of the planes the
+                    // strut reaches, so that the shifts k - r and the offsets
+                    // m_r stay small (m_k = m_r + (k - r) dm, dm = dz (u_z u -
+                    // e_z), grows without bound along a steep strut)
+                    uint32_t pm = 0u;
+                    for (int s = 0; s < kSub; ++s) pm |= (mask >> (s * SZ)) & ((1u << SZ) - 1u);
+                    const int rr = pm ? (__builtin_ctz(pm) + 31 - __builtin_clz(pm)) >> 1 : 0;
+                    const double rd = (double)rr;
+                    const double tcr = fma(rd, dzuz, tc0);
+                    const double mxr = fma(rd, dzuz * ln.x, mx), myr = fma(rd, dzuz * ln.y, my),
+                                 mzr = fma(rd, fma(dzuz, ln.z, -a.dz), mz);
+                    L.rk[lane] = (float)rr;
+                    L.e[lane] = make_float4((float)(ln.x * iR), (float)(ln.y * iR),
+                                            (float)(2.0 * dzuz * iR), (float)iR2);
+                    if constexpr (!PR) {
+                        L.dl[lane] = (float)(-dzuz * iR);
+                        L.gr[lane] = make_float4((float)(-tcr * iR), (float)((ln.w - tcr) * iR),
+                                                 (float)(2.0 * mxr * iR2), (float)(2.0 * myr * iR2));
+                    }
+                    L.m0[lane] = make_float4((float)mxr, (float)myr, (float)mzr, (float)Rs);
+                    L.u4[lane] = make_float4(uxf, uyf, (float)ln.z, (float)dzuz);
+                    const uint64_t cm = ballot64(mask != 0u);
+                    if (mask != 0u) {
+                        const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(cm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)cm, 0u));
+                        L.cand[rank] = (uint32_t)lane;
+                    }
+                }
+                // dL/dg at the lane's four pixels
+                float Gv[kSub][SZ];
+                q32::for_planes<0, kSub>([&](auto sc) {
+                    constexpr int s = decltype(sc)::value;
+                    const int pi = i0 + 8 * (s % NS) + lx, pj = j0 + 8 * (s / NS) + ly;
+                    const bool pix = pi < ti1 && pj < tj1;
+                    q32::for_planes<0, SZ>([&](auto kc) {
+                        constexpr int k = decltype(kc)::value;
+                        Gv[s][k] = (pix && k < nw)
+                                       ? grad[((size_t)(w0 + k - a.k0) * (size_t)a.H + (size_t)pj) *
+                                                  (size_t)a.W + (size_t)pi]
+                                       : 0.0f;
+                    });
+                });
+
+                __builtin_amdgcn_wave_barrier();
+                const int n = __popcll(ballot64(L.mask[lane] != 0u));
+
+                // --------------------------------------------- evaluation
+#pragma unroll 1
+                for (int j = 0; j < n; ++j) {
+                    const uint32_t e = L.cand[j];
+                    const uint32_t mask = __builtin_amdgcn_readfirstlane(L.mask[e]);
+                    const float4 E = L.e[e];
+                    const float rf = L.rk[e];
+                    float nD = 0.0f;
+                    float4 Rg = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    float Gk[SZ];
+                    if constexpr (!PR) {
+                        nD = L.dl[e];
+                        Rg = L.gr[e];
+                        q32::for_planes<0, SZ>([&](auto kc) {
+                            constexpr int k = decltype(kc)::value;
+                            Gk[k] = L.pg[k][e];
+                        });
+                    }
+                    float Aw = 0.0f, Aa = 0.0f, Ab = 0.0f;
+                    float AK = 0.0f, AKk = 0.0f, AKx = 0.0f, AKy = 0.0f, AKu = 0.0f;
+                    float AJ = 0.0f, AJk = 0.0f, AJx = 0.0f, AJy = 0.0f, AJu = 0.0f;
+                    q32::for_planes<0, kSub>([&](auto sc) {
+                        constexpr int s = decltype(sc)::value;
+                        const uint32_t ms = (mask >> (s * SZ)) & ((1u << SZ) - 1u);
+                        if (ms == 0u) return;
+                        // one plane's values at a time (not all planes kept
+                        // in registers across the four sub-blocks)
+                        uint32_t es = e;
+                        if constexpr (PR) asm volatile("" : "+v"(es));
+                        const float dX = Dx[s % NS], dY = Dy[s / NS];
+                        const float du = __builtin_fmaf(dX, E.x, dY * E.y);     // d.u^
+                        const float ndd = nd2[s] * E.w;                          // -|d^|^2
+                        float ar = 0.0f, br = 0.0f, Eg = 0.0f, P1 = 0.0f;
+                        if constexpr (!PR) {
+                            ar = Rg.x - du;
+                            br = Rg.y - du;
+                            Eg = __builtin_fmaf(du, du,
+                                                __builtin_fmaf(Rg.z, dX, __builtin_fmaf(Rg.w, dY, ndd)));
+                            P1 = E.z * du;
+                        }
+                        float Ks = 0.0f, Js = 0.0f;
+                        q32::for_planes<0, SZ>([&](auto kc) {
+                            constexpr int k = decltype(kc)::value;
+                            if (!((ms >> k) & 1u)) return;
+                            const float kap = (float)k - rf;      // k - r
+                            float al, be, Hp;
+                            if constexpr (PR) {
+                                const float4 P = L.pl[k][es];
+                                const float my2 = L.pmy[k][es];
+                                al = P.x - du;
+                                be = P.y - du;
+                                Hp = __builtin_fmaf(du, du,
+                                                    __builtin_fmaf(P.w, dX, __builtin_fmaf(my2, dY, ndd + P.z)));
+                            } else {
+                                al = __builtin_fmaf(kap, nD, ar);
+                                be = __builtin_fmaf(kap, nD, br);
+                                Hp = __builtin_fmaf(kap, P1, Gk[k] + Eg);
+                            }
+                            const float H = __builtin_amdgcn_fmed3f(Hp, 0.0f, 1.0f);
+                            const float h = __builtin_amdgcn_sqrtf(H);
+                            const float ca = __builtin_amdgcn_fmed3f(al, -h, h);
+                            const float cb = __builtin_amdgcn_fmed3f(be, -h, h);
+                            const float sm = ca + cb, D = cb - ca;
+                            const float s2 = sm * sm, D2 = D * D;
+                            const float A4 = __builtin_fmaf(D2, -1.0f / 3.0f, __builtin_fmaf(H, 4.0f, -s2));
+                            const float V16 = __builtin_fmaf(s2, 4.0f / 3.0f, D2 * (4.0f / 45.0f));
+                            const float Q16 = __builtin_fmaf(A4, A4, D2 * V16);
+                            const float g = Gv[s][k];
+                            const float gD = g * D;
+                            Aw = __builtin_fmaf(gD, Q16, Aw);
+                            const float Jq = gD * A4;
+                            const float xa = __builtin_fmaf(-ca, ca, H), xb = __builtin_fmaf(-cb, cb, H);
+                            const float pa = xa * xa, pb = xb * xb;
+                            Aa = __builtin_fmaf(g, pa, Aa);
+                            Ab = __builtin_fmaf(g, pb, Ab);
+                            const float gK = __builtin_fmaf(al, Jq, g * (pb - pa));
+                            Ks += gK;
+                            Js += Jq;
+                            AKk = __builtin_fmaf(kap, gK, AKk);
+                            AJk = __builtin_fmaf(kap, Jq, AJk);
+                        });
+                        AK += Ks;
+                        AKx = __builtin_fmaf(dX, Ks, AKx);
+                        AKy = __builtin_fmaf(dY, Ks, AKy);
+                        AKu = __builtin_fmaf(du, Ks, AKu);
+                        AJ += Js;
+                        AJx = __builtin_fmaf(dX, Js, AJx);
+                        AJy = __builtin_fmaf(dY, Js, AJy);
+                        AJu = __builtin_fmaf(du, Js, AJu);
+                    });
+                    // sum G K q_perp = m_r sum G K + dm sum (k - r) G K - sum G K d
+                    // + R u sum G K (d.u^), dm = dz u_z u - dz e_z
+                    const float4 M = L.m0[e], U = L.u4[e];
+                    const float dmx = U.w * U.x, dmy = U.w * U.y, dmz = __builtin_fmaf(U.w, U.z, -dzf);
+                    const float rux = M.w * U.x, ruy = M.w * U.y, ruz = M.w * U.z;
+                    const float v[kParts] = {
+                        Aw * (1.0f / 16.0f),
+                        Aa,
+                        Ab,
+                        __builtin_fmaf(M.x, AK, __builtin_fmaf(dmx, AKk, __builtin_fmaf(rux, AKu, -AKx))),
+                        __builtin_fmaf(M.y, AK, __builtin_fmaf(dmy, AKk, __builtin_fmaf(ruy, AKu, -AKy))),
+                        __builtin_fmaf(M.z, AK, __builtin_fmaf(dmz, AKk, ruz * AKu)),
+                        0.5f * __builtin_fmaf(M.x, AJ, __builtin_fmaf(dmx, AJk, __builtin_fmaf(rux, AJu, -AJx))),
+                        0.5f * __builtin_fmaf(M.y, AJ, __builtin_fmaf(dmy, AJk, __builtin_fmaf(ruy, AJu, -AJy))),
+                        0.5f * __builtin_fmaf(M.z, AJ, __builtin_fmaf(dmz, AJk, ruz * AJu))};
+                    deposit(L.slot[e], v, lane, own);
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        // each entry's sums go to its emission index
+        for (int q = lane; q < nent * kParts; q += kWave) {
+            const uint32_t e = a.emi[cbase + (uint32_t)(q / kParts)];
+            if (e < a.n_pairs) part[(size_t)e * kParts + (size_t)(q % kParts)] = (&L.slot[0][0])[q];
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+template <int SZ, bool SR, int NS>
+void launch_pr(const BackArgs& a, uint32_t n_items, hipStream_t st) {
+    if (a.plane_ref)
+        k_backward32<SZ, SR, true, NS><<<n_items, 64, 0, st>>>(a, n_items);
+    else
+        k_backward32<SZ, SR, false, NS><<<n_items, 64, 0, st>>>(a, n_items);
+}
+
+template <int SZ, bool SR>
+void launch_sz(const BackArgs& a, uint32_t n_items, hipStream_t st) {
+    if (a.wide)
+        launch_pr<SZ, SR, 2>(a, n_items, st);
+    else
+        launch_pr<SZ, SR, 1>(a, n_items, st);
+}
+
+template <int SZ>
+void launch_sr(const BackArgs& a, uint32_t n_items, hipStream_t st) {
+    if (a.strut_R)
+        launch_sz<SZ, true>(a, n_items, st);
+    else
+        launch_sz<SZ, false>(a, n_items, st);
+}
+
+lsl_status launch(const BackArgs& a, uint32_t n_items, hipStream_t st) {
+    if (a.slab <= 1)
+        launch_sr<1>(a, n_items, st);
+    else if (a.slab <= 2)
+        launch_sr<2>(a, n_items, st);
+    else if (a.slab <= 4)
+        launch_sr<4>(a, n_items, st);
+    else
+        launch_sr<8>(a, n_items, st);      // longer slabs: windows of 8 planes
+    LSL_HIP(hipGetLastError());
+    return LSL_OK;
+}
+
+}  // namespace b32
+
 // Per active strut: sum its pairs of the slabs [s_lo, s_hi] in emission
 // order, then form the strut's gradient and add it to acc (float64).
 template <typename T>
@@ -422,8 +859,18 @@ __global__ void k_reduce(ReduceArgs a, const SRange* ranges, int32_t sa, int32_t
     const double R4 = Rs * Rs * Rs * Rs;
     const Line ln = strut_line(r);
     const double u[3] = {ln.ux, ln.uy, ln.uz};
-    const double cw = w / R4;
     double* acc = a.acc + (size_t)p * 7;
+    if (a.normalized) {
+        // partials in units of R: sum G I / R, phi and K dimensionless, J R
+        acc[0] += s[0] * Rs;
+        for (int c = 0; c < 3; ++c) {
+            const double kq = s[3 + c] / ln.L;
+            acc[1 + c] -= w * (s[1] * u[c] + kq + 2.0 * s[6 + c] / Rs);   // dL/da
+            acc[4 + c] += w * (s[2] * u[c] + kq);                         // dL/db
+        }
+        return;
+    }
+    const double cw = w / R4;
     acc[0] += s[0] / R4;
     for (int c = 0; c < 3; ++c) {
         const double kq = s[3 + c] / ln.L;
@@ -514,7 +961,7 @@ lsl_status launch_backward(int dtype, const BackArgs& a, hipStream_t st) {
         set_error("slice_field_backward: too many work items in one launch");
         return LSL_EINTERNAL;
     }
-    if (dtype == LSL_F32) return launch_bt<float>(a, (uint32_t)n_items, st);
+    if (dtype == LSL_F32) return b32::launch(a, (uint32_t)n_items, st);
     return launch_bt<double>(a, (uint32_t)n_items, st);
 }
 

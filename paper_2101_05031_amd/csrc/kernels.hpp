@@ -179,6 +179,9 @@ struct BackArgs {
     const uint32_t* emi;              // bucket entry -> emission index
     const void* grad;                 // [nk][H][W]
     void* partial;                    // [n_pairs][9] T, in emission order
+    const double4* line;              // [n_binned]: u (x, y, z), L per strut (float64)
+    int32_t plane_ref;                // 1: every plane its own reference (coarse plane pitch)
+    int32_t wide;                     // float32: 1 = 16x16-pixel regions, 0 = 8x8
 };
 lsl_status launch_backward(int dtype, const BackArgs& a, hipStream_t st);
 
@@ -191,6 +194,7 @@ struct ReduceArgs {
     const void* w;
     double R;
     int32_t strut_R;                  // 1: strut j's support is rec[j].pad, else R
+    int32_t normalized;               // 1: partials in units of the support (float32 path)
     double* acc;                      // [n_binned][7]: dL/dw, dL/da (3), dL/db (3)
 };
 lsl_status launch_reduce(int dtype, const ReduceArgs& a, const SRange* ranges, int32_t sa,

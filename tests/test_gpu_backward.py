@@ -35,8 +35,19 @@ def small_case():
     return lat, grid
 
 
+def fine_case():
+    """Pixels of 0.075 mm and planes 0.08 mm apart (R = 1.5 mm): fine enough
+    that planes share reference planes in the float32 kernels (the small
+    case's coarse planes each carry their own)."""
+    lat = synth.kuhn_lattice(2, 6.0, seed=33)
+    grid = synth.grid_for(lat, 150, 140, 24, dz=0.08)
+    return lat, grid
+
+
 @pytest.mark.parametrize("case,tile,slab,max_pairs", [
-    ("kuhn", 16, 8, 0), ("kuhn", 32, 4, 0), ("kuhn", 16, 2, 2000), ("P1", 16, 8, 0),
+    ("kuhn", 16, 8, 0), ("kuhn", 32, 4, 0), ("kuhn", 16, 2, 2000), ("kuhn", 8, 16, 0),
+    ("fine", 16, 8, 0), ("fine", 32, 16, 0), ("fine", 8, 3, 0), ("fine", 64, 4, 3000),
+    ("P1", 16, 8, 0),
 ])
 def test_backward_matches_oracle(case, tile, slab, max_pairs):
     if case == "P1":
@@ -44,7 +55,7 @@ def test_backward_matches_oracle(case, tile, slab, max_pairs):
         ks = range(10, 22)
         rtol = 1e-10
     else:
-        lat, grid = small_case()
+        lat, grid = small_case() if case == "kuhn" else fine_case()
         ks = range(0, grid.n_slices)
         rtol = 1e-4
     print(f"backward {case} tile={tile} slab={slab} max_pairs={max_pairs}", flush=True)
