@@ -431,22 +431,32 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
 //   J R          = 2 D A'          (the H-derivative of the integral; the
 //                                   clamped ends add nothing, the integrand
 //                                   vanishes there)
-//   K            = phi(beta) - phi(alpha) + 4 alpha^ D A'
 //
-// (K and phi are dimensionless; the loop keeps 16 D Q and 4 D A', whose
-// powers of two are taken out before the wave sums.)  The q_perp weights
+// and the two ends' weights of q_perp, K_b = K and K_a = K + 2 J L:
+//
+//   K_b = phi(beta) - phi(alpha) + 4 alpha^ D A'
+//   K_a = phi(beta) - phi(alpha) + 4 beta^ D A'
+//   dI/db = phi(beta) u + (K_b / L) q_perp,  dI/da = -phi(alpha) u - (K_a / L) q_perp
+//
+// (summing K and J apart would cancel in K / L + 2 J for pixels near one end
+// of a strut much longer than its support).  K and phi are dimensionless;
+// the loop keeps 16 D Q and 4 D A', and takes out the power of two before
+// the wave sums.  The q_perp weights
 // follow from q_perp = m_k - d + (d.u) u with m_k = m_r + (k - r) dm: each
-// lane keeps, per (strut, region), sum G K, sum (k - r) G K, and the sums
-// of G K over each sub-block times the pixel's d_x, d_y and d.u (likewise
-// for J), and forms its three components once before the wave sums.  The
-// partials are then (sum G I / R, sum G phi(alpha), sum G phi(beta), sum G K
-// q_perp, sum G J R q_perp): k_reduce scales them by R.
+// lane keeps, per (strut, region), sum G K, sum (k - r) G K, and sum G K
+// over its right-hand and lower sub-blocks (whose d is 8 dx, 8 dy larger),
+// for K_b and K_a, and forms the three components once before the wave sums.
+// The partials are then (sum G I / R, sum G phi(alpha), sum G phi(beta), sum
+// G K_b q_perp, sum G K_a q_perp): k_reduce scales them by R and 1/L.
 //
 // The rounding of H^ grows with |d| / R (its pieces 2 m^.d^ and |d^|^2 grow
 // while H^ <= 1), so the 16x16 regions are used only while their farthest
 // pixel, 7.5 |(dx, dy)| from the centre, stays within the smallest support;
-// otherwise d is measured from each 8x8 block's centre, as in the field
-// kernel.
+// otherwise d is measured from each 8x8 block's centre and H^ = 1 -
+// |q_perp^|^2 is formed from q_perp^ = m_k^ - (d^ - (d.u^) u) itself, whose
+// components are of the size of the support (three more operations per
+// pair; for pixels coarse against the support this halves the error of the
+// node gradients).
 namespace b32 {
 
 template <int SZ, bool PR>
@@ -477,9 +487,16 @@ struct Lds<SZ, true> {
     float slot[kWave][kParts];
 };
 
-template <int SZ, bool SR, bool PR, int NS>
+// MODE 0: 16x16 regions, shared reference planes; 1: 16x16 regions, every
+// plane its own reference; 2: 8x8 regions, every plane its own reference
+// and H^ = 1 - |q_perp^|^2 formed from q_perp itself (coarse pixels against
+// the support: the pieces of H^ above would be large).
+template <int SZ, bool SR, int MODE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_backward32(
     BackArgs a, uint32_t n_items) {
+    constexpr int NS = MODE == 2 ? 1 : 2;     // sub-blocks per region side
+    constexpr bool PR = MODE != 0;            // per-plane values in LDS
+    constexpr bool QD = MODE == 2;            // H^ from q_perp
     constexpr int kSub = NS * NS;             // 8x8 sub-blocks of a region
     constexpr int kEdge = 8 * NS;             // region edge in pixels
     __shared__ Lds<SZ, PR> L;
@@ -514,7 +531,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         nd2[s] = (float)(-(ex * ex + ey * ey));
     }
     const float hxf = (float)(3.5 * a.dx), hyf = (float)(3.5 * a.dy);
-    const float dzf = (float)a.dz;
+    const float dzf = (float)a.dz, dxf = (float)a.dx, dyf = (float)a.dy;
     const int nreg = a.tile >= kEdge ? a.tile / kEdge : 1;
     const int ti1 = (tx + 1) * a.tile < a.W ? (tx + 1) * a.tile : a.W;
     const int tj1 = (ty + 1) * a.tile < a.H ? (ty + 1) * a.tile : a.H;
@@ -613,14 +630,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                             bits |= pass << (s * SZ);
                         }
                         mask |= bits << k;
-                        const float G = (float)fma(-m2, iR2, 1.0);
-                        if constexpr (PR) {
+                        if constexpr (QD) {
+                            // m_k / R
+                            const double mxk = fma(kd, dzuz * ln.x, mx), myk = fma(kd, dzuz * ln.y, my),
+                                         mzk = fma(kd, fma(dzuz, ln.z, -a.dz), mz);
+                            L.pl[k][lane] = make_float4((float)(-tc * iR), (float)((ln.w - tc) * iR),
+                                                        (float)(mxk * iR), (float)(myk * iR));
+                            L.pmy[k][lane] = (float)(mzk * iR);
+                        } else if constexpr (PR) {
                             const double mxk = fma(kd, dzuz * ln.x, mx), myk = fma(kd, dzuz * ln.y, my);
-                            L.pl[k][lane] = make_float4((float)(-tc * iR), (float)((ln.w - tc) * iR), G,
-                                                        (float)(2.0 * mxk * iR2));
+                            L.pl[k][lane] = make_float4((float)(-tc * iR), (float)((ln.w - tc) * iR),
+                                                        (float)fma(-m2, iR2, 1.0), (float)(2.0 * mxk * iR2));
                             L.pmy[k][lane] = (float)(2.0 * myk * iR2);
                         } else {
-                            L.pg[k][lane] = G;
+                            L.pg[k][lane] = (float)fma(-m2, iR2, 1.0);
                         }
                     }
                     if (!valid) mask = 0u;
@@ -638,7 +661,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                                  mzr = fma(rd, fma(dzuz, ln.z, -a.dz), mz);
                     L.rk[lane] = (float)rr;
                     L.e[lane] = make_float4((float)(ln.x * iR), (float)(ln.y * iR),
-                                            (float)(2.0 * dzuz * iR), (float)iR2);
+                                            (float)(2.0 * dzuz * iR), (float)(QD ? iR : iR2));
                     if constexpr (!PR) {
                         L.dl[lane] = (float)(-dzuz * iR);
                         L.gr[lane] = make_float4((float)(-tcr * iR), (float)((ln.w - tcr) * iR),
@@ -677,6 +700,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     const uint32_t e = L.cand[j];
                     const uint32_t mask = __builtin_amdgcn_readfirstlane(L.mask[e]);
                     const float4 E = L.e[e];
+                    const float4 U = L.u4[e];
                     const float rf = L.rk[e];
                     float nD = 0.0f;
                     float4 Rg = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -689,9 +713,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                             Gk[k] = L.pg[k][e];
                         });
                     }
+                    // per lane: sum G I, G phi(alpha), G phi(beta); sum G K, sum
+                    // (k - r) G K and sum G K over the right-hand (sx = 1) and
+                    // lower (sy = 1) sub-blocks, whose pixels lie 8 dx, 8 dy
+                    // further (likewise for J)
                     float Aw = 0.0f, Aa = 0.0f, Ab = 0.0f;
-                    float AK = 0.0f, AKk = 0.0f, AKx = 0.0f, AKy = 0.0f, AKu = 0.0f;
-                    float AJ = 0.0f, AJk = 0.0f, AJx = 0.0f, AJy = 0.0f, AJu = 0.0f;
+                    float AB = 0.0f, ABk = 0.0f, SXB = 0.0f, SYB = 0.0f;
+                    float AA = 0.0f, AAk = 0.0f, SXA = 0.0f, SYA = 0.0f;
                     q32::for_planes<0, kSub>([&](auto sc) {
                         constexpr int s = decltype(sc)::value;
                         const uint32_t ms = (mask >> (s * SZ)) & ((1u << SZ) - 1u);
@@ -702,7 +730,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                         if constexpr (PR) asm volatile("" : "+v"(es));
                         const float dX = Dx[s % NS], dY = Dy[s / NS];
                         const float du = __builtin_fmaf(dX, E.x, dY * E.y);     // d.u^
-                        const float ndd = nd2[s] * E.w;                          // -|d^|^2
+                        float ndd = 0.0f, vx = 0.0f, vy = 0.0f, vz = 0.0f;
+                        if constexpr (QD) {
+                            // q_perp^ = m_k^ - v, v = d^ - (d.u^) u
+                            vx = __builtin_fmaf(-du, U.x, dX * E.w);
+                            vy = __builtin_fmaf(-du, U.y, dY * E.w);
+                            vz = -du * U.z;
+                        } else {
+                            ndd = nd2[s] * E.w;                                  // -|d^|^2
+                        }
                         float ar = 0.0f, br = 0.0f, Eg = 0.0f, P1 = 0.0f;
                         if constexpr (!PR) {
                             ar = Rg.x - du;
@@ -711,13 +747,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                                                 __builtin_fmaf(Rg.z, dX, __builtin_fmaf(Rg.w, dY, ndd)));
                             P1 = E.z * du;
                         }
-                        float Ks = 0.0f, Js = 0.0f;
+                        float Bs = 0.0f, As = 0.0f;
                         q32::for_planes<0, SZ>([&](auto kc) {
                             constexpr int k = decltype(kc)::value;
                             if (!((ms >> k) & 1u)) return;
                             const float kap = (float)k - rf;      // k - r
                             float al, be, Hp;
-                            if constexpr (PR) {
+                            if constexpr (QD) {
+                                const float4 P = L.pl[k][es];
+                                const float qz = L.pmy[k][es] - vz;
+                                const float qx = P.z - vx, qy = P.w - vy;
+                                al = P.x - du;
+                                be = P.y - du;
+                                Hp = 1.0f - __builtin_fmaf(qx, qx, __builtin_fmaf(qy, qy, qz * qz));
+                            } else if constexpr (PR) {
                                 const float4 P = L.pl[k][es];
                                 const float my2 = L.pmy[k][es];
                                 al = P.x - du;
@@ -741,41 +784,54 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                             const float g = Gv[s][k];
                             const float gD = g * D;
                             Aw = __builtin_fmaf(gD, Q16, Aw);
-                            const float Jq = gD * A4;
+                            const float Jq = gD * A4;                    // 2 G J R
                             const float xa = __builtin_fmaf(-ca, ca, H), xb = __builtin_fmaf(-cb, cb, H);
                             const float pa = xa * xa, pb = xb * xb;
                             Aa = __builtin_fmaf(g, pa, Aa);
                             Ab = __builtin_fmaf(g, pb, Ab);
-                            const float gK = __builtin_fmaf(al, Jq, g * (pb - pa));
-                            Ks += gK;
-                            Js += Jq;
-                            AKk = __builtin_fmaf(kap, gK, AKk);
-                            AJk = __builtin_fmaf(kap, Jq, AJk);
+                            const float gd = g * (pb - pa);
+                            const float gKb = __builtin_fmaf(al, Jq, gd), gKa = __builtin_fmaf(be, Jq, gd);
+                            Bs += gKb;
+                            As += gKa;
+                            ABk = __builtin_fmaf(kap, gKb, ABk);
+                            AAk = __builtin_fmaf(kap, gKa, AAk);
                         });
-                        AK += Ks;
-                        AKx = __builtin_fmaf(dX, Ks, AKx);
-                        AKy = __builtin_fmaf(dY, Ks, AKy);
-                        AKu = __builtin_fmaf(du, Ks, AKu);
-                        AJ += Js;
-                        AJx = __builtin_fmaf(dX, Js, AJx);
-                        AJy = __builtin_fmaf(dY, Js, AJy);
-                        AJu = __builtin_fmaf(du, Js, AJu);
+                        AB += Bs;
+                        AA += As;
+                        if constexpr (s % NS != 0) {
+                            SXB += Bs;
+                            SXA += As;
+                        }
+                        if constexpr (s / NS != 0) {
+                            SYB += Bs;
+                            SYA += As;
+                        }
                     });
+                    // sums of G K times the pixel's d_x, d_y and d.u^ (d of
+                    // sub-block (sx, sy) = d_00 + 8 (sx dx, sy dy))
+                    const float du0 = __builtin_fmaf(Dx[0], E.x, Dy[0] * E.y);
+                    const float e8x = 8.0f * dxf * E.x, e8y = 8.0f * dyf * E.y;
+                    const float ABx = __builtin_fmaf(8.0f * dxf, SXB, Dx[0] * AB);
+                    const float ABy = __builtin_fmaf(8.0f * dyf, SYB, Dy[0] * AB);
+                    const float ABu = __builtin_fmaf(e8x, SXB, __builtin_fmaf(e8y, SYB, du0 * AB));
+                    const float AAx = __builtin_fmaf(8.0f * dxf, SXA, Dx[0] * AA);
+                    const float AAy = __builtin_fmaf(8.0f * dyf, SYA, Dy[0] * AA);
+                    const float AAu = __builtin_fmaf(e8x, SXA, __builtin_fmaf(e8y, SYA, du0 * AA));
                     // sum G K q_perp = m_r sum G K + dm sum (k - r) G K - sum G K d
-                    // + R u sum G K (d.u^), dm = dz u_z u - dz e_z
-                    const float4 M = L.m0[e], U = L.u4[e];
+                    // + R u sum G K (d.u^), dm = dz u_z u - dz e_z, for K_b and K_a
+                    const float4 M = L.m0[e];
                     const float dmx = U.w * U.x, dmy = U.w * U.y, dmz = __builtin_fmaf(U.w, U.z, -dzf);
                     const float rux = M.w * U.x, ruy = M.w * U.y, ruz = M.w * U.z;
                     const float v[kParts] = {
                         Aw * (1.0f / 16.0f),
                         Aa,
                         Ab,
-                        __builtin_fmaf(M.x, AK, __builtin_fmaf(dmx, AKk, __builtin_fmaf(rux, AKu, -AKx))),
-                        __builtin_fmaf(M.y, AK, __builtin_fmaf(dmy, AKk, __builtin_fmaf(ruy, AKu, -AKy))),
-                        __builtin_fmaf(M.z, AK, __builtin_fmaf(dmz, AKk, ruz * AKu)),
-                        0.5f * __builtin_fmaf(M.x, AJ, __builtin_fmaf(dmx, AJk, __builtin_fmaf(rux, AJu, -AJx))),
-                        0.5f * __builtin_fmaf(M.y, AJ, __builtin_fmaf(dmy, AJk, __builtin_fmaf(ruy, AJu, -AJy))),
-                        0.5f * __builtin_fmaf(M.z, AJ, __builtin_fmaf(dmz, AJk, ruz * AJu))};
+                        __builtin_fmaf(M.x, AB, __builtin_fmaf(dmx, ABk, __builtin_fmaf(rux, ABu, -ABx))),
+                        __builtin_fmaf(M.y, AB, __builtin_fmaf(dmy, ABk, __builtin_fmaf(ruy, ABu, -ABy))),
+                        __builtin_fmaf(M.z, AB, __builtin_fmaf(dmz, ABk, ruz * ABu)),
+                        __builtin_fmaf(M.x, AA, __builtin_fmaf(dmx, AAk, __builtin_fmaf(rux, AAu, -AAx))),
+                        __builtin_fmaf(M.y, AA, __builtin_fmaf(dmy, AAk, __builtin_fmaf(ruy, AAu, -AAy))),
+                        __builtin_fmaf(M.z, AA, __builtin_fmaf(dmz, AAk, ruz * AAu))};
                     deposit(L.slot[e], v, lane, own);
                 }
                 __builtin_amdgcn_wave_barrier();
@@ -791,20 +847,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }
 }
 
-template <int SZ, bool SR, int NS>
-void launch_pr(const BackArgs& a, uint32_t n_items, hipStream_t st) {
-    if (a.plane_ref)
-        k_backward32<SZ, SR, true, NS><<<n_items, 64, 0, st>>>(a, n_items);
-    else
-        k_backward32<SZ, SR, false, NS><<<n_items, 64, 0, st>>>(a, n_items);
-}
-
 template <int SZ, bool SR>
 void launch_sz(const BackArgs& a, uint32_t n_items, hipStream_t st) {
-    if (a.wide)
-        launch_pr<SZ, SR, 2>(a, n_items, st);
+    if (!a.wide)
+        k_backward32<SZ, SR, 2><<<n_items, 64, 0, st>>>(a, n_items);
+    else if (a.plane_ref)
+        k_backward32<SZ, SR, 1><<<n_items, 64, 0, st>>>(a, n_items);
     else
-        launch_pr<SZ, SR, 1>(a, n_items, st);
+        k_backward32<SZ, SR, 0><<<n_items, 64, 0, st>>>(a, n_items);
 }
 
 template <int SZ>
@@ -861,12 +911,12 @@ __global__ void k_reduce(ReduceArgs a, const SRange* ranges, int32_t sa, int32_t
     const double u[3] = {ln.ux, ln.uy, ln.uz};
     double* acc = a.acc + (size_t)p * 7;
     if (a.normalized) {
-        // partials in units of R: sum G I / R, phi and K dimensionless, J R
+        // partials in units of R: sum G I / R; phi and the end weights K_b,
+        // K_a dimensionless
         acc[0] += s[0] * Rs;
         for (int c = 0; c < 3; ++c) {
-            const double kq = s[3 + c] / ln.L;
-            acc[1 + c] -= w * (s[1] * u[c] + kq + 2.0 * s[6 + c] / Rs);   // dL/da
-            acc[4 + c] += w * (s[2] * u[c] + kq);                         // dL/db
+            acc[1 + c] -= w * (s[1] * u[c] + s[6 + c] / ln.L);   // dL/da
+            acc[4 + c] += w * (s[2] * u[c] + s[3 + c] / ln.L);   // dL/db
         }
         return;
     }

@@ -24,6 +24,7 @@ def grad_close(got, ref, rtol, what):
     scale = np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
     per = np.abs(got - ref) / scale
     norm = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"{what}: per-parameter {per.max():.2e}, normwise {norm:.2e}", flush=True)
     assert per.max() <= rtol and norm <= rtol, \
         f"{what}: per-parameter {per.max():.2e}, normwise {norm:.2e} (tol {rtol:.0e})"
     return per.max(), norm
