@@ -654,7 +654,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     // e_z), grows without bound along a steep strut)
                     uint32_t pm = 0u;
                     for (int s = 0; s < kSub; ++s) pm |= (mask >> (s * SZ)) & ((1u << SZ) - 1u);
-                    const int rr = pm ? (__builtin_ctz(pm) + 31 - __builtin_clz(pm)) >> 1 : 0;
+                    // (shared reference planes: the window's first plane, as
+                    // fine planes keep (k - r) dz small against R)
+                    const int rr = (MODE != 0 && pm) ? (__builtin_ctz(pm) + 31 - __builtin_clz(pm)) >> 1 : 0;
                     const double rd = (double)rr;
                     const double tcr = fma(rd, dzuz, tc0);
                     const double mxr = fma(rd, dzuz * ln.x, mx), myr = fma(rd, dzuz * ln.y, my),
@@ -720,6 +722,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     float Aw = 0.0f, Aa = 0.0f, Ab = 0.0f;
                     float AB = 0.0f, ABk = 0.0f, SXB = 0.0f, SYB = 0.0f;
                     float AA = 0.0f, AAk = 0.0f, SXA = 0.0f, SYA = 0.0f;
+                    const float du0 = __builtin_fmaf(Dx[0], E.x, Dy[0] * E.y);
+                    const float e8x = NS == 2 ? 8.0f * dxf * E.x : 0.0f;
+                    const float e8y = NS == 2 ? 8.0f * dyf * E.y : 0.0f;
                     q32::for_planes<0, kSub>([&](auto sc) {
                         constexpr int s = decltype(sc)::value;
                         const uint32_t ms = (mask >> (s * SZ)) & ((1u << SZ) - 1u);
@@ -729,7 +734,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                         uint32_t es = e;
                         if constexpr (PR) asm volatile("" : "+v"(es));
                         const float dX = Dx[s % NS], dY = Dy[s / NS];
-                        const float du = __builtin_fmaf(dX, E.x, dY * E.y);     // d.u^
+                        // d.u^ (d of sub-block (sx, sy) = d_00 + 8 (sx dx, sy dy))
+                        float du = du0;
+                        if constexpr (s % NS != 0) du += e8x;
+                        if constexpr (s / NS != 0) du += e8y;
                         float ndd = 0.0f, vx = 0.0f, vy = 0.0f, vz = 0.0f;
                         if constexpr (QD) {
                             // q_perp^ = m_k^ - v, v = d^ - (d.u^) u
@@ -751,7 +759,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                         q32::for_planes<0, SZ>([&](auto kc) {
                             constexpr int k = decltype(kc)::value;
                             if (!((ms >> k) & 1u)) return;
-                            const float kap = (float)k - rf;      // k - r
+                            // k - r (r = 0 with shared reference planes)
+                            const float kap = MODE == 0 ? (float)k : (float)k - rf;
                             float al, be, Hp;
                             if constexpr (QD) {
                                 const float4 P = L.pl[k][es];
@@ -767,6 +776,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                                 be = P.y - du;
                                 Hp = __builtin_fmaf(du, du,
                                                     __builtin_fmaf(P.w, dX, __builtin_fmaf(my2, dY, ndd + P.z)));
+                            } else if constexpr (k == 0) {
+                                al = ar;
+                                be = br;
+                                Hp = Gk[0] + Eg;
                             } else {
                                 al = __builtin_fmaf(kap, nD, ar);
                                 be = __builtin_fmaf(kap, nD, br);
@@ -793,8 +806,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                             const float gKb = __builtin_fmaf(al, Jq, gd), gKa = __builtin_fmaf(be, Jq, gd);
                             Bs += gKb;
                             As += gKa;
-                            ABk = __builtin_fmaf(kap, gKb, ABk);
-                            AAk = __builtin_fmaf(kap, gKa, AAk);
+                            if (MODE != 0 || k != 0) {
+                                ABk = __builtin_fmaf(kap, gKb, ABk);
+                                AAk = __builtin_fmaf(kap, gKa, AAk);
+                            }
                         });
                         AB += Bs;
                         AA += As;
@@ -807,10 +822,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                             SYA += As;
                         }
                     });
-                    // sums of G K times the pixel's d_x, d_y and d.u^ (d of
-                    // sub-block (sx, sy) = d_00 + 8 (sx dx, sy dy))
-                    const float du0 = __builtin_fmaf(Dx[0], E.x, Dy[0] * E.y);
-                    const float e8x = 8.0f * dxf * E.x, e8y = 8.0f * dyf * E.y;
+                    // sums of G K times the pixel's d_x, d_y and d.u^
                     const float ABx = __builtin_fmaf(8.0f * dxf, SXB, Dx[0] * AB);
                     const float ABy = __builtin_fmaf(8.0f * dyf, SYB, Dy[0] * AB);
                     const float ABu = __builtin_fmaf(e8x, SXB, __builtin_fmaf(e8y, SYB, du0 * AB));
