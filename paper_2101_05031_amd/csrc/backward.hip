@@ -719,9 +719,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     // (k - r) G K and sum G K over the right-hand (sx = 1) and
                     // lower (sy = 1) sub-blocks, whose pixels lie 8 dx, 8 dy
                     // further (likewise for J)
-                    float Aw = 0.0f, Aa = 0.0f, Ab = 0.0f;
-                    float AB = 0.0f, ABk = 0.0f, SXB = 0.0f, SYB = 0.0f;
-                    float AA = 0.0f, AAk = 0.0f, SXA = 0.0f, SYA = 0.0f;
+                    float Aw = 0.0f, Aa = 0.0f, Ab = 0.0f, ABk = 0.0f, AAk = 0.0f;
+                    float Bs[kSub], As[kSub];                 // per sub-block
+                    q32::for_planes<0, kSub>([&](auto sc) {
+                        constexpr int s = decltype(sc)::value;
+                        Bs[s] = As[s] = 0.0f;
+                    });
                     const float du0 = __builtin_fmaf(Dx[0], E.x, Dy[0] * E.y);
                     const float e8x = NS == 2 ? 8.0f * dxf * E.x : 0.0f;
                     const float e8y = NS == 2 ? 8.0f * dyf * E.y : 0.0f;
@@ -755,7 +758,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                                                 __builtin_fmaf(Rg.z, dX, __builtin_fmaf(Rg.w, dY, ndd)));
                             P1 = E.z * du;
                         }
-                        float Bs = 0.0f, As = 0.0f;
                         q32::for_planes<0, SZ>([&](auto kc) {
                             constexpr int k = decltype(kc)::value;
                             if (!((ms >> k) & 1u)) return;
@@ -803,25 +805,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                             Aa = __builtin_fmaf(g, pa, Aa);
                             Ab = __builtin_fmaf(g, pb, Ab);
                             const float gd = g * (pb - pa);
-                            const float gKb = __builtin_fmaf(al, Jq, gd), gKa = __builtin_fmaf(be, Jq, gd);
-                            Bs += gKb;
-                            As += gKa;
+                            // (shared reference planes, fine pixels: J itself
+                            // instead of K_a, one operation less)
+                            const float gKb = __builtin_fmaf(al, Jq, gd);
+                            const float gKa = MODE == 0 ? Jq : __builtin_fmaf(be, Jq, gd);
+                            Bs[s] += gKb;
+                            As[s] += gKa;
                             if (MODE != 0 || k != 0) {
                                 ABk = __builtin_fmaf(kap, gKb, ABk);
                                 AAk = __builtin_fmaf(kap, gKa, AAk);
                             }
                         });
-                        AB += Bs;
-                        AA += As;
-                        if constexpr (s % NS != 0) {
-                            SXB += Bs;
-                            SXA += As;
-                        }
-                        if constexpr (s / NS != 0) {
-                            SYB += Bs;
-                            SYA += As;
-                        }
                     });
+                    // over all sub-blocks, the right-hand ones and the lower ones
+                    float AB = Bs[0], AA = As[0], SXB = 0.0f, SXA = 0.0f, SYB = 0.0f, SYA = 0.0f;
+                    if constexpr (NS == 2) {
+                        SXB = Bs[1] + Bs[3];
+                        SXA = As[1] + As[3];
+                        SYB = Bs[2] + Bs[3];
+                        SYA = As[2] + As[3];
+                        AB = (Bs[0] + Bs[2]) + SXB;
+                        AA = (As[0] + As[2]) + SXA;
+                    }
                     // sums of G K times the pixel's d_x, d_y and d.u^
                     const float ABx = __builtin_fmaf(8.0f * dxf, SXB, Dx[0] * AB);
                     const float ABy = __builtin_fmaf(8.0f * dyf, SYB, Dy[0] * AB);
@@ -834,7 +839,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     const float4 M = L.m0[e];
                     const float dmx = U.w * U.x, dmy = U.w * U.y, dmz = __builtin_fmaf(U.w, U.z, -dzf);
                     const float rux = M.w * U.x, ruy = M.w * U.y, ruz = M.w * U.z;
-                    const float v[kParts] = {
+                    float v[kParts] = {
                         Aw * (1.0f / 16.0f),
                         Aa,
                         Ab,
@@ -844,6 +849,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                         __builtin_fmaf(M.x, AA, __builtin_fmaf(dmx, AAk, __builtin_fmaf(rux, AAu, -AAx))),
                         __builtin_fmaf(M.y, AA, __builtin_fmaf(dmy, AAk, __builtin_fmaf(ruy, AAu, -AAy))),
                         __builtin_fmaf(M.z, AA, __builtin_fmaf(dmz, AAk, ruz * AAu))};
+                    if constexpr (MODE == 0) {
+                        // K_a = K_b + 2 J L: the second sums carried J
+                        const float Lh = Rg.y - Rg.x;
+                        v[6] = __builtin_fmaf(Lh, v[6], v[3]);
+                        v[7] = __builtin_fmaf(Lh, v[7], v[4]);
+                        v[8] = __builtin_fmaf(Lh, v[8], v[5]);
+                    }
                     deposit(L.slot[e], v, lane, own);
                 }
                 __builtin_amdgcn_wave_barrier();
