@@ -29,7 +29,13 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FLOP_PER_USEFUL_PAIR = 36          # see the field kernel's op count
+# Algorithmic work per useful (pixel, strut) pair: the field term counted
+# with FMA = 2 and add, mul, sqrt, clamp = 1 each (40 for the closed form with
+# a compensated sum); the adjoint's terms counted the same way (48: the field
+# term without its sum, the two end terms phi, the H-derivative and the
+# q_perp weights of both ends, with their per-pixel sums)
+FLOP_PER_USEFUL_PAIR = 40
+FLOP_PER_USEFUL_PAIR_ADJOINT = 48
 PEAK_FP32_VECTOR = 157.3e12        # MI355X published FP32 vector peak
 PEAK_FP64_VECTOR = 78.6e12         # MI355X published FP64 vector peak
 HBM_PEAK = 8.0e12
@@ -85,7 +91,7 @@ def peak_probe():
             rec["tflops"] = 2.0 * rate / 1e12
         if m == 4:
             rec["pairs_per_s"] = rate
-            rec["tflops_at_36_flop_per_pair"] = 36.0 * rate / 1e12
+            rec["tflops_at_40_flop_per_pair"] = FLOP_PER_USEFUL_PAIR * rate / 1e12
         out[names[m]] = rec
         print(f"[probe] {names[m]}: {rec}", file=sys.stderr, flush=True)
     print(json.dumps({"peak_probe": out, "published_fp32_tflops": PEAK_FP32_VECTOR / 1e12}),
@@ -234,10 +240,13 @@ def main():
         api.slice_field_backward(bb, 0, S, G, grad_weight, grad_nodes)
         return bb
 
+    bwd_acc = {"ms": 0.0, "n": 0}
+
     def timed(fn, k):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         field_ms = 0.0
+        bwd_acc["ms"], bwd_acc["n"] = 0.0, 0
         for key in stage_acc:
             stage_acc[key] = 0.0 if key != "n" else 0
         bin_events.clear()
@@ -252,6 +261,9 @@ def main():
             stage_acc["field"] += inf["last_field_ms"]
             stage_acc["contours"] += inf["last_contour_ms"]
             stage_acc["n"] += 1
+            if inf["last_backward_ms"] >= 0:
+                bwd_acc["ms"] += inf["last_backward_ms"]
+                bwd_acc["n"] += 1
             print(f"[bench] step {i + 1}/{k} done", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / k, field_ms / k
@@ -268,8 +280,10 @@ def main():
               "ms_per_slab": {key: v / n_slabs for key, v in stages.items()},
               "n_slabs": n_slabs}
     t_fb = None
+    bwd_ms = None
     if not args.no_backward:
         t_fb, _ = timed(fwd_bwd_step, args.steps)
+        bwd_ms = bwd_acc["ms"] / bwd_acc["n"] if bwd_acc["n"] else None
 
     # sub-pixel contours and chains of every plane of the last forward step's
     # field (the step after the path's contours), timed with events
@@ -348,16 +362,46 @@ def main():
     peak = PEAK_FP64_VECTOR if dtype == torch.float64 else PEAK_FP32_VECTOR
     field_s = field_ms * 1e-3
     achieved = useful * FLOP_PER_USEFUL_PAIR / field_s if field_s > 0 else None
-    traffic = None
+    # HBM bytes per launch from the committed counter summary, for the kernels
+    # whose source has not changed since
+    traffic = {}
     tpath = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
     if os.path.exists(tpath):
         try:
             from paper_2101_05031_amd import build as B
             rec = json.load(open(tpath))
-            if rec.get("kernel_hash") == B.kernel_hash("field"):
-                traffic = rec.get("bytes_per_launch")
+            for stage, r in rec.get("stages", {}).items():
+                if r.get("kernel_hash") == B.kernel_hash(stage):
+                    traffic[stage] = r.get("bytes_per_step")
         except Exception:
-            traffic = None
+            traffic = {}
+    # binning and contours: algorithmic bytes of the measurement contract per
+    # step, over the stages' device time, against the HBM peak
+    nb = len(lat.edges)
+    n_slabs_tot = (S + info["slab"] - 1) // info["slab"]
+    ms_step = stages["ms_per_step"]
+    bin_ms = ms_step["lattice_bin"] + ms_step["group_bin"]
+    bin_bytes = (12 * nb + 12 * lat.n_nodes + 32 * active_strut_slabs(lat, grid, info["slab"])
+                 + 4 * info["total_pairs"] + 4 * n_slabs_tot * (info["tiles_x"] * info["tiles_y"] + 1))
+    # contours read the binary image (1 bit per pixel), write its row-major
+    # copy, 16 bytes per segment and the per-plane offsets
+    img_bytes = S * H * W / 8
+    cont_bytes = 2 * img_bytes + 16 * total + 8 * (S + 1)
+    cont_ms = ms_step["contours"]
+
+    def hbm(alg_bytes, ms, stage):
+        return {"bound": "hbm", "achieved": alg_bytes / (ms * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s", "frac": alg_bytes / (ms * 1e-3) / HBM_PEAK, "alg_bytes": alg_bytes,
+                "ms_per_step": ms, "traffic": traffic.get(stage)}
+
+    adjoint = None
+    if bwd_ms:
+        a_flops = useful * FLOP_PER_USEFUL_PAIR_ADJOINT / (bwd_ms * 1e-3)
+        adjoint = {"bound": "alu", "kernel": "k_backward32 (adjoint)", "achieved": a_flops / 1e12,
+                   "peak": peak / 1e12, "unit": "TFLOP/s", "frac": a_flops / peak,
+                   "ms_per_launch": bwd_ms, "flop_per_useful_pair": FLOP_PER_USEFUL_PAIR_ADJOINT,
+                   "vs_field_launch": bwd_ms / field_ms if field_ms > 0 else None,
+                   "traffic": traffic.get("backward")}
     out = {
         "metric": "pixel-strut field evals/s (useful pairs) and slices/s at 1M struts; "
                   "fwd+bwd/fwd time ratio",
@@ -412,10 +456,13 @@ def main():
             # the same with every evaluated pair counted (counter view)
             "frac_executed": (None if field_s <= 0 else
                               stats["candidates"] * FLOP_PER_USEFUL_PAIR / field_s / peak),
-            "traffic": traffic,
+            "traffic": traffic.get("field"),
             "field_ms_per_launch": field_ms,
             "flop_per_useful_pair": FLOP_PER_USEFUL_PAIR,
             "inner_loop": inner,
+            "adjoint": adjoint,
+            "binning": hbm(bin_bytes, bin_ms, "binning") if bin_ms > 0 else None,
+            "contours": hbm(cont_bytes, cont_ms, "contours") if cont_ms > 0 else None,
         },
     }
     if cpu is not None:
@@ -457,6 +504,34 @@ def _oracle_strip(task):
     return count[0]
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def active_strut_slabs(lat, grid, slab: int) -> int:
+    """Sum over slabs of the struts whose support meets the slab (what the
+    slab windows read), from the struts' z extents widened by R."""
+    n = np.asarray(lat.nodes, dtype=np.float64)
+    e = np.asarray(lat.edges)
+    live = (np.asarray(lat.weight) != 0) & (e[:, 0] != e[:, 1])
+    R = np.asarray(lat.support, dtype=np.float64)[live] if lat.support is not None else lat.R
+    za, zb = n[e[live, 0], 2], n[e[live, 1], 2]
+    lo, hi = np.minimum(za, zb) - R, np.maximum(za, zb) + R
+    n_slabs = (grid.n_slices + slab - 1) // slab
+    h = grid.dz * slab
+    s0 = np.clip(np.floor((lo - grid.z0) / h), 0, n_slabs - 1)
+    s1 = np.clip(np.floor((hi - grid.z0) / h), 0, n_slabs - 1)
+    inside = (hi >= grid.z0) & (lo <= grid.z0 + grid.dz * grid.n_slices)
+    return int(np.sum((s1 - s0 + 1)[inside]))
+
+
 def cpu_baseline(lat, grid, planes: int = 8, strips: int = 8):
     """The FP64 oracle, as it stands, on the host cores: `planes` evenly
     spaced planes of the workload, whole, each split into `strips` row strips,
@@ -476,7 +551,7 @@ def cpu_baseline(lat, grid, planes: int = 8, strips: int = 8):
     if useful == 0:
         raise RuntimeError("cpu_baseline counted no useful pairs")
     return {"value": useful / dt, "unit": "pixel*strut evals/s", "cores": nproc,
-            "kind": "oracle",
+            "kind": "oracle", "host_cpus": os.cpu_count(), "cpu_model": cpu_model(),
             "per_core": useful / dt / nproc,
             "sample": f"planes {ks}, whole {grid.W}x{grid.H} each, in {len(tasks)} row strips over "
                       f"{nproc} worker processes ({useful} useful pairs, {dt:.1f} s wall, numpy "

@@ -134,6 +134,10 @@ typedef struct lsl_bins_info {
                                when 7 dz |d| <= R^2 / 10 (d the farthest pixel
                                of an 8x8 block from its centre, R the smallest
                                support), else 1; 1 for other kernels          */
+    double last_backward_ms;    /* device time of the adjoint kernels of the last
+                                   slice_field_backward call (HIP events around
+                                   them on its stream, waited for here); -1 if
+                                   none                                        */
 } lsl_bins_info;
 
 /* ---------------------------------------------------------------------------
@@ -177,11 +181,23 @@ lsl_status lattice_bin(const lsl_lattice* lattice, const lsl_grid* grid,
 lsl_status lattice_bins_free(lattice_bins* bins);
 
 /* Returns every cached device buffer to the device (hipFree, after
- * synchronising each device that holds some).  *cached_bytes (host,
- * nullable) receives the bytes the cache held.  Setting LSL_NO_CACHE=1 in
- * the environment before the first call disables the cache: buffers are
- * then allocated and freed directly. */
+ * synchronising each device that holds some) and releases the cached
+ * executable graphs of slice_batch (after their last launches complete).
+ * *cached_bytes (host, nullable) receives the bytes the buffer cache held.
+ * Setting LSL_NO_CACHE=1 in the environment before the first call disables
+ * the buffer cache: buffers are then allocated and freed directly. */
 lsl_status lsl_cache_trim(int64_t* cached_bytes);
+
+/* slice_batch runs each slab group as three HIP graphs (work queue, field,
+ * image + contours) through one cache of executable graphs per process,
+ * shared by every handle: a call records its launches and updates a cached
+ * executable graph of the same launch shape (Sec. 6.4: layers differ only
+ * in how much work they carry), instantiating one only for a new shape or
+ * a refused update.  Two entries per shape serve consecutive groups in
+ * turn, at most 64 entries are kept.  Reports (host pointers, each
+ * nullable) the graphs instantiated and updated since the process started
+ * and the entries held now. */
+lsl_status lsl_graph_cache_stats(int64_t* instantiated, int64_t* updated, int64_t* entries);
 
 /* Sizes and memory use of a handle.  `out` is [host]. */
 lsl_status lattice_bins_info(const lattice_bins* bins, lsl_bins_info* out);

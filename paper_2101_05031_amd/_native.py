@@ -47,7 +47,7 @@ class LslBinsInfo(Structure):
                 ("n_groups", c_int32), ("current_group", c_int32),
                 ("last_field_ms", c_double), ("last_group_bin_ms", c_double),
                 ("last_queue_ms", c_double), ("last_contour_ms", c_double),
-                ("plane_group", c_int32)]
+                ("plane_group", c_int32), ("last_backward_ms", c_double)]
 
 
 class LslSupport(Structure):
@@ -62,6 +62,7 @@ SIGNATURES = {
                               POINTER(c_void_p), c_void_p]),
     "lattice_bins_free": (c_int32, [c_void_p]),
     "lsl_cache_trim": (c_int32, [POINTER(c_int64)]),
+    "lsl_graph_cache_stats": (c_int32, [POINTER(c_int64), POINTER(c_int64), POINTER(c_int64)]),
     "lattice_bins_info": (c_int32, [c_void_p, POINTER(LslBinsInfo)]),
     "lattice_bins_group": (c_int32, [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32),
                                      POINTER(c_int64)]),

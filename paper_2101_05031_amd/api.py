@@ -329,11 +329,19 @@ def probe_valu(mode: int, iters: int = 4096, stream=None) -> dict:
 
 
 def cache_trim() -> int:
-    """Return the library's cached device buffers to the device; returns the
-    bytes the cache held."""
+    """Return the library's cached device buffers to the device and release
+    its cached executable graphs; returns the bytes the buffer cache held."""
     n = c_int64()
     N.check(N.lib().lsl_cache_trim(byref(n)), "lsl_cache_trim")
     return n.value
+
+
+def graph_cache_stats() -> dict:
+    """slice_batch's executable-graph cache: graphs instantiated and updated
+    since the process started, and the entries held now."""
+    i, u, n = c_int64(), c_int64(), c_int64()
+    N.check(N.lib().lsl_graph_cache_stats(byref(i), byref(u), byref(n)), "lsl_graph_cache_stats")
+    return {"instantiated": i.value, "updated": u.value, "entries": n.value}
 
 
 def lattice_support(nodes, edges, weight, print_dir=(0.0, 0.0, 1.0), grad: bool = False,

@@ -47,8 +47,10 @@ def _compile(src: str, out_dir: str) -> str:
 
 
 KERNEL_SOURCES = {
-    "field": ["field_block.hpp", "batch.hip", "common.hpp", "kernels.hpp"],
-    "backward": ["backward.hip", "common.hpp"],
+    "field": ["field_q32.hpp", "field_block.hpp", "batch.hip", "common.hpp", "kernels.hpp"],
+    "backward": ["backward.hip", "field_q32.hpp", "common.hpp", "kernels.hpp"],
+    "binning": ["prep.hip", "bin.hip", "primitives.hip", "common.hpp", "kernels.hpp"],
+    "contours": ["contours.hip", "common.hpp", "kernels.hpp"],
 }
 
 

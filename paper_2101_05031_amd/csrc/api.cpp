@@ -159,6 +159,121 @@ struct Group {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Executable graphs of slice_batch, shared by every handle of the process.
+// A call captures its launches afresh (a cheap recording) and brings a cached
+// executable graph of the same launch shape up to date with
+// hipGraphExecUpdate; a new one is instantiated only when no entry of that
+// shape exists or the update is refused (the recorded launches differ in
+// kind or number).  Consecutive slab groups of a call use two entries of a
+// shape in turn, and an entry's previous launch is waited for before it is
+// updated, so an executable graph is never changed while the device may run
+// it.  At most kCap entries are kept (the least recently used goes first);
+// lsl_cache_trim releases them all.
+// ---------------------------------------------------------------------------
+class GraphCache {
+  public:
+    static GraphCache& get() {
+        static GraphCache* c = new GraphCache();     // never destroyed: no teardown at exit
+        return *c;
+    }
+    // Launches `graph` (captured, not instantiated; the caller keeps
+    // ownership) on `st` through the entry for `key` on the current device.
+    lsl_status launch(const std::vector<unsigned char>& key, hipGraph_t graph, hipStream_t st) {
+        int dev = 0;
+        LSL_HIP(hipGetDevice(&dev));
+        std::lock_guard<std::mutex> lk(mu_);
+        Entry* ent = nullptr;
+        for (auto& e : e_)
+            if (e.dev == dev && e.key == key) ent = &e;
+        if (ent) {
+            LSL_HIP(hipEventSynchronize(ent->done));
+            hipGraphNode_t bad = nullptr;
+            hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+            if (hipGraphExecUpdate(ent->exec, graph, &bad, &res) == hipSuccess &&
+                res == hipGraphExecUpdateSuccess) {
+                ++n_update_;
+            } else {
+                hipGetLastError();
+                hipGraphExecDestroy(ent->exec);
+                ent->exec = nullptr;
+            }
+        } else {
+            if (e_.size() >= kCap) {
+                size_t old = 0;
+                for (size_t i = 1; i < e_.size(); ++i)
+                    if (e_[i].use < e_[old].use) old = i;
+                LSL_TRY(release(e_[old]));
+                e_.erase(e_.begin() + (std::ptrdiff_t)old);
+            }
+            Entry ne{};
+            ne.key = key;
+            ne.dev = dev;
+            LSL_HIP(hipEventCreateWithFlags(&ne.done, hipEventDisableTiming));
+            e_.push_back(ne);
+            ent = &e_.back();
+        }
+        if (!ent->exec) {
+            const hipError_t ie = hipGraphInstantiate(&ent->exec, graph, nullptr, nullptr, 0);
+            if (ie != hipSuccess) {
+                ent->exec = nullptr;
+                hipGetLastError();
+                set_error(std::string("slice_batch: graph instantiation failed: ") +
+                          hipGetErrorString(ie));
+                return LSL_EDEVICE;
+            }
+            ++n_instantiate_;
+        }
+        ent->use = ++tick_;
+        LSL_HIP(hipGraphLaunch(ent->exec, st));
+        LSL_HIP(hipEventRecord(ent->done, st));
+        return LSL_OK;
+    }
+    // Waits for and releases every entry (each on its own device).
+    lsl_status trim() {
+        std::lock_guard<std::mutex> lk(mu_);
+        int cur = 0;
+        LSL_HIP(hipGetDevice(&cur));
+        lsl_status st = LSL_OK;
+        for (auto& e : e_) {
+            const lsl_status s = release(e);
+            if (st == LSL_OK) st = s;
+        }
+        e_.clear();
+        hipSetDevice(cur);
+        return st;
+    }
+    void stats(int64_t* inst, int64_t* upd, int64_t* n) {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (inst) *inst = n_instantiate_;
+        if (upd) *upd = n_update_;
+        if (n) *n = (int64_t)e_.size();
+    }
+
+  private:
+    struct Entry {
+        std::vector<unsigned char> key;
+        int dev;
+        hipGraphExec_t exec;
+        hipEvent_t done;            // recorded after the entry's last launch
+        uint64_t use;
+    };
+    static lsl_status release(Entry& e) {
+        LSL_HIP(hipSetDevice(e.dev));
+        if (e.done) LSL_HIP(hipEventSynchronize(e.done));
+        if (e.exec) hipGraphExecDestroy(e.exec);
+        if (e.done) hipEventDestroy(e.done);
+        e.exec = nullptr;
+        e.done = nullptr;
+        return LSL_OK;
+    }
+    static constexpr size_t kCap = 64;
+    std::mutex mu_;
+    std::vector<Entry> e_;
+    uint64_t tick_ = 0;
+    int64_t n_instantiate_ = 0, n_update_ = 0;
+};
+
 struct lattice_bins {
     int dtype = LSL_F32;
     int64_t n_nodes = 0, n_edges = 0;
@@ -228,27 +343,29 @@ struct lattice_bins {
     std::vector<std::pair<void*, size_t>> allocs;
     int64_t dev_bytes = 0, peak_bytes = 0;
 
-    // persistent path: captured graphs keyed by their launch arguments
-    struct GraphEntry {
-        std::vector<unsigned char> key;
-        hipGraphExec_t exec[3];     // queue build | persistent field | image + contours
-    };
     // per slab group of a slice_batch call, on the caller's stream: before and
     // after binning the group, after each of the three graphs
     struct StageEvents {
         hipEvent_t ev[5];
     };
     std::vector<StageEvents> stage_events;
+    // around each slab group's adjoint kernel of the last slice_field_backward
+    struct EvPair {
+        hipEvent_t ev[2];
+    };
+    std::vector<EvPair> back_events;
+    size_t n_back = 0;
     double last_field_ms = -1.0, last_group_bin_ms = -1.0, last_queue_ms = -1.0,
            last_contour_ms = -1.0;
     bool queue_in_alt = false;      // the sorted work queue is in the alternate buffer
-    std::vector<GraphEntry> graphs;
 
     ~lattice_bins() {
         hipDeviceSynchronize();
-        drop_graphs();
         for (auto& se : stage_events)
             for (auto& e : se.ev)
+                if (e) hipEventDestroy(e);
+        for (auto& bp : back_events)
+            for (auto& e : bp.ev)
                 if (e) hipEventDestroy(e);
         for (auto& a : allocs) DeviceCache::get().release(a.first, a.second);
     }
@@ -287,10 +404,9 @@ struct lattice_bins {
     size_t esize() const { return dtype == LSL_F64 ? 8 : 4; }
     // Grows library scratch *p (capacity *cap elements) to `need` elements:
     // waits for the work queued on `st` (it may still use the old buffer),
-    // releases it and allocates the new one.  `in_graphs`: the buffer's address
-    // is baked into captured graphs, which are then dropped.
+    // releases it and allocates the new one.
     template <typename T>
-    lsl_status grow(T** p, size_t* cap, size_t need, hipStream_t st, bool in_graphs) {
+    lsl_status grow(T** p, size_t* cap, size_t need, hipStream_t st) {
         if (need <= *cap) return LSL_OK;
         LSL_HIP(hipStreamSynchronize(st));
         release(*p);
@@ -298,14 +414,7 @@ struct lattice_bins {
         *cap = 0;
         LSL_TRY(alloc_t(p, need));
         *cap = need;
-        if (in_graphs) drop_graphs();
         return LSL_OK;
-    }
-    void drop_graphs() {
-        for (auto& g : graphs)
-            for (auto& x : g.exec)
-                if (x) hipGraphExecDestroy(x);
-        graphs.clear();
     }
 };
 
@@ -554,7 +663,7 @@ size_t blk_words(const lattice_bins* b, int32_t nk) {
 
 // library scratch for the block-major binary images of nk planes
 lsl_status ensure_cbits(lattice_bins* b, int32_t nk, hipStream_t st) {
-    return b->grow(&b->cbits, &b->cbits_elems, blk_words(b, nk), st, true);
+    return b->grow(&b->cbits, &b->cbits_elems, blk_words(b, nk), st);
 }
 
 }  // namespace
@@ -925,8 +1034,15 @@ lsl_status lattice_support(const lsl_lattice* L, const double* print_dir, lsl_su
 }
 
 lsl_status lsl_cache_trim(int64_t* cached_bytes) {
+    set_error("");
     if (cached_bytes) *cached_bytes = (int64_t)DeviceCache::get().cached();
+    const lsl_status gs = GraphCache::get().trim();
     DeviceCache::get().trim();
+    return gs;
+}
+
+lsl_status lsl_graph_cache_stats(int64_t* instantiated, int64_t* updated, int64_t* entries) {
+    GraphCache::get().stats(instantiated, updated, entries);
     return LSL_OK;
 }
 
@@ -953,6 +1069,21 @@ lsl_status lattice_bins_info(const lattice_bins* b, lsl_bins_info* o) {
     o->last_contour_ms = b->last_contour_ms;
     o->plane_group =
         (b->dtype == LSL_F32 && b->kernel == LSL_KERNEL_QUARTIC && !b->plane_ref) ? 8 : 1;
+    o->last_backward_ms = -1.0;
+    if (b->n_back > 0 && hipEventSynchronize(b->back_events[b->n_back - 1].ev[1]) == hipSuccess) {
+        double acc = 0.0;
+        bool ok = true;
+        for (size_t i = 0; i < b->n_back && ok; ++i) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, b->back_events[i].ev[0], b->back_events[i].ev[1]) ==
+                hipSuccess)
+                acc += ms;
+            else
+                ok = false;
+        }
+        if (ok) o->last_backward_ms = acc;
+    }
+    hipGetLastError();
     return LSL_OK;
 }
 
@@ -1058,8 +1189,7 @@ lsl_status slice_contours(const lattice_bins* cb, int32_t nk, const void* field,
     LSL_CHECK(capacity == 0 || segs != nullptr, "segs is NULL");
     lattice_bins* b = const_cast<lattice_bins*>(cb);   // scratch only
     hipStream_t st = S(stream);
-    LSL_TRY(b->grow(&b->ctmp, &b->ctmp_elems, contour_tmp_elems(nk, b->grid.W, b->grid.H), st,
-                    true));
+    LSL_TRY(b->grow(&b->ctmp, &b->ctmp_elems, contour_tmp_elems(nk, b->grid.W, b->grid.H), st));
     LSL_TRY(ensure_cbits(b, nk, st));
     // the binary images (block-major), then marching squares on them
     const uint64_t* img = (const uint64_t*)b->cbits;
@@ -1095,8 +1225,7 @@ lsl_status slice_polylines(const lattice_bins* cb, int32_t nk, const void* field
     LSL_CHECK((chain == nullptr) == (rank == nullptr), "chain and rank go together");
     lattice_bins* b = const_cast<lattice_bins*>(cb);   // scratch only
     hipStream_t st = S(stream);
-    LSL_TRY(b->grow(&b->ctmp, &b->ctmp_elems, contour_tmp_elems(nk, b->grid.W, b->grid.H), st,
-                    true));
+    LSL_TRY(b->grow(&b->ctmp, &b->ctmp_elems, contour_tmp_elems(nk, b->grid.W, b->grid.H), st));
     LSL_TRY(ensure_cbits(b, nk, st));
     const uint64_t* img = (const uint64_t*)b->cbits;
     LSL_TRY(launch_bits_blk(b->dtype, field, nk, b->grid.W, b->grid.H, b->C,
@@ -1119,8 +1248,7 @@ lsl_status slice_polylines(const lattice_bins* cb, int32_t nk, const void* field
     for (int32_t k = 0; k < nk; ++k) longest = std::max<int64_t>(longest, h_off[k + 1] - h_off[k]);
     int32_t rounds = 1;
     while (((int64_t)1 << (rounds - 1)) < longest) ++rounds;
-    LSL_TRY(b->grow(&b->pscratch, &b->pscratch_elems, polyline_scratch_elems((uint64_t)tot), st,
-                    false));
+    LSL_TRY(b->grow(&b->pscratch, &b->pscratch_elems, polyline_scratch_elems((uint64_t)tot), st));
     return launch_polylines(img, field, b->dtype, b->C, nk, b->grid.W, b->grid.H, b->ctmp, offsets,
                             (uint64_t)tot, rounds, segs, b->pscratch, chain, rank, st);
 }
@@ -1147,7 +1275,7 @@ lsl_status slice_occupancy_loss(const lattice_bins* cb, int32_t nk, const void* 
     hipStream_t st = S(stream);
     const size_t n = (size_t)nk * (size_t)b->grid.W * (size_t)b->grid.H;
     const size_t need = occupancy_blocks(n);
-    LSL_TRY(b->grow(&b->dscratch, &b->dscratch_elems, need, st, false));
+    LSL_TRY(b->grow(&b->dscratch, &b->dscratch_elems, need, st));
     return launch_occupancy_loss(b->dtype, field, target, n, b->C, tau, grad_field, loss,
                                  b->dscratch, st);
 }
@@ -1187,7 +1315,7 @@ lsl_status slice_density_loss(const lattice_bins* cb, int32_t nk, const void* fi
     DensityArgs a{};
     LSL_TRY(density_plan(nk, b->grid.W, b->grid.H, vx, vy, vz, &a));
     const size_t need = density_scratch_elems(a);
-    LSL_TRY(b->grow(&b->dscratch, &b->dscratch_elems, need, st, false));
+    LSL_TRY(b->grow(&b->dscratch, &b->dscratch_elems, need, st));
     return launch_density_loss(b->dtype, a, field, b->C, tau, target, soft_density, grad_field,
                                loss, b->dscratch, st);
 }
@@ -1258,10 +1386,11 @@ BackArgs back_args(const lattice_bins* b, int g, int32_t k0, int32_t nk, int s_l
     return a;
 }
 
-struct BatchKey {
-    int32_t g, k0, nk, first;
-    void *field, *bits, *segs, *offsets;
-    int64_t capacity;
+// What decides the kernels a slab group's graphs record (the cached graphs
+// of one shape differ only in launch arguments).
+struct GraphShape {
+    int32_t dtype, kernel, strut_R, plane_ref, slab, tile, phase;
+    int32_t field, bits, segs, slot;
 };
 
 // Enqueues one phase of a group's part of slice_batch on `st`:
@@ -1321,31 +1450,27 @@ lsl_status batch_group_work(lattice_bins* b, int g, int32_t k0, int32_t nk, int 
     return LSL_OK;
 }
 
-lsl_status capture(hipStream_t cap, hipGraphExec_t* exec, const std::function<lsl_status(hipStream_t)>& fn) {
-    *exec = nullptr;
+// Records fn's launches on the capture stream `cap` into *graph (owned by
+// the caller afterwards).
+lsl_status capture(hipStream_t cap, hipGraph_t* graph,
+                   const std::function<lsl_status(hipStream_t)>& fn) {
+    *graph = nullptr;
     LSL_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
     lsl_status ws = fn(cap);
-    hipGraph_t graph = nullptr;
-    hipError_t ce = hipStreamEndCapture(cap, &graph);
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(cap, &g);
     if (ws != LSL_OK) {
-        if (graph) hipGraphDestroy(graph);
+        if (g) hipGraphDestroy(g);
         hipGetLastError();
         return ws;
     }
-    if (ce != hipSuccess || !graph) {
-        if (graph) hipGraphDestroy(graph);
+    if (ce != hipSuccess || !g) {
+        if (g) hipGraphDestroy(g);
         hipGetLastError();
         set_error(std::string("slice_batch: graph capture failed: ") + hipGetErrorString(ce));
         return LSL_EDEVICE;
     }
-    hipError_t ie = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
-    if (ie != hipSuccess) {
-        *exec = nullptr;
-        hipGetLastError();
-        set_error(std::string("slice_batch: graph instantiation failed: ") + hipGetErrorString(ie));
-        return LSL_EDEVICE;
-    }
+    *graph = g;
     return LSL_OK;
 }
 
@@ -1362,6 +1487,7 @@ lsl_status slice_field_backward(lattice_bins* b, int32_t k0, int32_t nk, const v
     LSL_CHECK(b->kernel == LSL_KERNEL_QUARTIC,
               "slice_field_backward covers the quartic kernel only");
     hipStream_t st = S(stream);
+    b->n_back = 0;
     if (!b->acc) LSL_TRY(b->alloc_t(&b->acc, (size_t)std::max<uint32_t>(b->n_binned, 1) * 7));
     if (!b->partial) LSL_TRY(b->alloc(&b->partial, b->cap_pairs * 9 * b->esize()));
     if (!b->emi) LSL_TRY(b->alloc_t(&b->emi, b->cap_pairs));
@@ -1391,7 +1517,15 @@ lsl_status slice_field_backward(lattice_bins* b, int32_t k0, int32_t nk, const v
                 b->emi_group = g;
             }
             BackArgs a = back_args(b, g, k0, nk, s_lo, s_hi, grad_field);
+            if (b->back_events.size() <= b->n_back) {
+                lattice_bins::EvPair bp{};
+                for (auto& e : bp.ev) LSL_HIP(hipEventCreate(&e));
+                b->back_events.push_back(bp);
+            }
+            hipEvent_t* bev = b->back_events[b->n_back++].ev;
+            LSL_HIP(hipEventRecord(bev[0], st));
             LSL_TRY(launch_backward(b->dtype, a, st));
+            LSL_HIP(hipEventRecord(bev[1], st));
             ReduceArgs r{};
             r.partial = b->partial;
             r.active = b->active[b->cur_buf];
@@ -1444,10 +1578,9 @@ lsl_status slice_batch(lattice_bins* b, int32_t k0, int32_t nk, void* field, uin
         b->queue_cap = 0;
         LSL_TRY(b->alloc_t(&b->queue_buf, 4 * max_items + 64 + radix_tmp_elems(max_items)));
         b->queue_cap = max_items;
-        b->drop_graphs();
     }
     LSL_TRY(b->grow(&b->ctmp, &b->ctmp_elems,
-                    contour_tmp_elems((int32_t)max_planes, b->grid.W, b->grid.H), st, true));
+                    contour_tmp_elems((int32_t)max_planes, b->grid.W, b->grid.H), st));
     LSL_TRY(ensure_cbits(b, (int32_t)max_planes, st));
     uint32_t* counter = b->queue_buf + 4 * b->queue_cap;
     unsigned long long* base = (unsigned long long*)(counter + 32);
@@ -1474,40 +1607,33 @@ lsl_status slice_batch(lattice_bins* b, int32_t k0, int32_t nk, void* field, uin
         hipEvent_t* ev = b->stage_events[n_call_groups++].ev;
         LSL_HIP(hipEventRecord(ev[0], st));
         LSL_TRY(ensure_group(b, g, st));
-        LSL_HIP(hipEventRecord(ev[1], st));
-        BatchKey key{g, k0, nk, 0, field, bits, segs, offsets, capacity};
-        std::vector<unsigned char> kb((unsigned char*)&key, (unsigned char*)&key + sizeof(key));
-        lattice_bins::GraphEntry* ent = nullptr;
-        for (auto& ge : b->graphs)
-            if (ge.key == kb) ent = &ge;
-        if (!ent) {
-            if (!cap) LSL_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-            lattice_bins::GraphEntry ne{};
-            ne.key = kb;
-            for (int ph = 0; ph < 3; ++ph) {
-                lsl_status cs = capture(cap, &ne.exec[ph], [&](hipStream_t cs_st) {
-                    return batch_group_work(b, g, k0, nk, s_lo, s_hi, field, bits, segs,
-                                            capacity, offsets, ph, cs_st);
-                });
-                if (cs != LSL_OK) {
-                    for (auto& x : ne.exec)
-                        if (x) hipGraphExecDestroy(x);
-                    if (cap) hipStreamDestroy(cap);
-                    return cs;
-                }
-            }
-            b->graphs.push_back(ne);
-            ent = &b->graphs.back();
-            // capturing took host time: restart the group's binning stage here
-            LSL_HIP(hipEventRecord(ev[1], st));
+        // the group's three phases, recorded on the capture stream, then
+        // launched through the process's graph cache: the launch shape (what
+        // decides which kernels run) and which of the shape's two entries
+        // this group takes
+        if (!cap) LSL_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hipGraph_t gr[3] = {nullptr, nullptr, nullptr};
+        lsl_status cs = LSL_OK;
+        for (int ph = 0; ph < 3 && cs == LSL_OK; ++ph)
+            cs = capture(cap, &gr[ph], [&](hipStream_t cs_st) {
+                return batch_group_work(b, g, k0, nk, s_lo, s_hi, field, bits, segs, capacity,
+                                        offsets, ph, cs_st);
+            });
+        // the captures took host time: the group's binning stage ends here
+        if (cs == LSL_OK && hipEventRecord(ev[1], st) != hipSuccess) cs = LSL_EDEVICE;
+        for (int ph = 0; ph < 3 && cs == LSL_OK; ++ph) {
+            GraphShape shape{b->dtype,   b->kernel,        b->strut_R ? 1 : 0,
+                             b->plane_ref ? 1 : 0, b->slab, b->tile, ph,
+                             field ? 1 : 0, bits ? 1 : 0, capacity > 0 ? 1 : 0,
+                             (int32_t)((n_call_groups - 1) & 1)};
+            std::vector<unsigned char> key((unsigned char*)&shape,
+                                           (unsigned char*)&shape + sizeof(shape));
+            cs = GraphCache::get().launch(key, gr[ph], st);
+            if (cs == LSL_OK && hipEventRecord(ev[2 + ph], st) != hipSuccess) cs = LSL_EDEVICE;
         }
-        LSL_HIP(hipGraphLaunch(ent->exec[0], st));
-        LSL_HIP(hipEventRecord(ev[2], st));
-        LSL_HIP(hipGraphLaunch(ent->exec[1], st));
-        LSL_HIP(hipEventRecord(ev[3], st));
-        LSL_HIP(hipGraphLaunch(ent->exec[2], st));
-        LSL_HIP(hipEventRecord(ev[4], st));
-        return LSL_OK;
+        for (auto& x : gr)
+            if (x) hipGraphDestroy(x);
+        return cs;
     }));
     if (cap) hipStreamDestroy(cap);
     unsigned long long tot = 0;

@@ -119,6 +119,71 @@ __device__ __forceinline__ void comp_add(float g, float& s, float& c) {
     s = sn;
 }
 
+// The terms of one candidate strut (staging lane e, planes `mask`, uniform;
+// E, nD and the planes' G_k its staged values) at the pixel d = (dX, dY) of each plane it
+// reaches, added to the open runs of the planes of the slab that starts at
+// plane kb (reference group gb).
+template <int SZ, bool STATS, bool PLANE_REF>
+__device__ __forceinline__ void add_candidate(const Lds<SZ, PLANE_REF>& L, uint32_t e,
+                                              uint32_t mask, float4 E, float nD, int kb, int gb,
+                                              const float (&Gk)[SZ], float dX, float dY,
+                                              float nd2, bool pix, float (&acc_s)[SZ],
+                                              float (&acc_c)[SZ], float (&run)[SZ],
+                                              int (&open)[SZ], unsigned long long& n_cand,
+                                              unsigned long long& n_useful) {
+    const float du = __builtin_fmaf(dX, E.x, dY * E.y);        // d.u^
+    const float P1 = E.z * du;
+    const float ndd = nd2 * E.w;                                // -|d^|^2
+    float Eg = 0.0f, ar = 0.0f, br = 0.0f;
+    int gcur = -1;
+    for_planes<0, SZ>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        if (!((mask >> k) & 1u)) return;
+        float al, be, H;
+        if constexpr (PLANE_REF) {
+            const float4 P = L.pl[k][e];
+            const float2 M = L.pm[k][e];
+            al = P.x - du;
+            be = P.y - du;
+            H = __builtin_amdgcn_fmed3f(
+                __builtin_fmaf(du, du,
+                               __builtin_fmaf(M.x, dX, __builtin_fmaf(M.y, dY, ndd + P.z))),
+                0.0f, 1.0f);
+        } else {
+            const int g = ((kb + k) >> 3) - gb;
+            if (g != gcur) {
+                const float4 Rg = L.gr[g][e];
+                ar = Rg.x - du;
+                br = Rg.y - du;
+                Eg = __builtin_fmaf(du, du,
+                                    __builtin_fmaf(Rg.z, dX, __builtin_fmaf(Rg.w, dY, ndd)));
+                gcur = g;
+            }
+            const float kap = kappa((kb + k) & 7);
+            al = __builtin_fmaf(kap, nD, ar);
+            be = __builtin_fmaf(kap, nD, br);
+            H = __builtin_amdgcn_fmed3f(__builtin_fmaf(kap, P1, Gk[k] + Eg), 0.0f, 1.0f);
+        }
+        const float h = __builtin_amdgcn_sqrtf(H);
+        const float ca = __builtin_amdgcn_fmed3f(al, -h, h);
+        const float cb = __builtin_amdgcn_fmed3f(be, -h, h);
+        const float s = ca + cb, D = cb - ca;
+        const float s2 = s * s, D2 = D * D;
+        const float A = __builtin_fmaf(D2, -1.0f / 12.0f, __builtin_fmaf(s2, -0.25f, H));
+        const float V = __builtin_fmaf(s2, 1.0f / 12.0f, D2 * (1.0f / 180.0f));
+        const float Q = __builtin_fmaf(A, A, D2 * V);
+        if (STATS) {
+            n_cand += pix ? 1ull : 0ull;
+            n_useful += (pix && D * Q > 0.0f) ? 1ull : 0ull;
+        }
+        run[k] = __builtin_fmaf(D, Q, run[k]);
+        if (++open[k] == kRun) {
+            comp_add(run[k], acc_s[k], acc_c[k]);
+            run[k] = 0.0f;
+            open[k] = 0;
+        }
+    });}
+
 // One wave: the 8x8 block `sub` of tile (tx, ty) over the planes of `slab`
 // in [k0, k0+nk).  PLANE_REF: every plane is its own reference (see above).
 template <int SZ, bool STATS, bool SR, bool PLANE_REF>
@@ -288,58 +353,8 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
             const uint32_t cn = L.cand[j + 1 < n ? j + 1 : j];
             const float4 En = L.e[cn & 63u];
             const float nDn = L.dl[cn & 63u];
-            const float du = __builtin_fmaf(dX, E.x, dY * E.y);        // d.u^
-            const float P1 = E.z * du;
-            const float ndd = nd2 * E.w;                                // -|d^|^2
-            float Eg = 0.0f, ar = 0.0f, br = 0.0f;
-            int gcur = -1;
-            for_planes<0, SZ>([&](auto kc) {
-                constexpr int k = decltype(kc)::value;
-                if (!((mask >> k) & 1u)) return;
-                float al, be, H;
-                if constexpr (PLANE_REF) {
-                    const float4 P = L.pl[k][e];
-                    const float2 M = L.pm[k][e];
-                    al = P.x - du;
-                    be = P.y - du;
-                    H = __builtin_amdgcn_fmed3f(
-                        __builtin_fmaf(du, du,
-                                       __builtin_fmaf(M.x, dX, __builtin_fmaf(M.y, dY, ndd + P.z))),
-                        0.0f, 1.0f);
-                } else {
-                    const int g = ((kb + k) >> 3) - gb;
-                    if (g != gcur) {
-                        const float4 Rg = L.gr[g][e];
-                        ar = Rg.x - du;
-                        br = Rg.y - du;
-                        Eg = __builtin_fmaf(du, du,
-                                            __builtin_fmaf(Rg.z, dX, __builtin_fmaf(Rg.w, dY, ndd)));
-                        gcur = g;
-                    }
-                    const float kap = kappa((kb + k) & 7);
-                    al = __builtin_fmaf(kap, nD, ar);
-                    be = __builtin_fmaf(kap, nD, br);
-                    H = __builtin_amdgcn_fmed3f(__builtin_fmaf(kap, P1, Gk[k] + Eg), 0.0f, 1.0f);
-                }
-                const float h = __builtin_amdgcn_sqrtf(H);
-                const float ca = __builtin_amdgcn_fmed3f(al, -h, h);
-                const float cb = __builtin_amdgcn_fmed3f(be, -h, h);
-                const float s = ca + cb, D = cb - ca;
-                const float s2 = s * s, D2 = D * D;
-                const float A = __builtin_fmaf(D2, -1.0f / 12.0f, __builtin_fmaf(s2, -0.25f, H));
-                const float V = __builtin_fmaf(s2, 1.0f / 12.0f, D2 * (1.0f / 180.0f));
-                const float Q = __builtin_fmaf(A, A, D2 * V);
-                if (STATS) {
-                    n_cand += pix ? 1ull : 0ull;
-                    n_useful += (pix && D * Q > 0.0f) ? 1ull : 0ull;
-                }
-                run[k] = __builtin_fmaf(D, Q, run[k]);
-                if (++open[k] == kRun) {
-                    comp_add(run[k], acc_s[k], acc_c[k]);
-                    run[k] = 0.0f;
-                    open[k] = 0;
-                }
-            });
+            add_candidate<SZ, STATS, PLANE_REF>(L, e, mask, E, nD, kb, gb, Gk, dX, dY, nd2, pix,
+                                                acc_s, acc_c, run, open, n_cand, n_useful);
             c = cn;
             E = En;
             nD = nDn;

@@ -2,7 +2,7 @@
 // and adjoint kernels (diagnostics; not part of the slicing path).  Each
 // mode runs 16 independent chains per lane over a grid of 16 blocks of 256
 // per compute unit and reports the lane operations issued.
-#include "field_block.hpp"
+#include "field_q32.hpp"
 
 namespace lsl {
 namespace {
@@ -47,36 +47,62 @@ __global__ __launch_bounds__(256) void k_probe_f64(double* out, int iters, doubl
     out[gid] = s;
 }
 
-// The field kernel's per-pair sequence alone: 64 staged struts in LDS (as
-// the field kernel stages them), every lane one pixel of an 8x8 block, the
-// terms summed as the field kernel sums them (runs of Group<float>::n).
+// The float32 field kernel's evaluation alone: every wave one 8x8 block, 64
+// struts staged in LDS as the kernel stages them (a slab of 8 planes sharing
+// one reference plane), each a candidate at every plane, the terms formed and
+// summed by the kernel's own code (q32::add_candidate).  The staged values
+// put every pixel inside every strut's support.
 __global__ __launch_bounds__(256) void k_probe_term(float* out, int iters) {
-    __shared__ Stage<float> st[4][kWave];
+    constexpr int SZ = 8;
+    __shared__ q32::Lds<SZ, false> lds[4];
     const int lane = lane_id(), wv = threadIdx.x >> 6;
-    Stage<float> e;
-    e.mx2 = 0.02f * (float)(lane & 7);
-    e.my2 = -0.03f * (float)(lane >> 3);
-    e.ux = 0.6f;
-    e.uy = 0.48f;
-    e.ntc = -0.5f - 0.01f * (float)lane;
-    e.nbtc = 1.5f + 0.01f * (float)lane;
-    e.H0 = 1.9f - 0.005f * (float)lane;
-    e.wq = 0.2f;
-    st[wv][lane] = e;
-    __syncthreads();
+    q32::Lds<SZ, false>& L = lds[wv];
+    for (int k = 0; k < SZ; ++k) L.pg[k][lane] = 0.6f - 0.01f * (float)k - 0.002f * (float)lane;
+    L.gr[0][lane] = make_float4(-0.3f - 0.004f * (float)lane, 0.8f + 0.004f * (float)lane, 0.02f,
+                                -0.03f);
+    L.e[lane] = make_float4(0.35f, 0.28f, 0.01f, 0.44f);
+    L.dl[lane] = -0.01f;
+    L.cand[lane] = (uint32_t)lane | (0xffu << 8);
+    __builtin_amdgcn_wave_barrier();
     const float dX = 0.05f * ((float)(lane & 7) - 3.5f), dY = 0.05f * ((float)(lane >> 3) - 3.5f);
-    const float d2 = dX * dX + dY * dY;
-    float s = 0.0f, c = 0.0f;
-    constexpr int G = fieldk::Group<float>::n;
-    static_assert(kWave % G == 0, "runs must tile the staged list");
-    for (int i = 0; i < iters; ++i)
-        for (int j = 0; j < kWave; j += G) {
-            float g = fieldk::eval_term<float>(st[wv][j], dX, dY, d2);
-#pragma unroll
-            for (int q = 1; q < G; ++q) g += fieldk::eval_term<float>(st[wv][j + q], dX, dY, d2);
-            fieldk::comp_add(g, s, c);
+    const float nd2 = -(dX * dX + dY * dY);
+    float acc_s[SZ], acc_c[SZ], run[SZ];
+    int open[SZ];
+    q32::for_planes<0, SZ>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        acc_s[k] = acc_c[k] = run[k] = 0.0f;
+        open[k] = 0;
+    });
+    unsigned long long n_cand = 0, n_useful = 0;
+    for (int i = 0; i < iters; ++i) {
+        uint32_t c = L.cand[0];
+        float4 E = L.e[c & 63u];
+        float nD = L.dl[c & 63u];
+#pragma unroll 1
+        for (int j = 0; j < kWave; ++j) {
+            const uint32_t e = c & 63u;
+            const uint32_t mask = __builtin_amdgcn_readfirstlane(c >> 8);
+            float Gk[SZ];
+            q32::for_planes<0, SZ>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                Gk[k] = L.pg[k][e];
+            });
+            const uint32_t cn = L.cand[j + 1 < kWave ? j + 1 : j];
+            const float4 En = L.e[cn & 63u];
+            const float nDn = L.dl[cn & 63u];
+            q32::add_candidate<SZ, false, false>(L, e, mask, E, nD, 0, 0, Gk, dX, dY, nd2, true,
+                                                 acc_s, acc_c, run, open, n_cand, n_useful);
+            c = cn;
+            E = En;
+            nD = nDn;
         }
-    out[blockIdx.x * 256 + threadIdx.x] = s + c;
+    }
+    float t = 0.0f;
+    q32::for_planes<0, SZ>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        t += acc_s[k] + acc_c[k] + run[k];
+    });
+    out[blockIdx.x * 256 + threadIdx.x] = t;
 }
 
 }  // namespace
@@ -134,7 +160,8 @@ extern "C" lsl_status lsl_probe_valu(int32_t mode, int32_t iters, float* ms, dou
         return LSL_EDEVICE;
     }
     *ms = t;
-    // mode 4: one pair = one term; the others: one lane operation per chain step
-    *lane_ops = (double)n * (double)iters * (mode == 4 ? (double)kWave : (double)kChains);
+    // mode 4: one pair = one term (64 struts x 8 planes per lane and
+    // iteration); the others: one lane operation per chain step
+    *lane_ops = (double)n * (double)iters * (mode == 4 ? (double)kWave * 8.0 : (double)kChains);
     return LSL_OK;
 }

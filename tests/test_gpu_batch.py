@@ -53,6 +53,49 @@ def test_batch_equals_plain_path(max_pairs):
     assert info["last_queue_ms"] >= 0 and info["last_group_bin_ms"] >= 0
 
 
+def test_graphs_reused_across_calls_handles_and_groups():
+    """slice_batch records each call's launches and updates cached executable
+    graphs of the same launch shape: a many-group call takes at most two
+    entries per phase of its shape, later calls on new handles instantiate
+    nothing, and every replay gives the plain path's field and segments
+    bitwise."""
+    lat, grid = uneven_case()
+    S = grid.n_slices
+    b1 = bin_lattice(lat, grid, max_pairs=15000)
+    n_groups = b1.info()["n_groups"]
+    assert n_groups >= 4
+    ref = api.slice_field(b1, 0, S)
+    rsegs, roff, _ = api.slice_contours(b1, ref)
+    cap = len(rsegs) + 16
+    field = torch.empty_like(ref)
+    segs = torch.empty((cap, 4), dtype=torch.float32, device="cuda")
+    offs = torch.empty(S + 1, dtype=torch.int64, device="cuda")
+
+    def run(b):
+        field.fill_(-1.0)
+        st, total, _, _ = api.slice_batch(b, 0, S, field=field, capacity=cap, segs=segs,
+                                          offsets=offs)
+        assert st == N.LSL_OK and total == len(rsegs)
+        assert torch.equal(field.view(torch.int32), ref.view(torch.int32))
+        assert torch.equal(offs, roff) and torch.equal(segs[:total], rsegs)
+
+    s0 = api.graph_cache_stats()
+    run(b1)
+    s1 = api.graph_cache_stats()
+    assert s1["instantiated"] - s0["instantiated"] <= 6
+    assert s1["instantiated"] - s0["instantiated"] + s1["updated"] - s0["updated"] == 3 * n_groups
+    for _ in range(2):
+        b2 = bin_lattice(lat, grid, max_pairs=15000)
+        run(b2)
+        del b2
+    run(b1)
+    s2 = api.graph_cache_stats()
+    print(f"graph cache: {s0} -> {s1} -> {s2} over {n_groups} groups", flush=True)
+    assert s2["instantiated"] == s1["instantiated"]
+    assert s2["updated"] - s1["updated"] == 3 * 3 * n_groups
+    assert s2["entries"] <= 64
+
+
 def test_batch_without_field_buffer_and_capacity():
     lat, grid = uneven_case()
     b = bin_lattice(lat, grid, max_pairs=15000)
