@@ -229,7 +229,7 @@ lsl_status lattice_bins_order(const lattice_bins* bins, int32_t* order,
  * field >= C (the binary image of Sec. 4).  Per pixel the sum runs over the
  * struts that can reach the pixel's 8x8 block in that plane, in edge-list
  * order; terms outside the support are exactly zero.  float32 sums add runs
- * of four consecutive terms and compensate once per run (the Gaussian
+ * of eight consecutive terms and compensate once per run (the Gaussian
  * variant and float64 compensate every term); the candidates of a block and
  * plane, hence the field's bits, do not depend on the tile, slab depth or
  * group split.  Builds missing groups
@@ -376,7 +376,9 @@ lsl_status slice_occupancy_loss_static(const lattice_bins* bins, int32_t nk, con
  * fields are recomputed, not stored.  Reductions run in a fixed order
  * (results are bitwise repeatable).
  *
- * grad_weight: [n_edges] lattice dtype (absent or unbinned struts get 0).
+ * grad_weight: [n_edges] lattice dtype (struts not binned get 0; zero-weight
+ * struts are binned, and get sum_p dL/dg I_j, when the lattice sets
+ * keep_zero_weight).
  * grad_nodes: [n_nodes][3] lattice dtype.  Either may be NULL.
  * accumulate: 0 overwrites the outputs, 1 adds to them.  Stream-ordered.
  * Covers the quartic kernel, with one support or per-strut supports (held
@@ -393,7 +395,9 @@ lsl_status slice_field_backward(lattice_bins* bins, int32_t k0, int32_t nk,
  * (slab, tile) are taken from a device queue in descending cost order, so
  * planes with very different strut counts share the GPU evenly (Sec. 6.4:
  * slicing time follows the number of struts meeting a plane).  Each group's
- * launch sequence is captured once into a HIP graph and replayed.
+ * launches run as three HIP graphs through the process's graph cache (see
+ * lsl_graph_cache_stats): recorded per call, instantiated once per launch
+ * shape and updated in place afterwards.
  *
  * field: optional [nk][H][W]; when NULL the field is not written (the
  * binary image is built in library scratch, one slab group at a time).
