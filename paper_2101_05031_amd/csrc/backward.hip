@@ -459,32 +459,32 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
 // node gradients).
 namespace b32 {
 
-template <int SZ, bool PR>
+template <int SZ, bool PR, int CH>
 struct Lds;
-template <int SZ>
-struct Lds<SZ, false> {
-    float pg[SZ][kWave];         // per plane: G_k
-    float4 gr[kWave];            // A_0, B_0, 2 m_0,x / R^2, 2 m_0,y / R^2
-    float4 e[kWave];             // u_x / R, u_y / R, c1, 1 / R^2
-    float dl[kWave];             // -dz u_z / R
-    float4 m0[kWave];            // m_0 (x, y, z), R
-    float4 u4[kWave];            // u (x, y, z), dz u_z
-    float rk[kWave];             // the reference plane r (window index)
-    uint32_t mask[kWave];        // reach bits: sub-block s, plane k at bit s SZ + k
-    uint32_t cand[kWave];
-    float slot[kWave][kParts];
+template <int SZ, int CH>
+struct Lds<SZ, false, CH> {
+    float pg[SZ][CH];         // per plane: G_k
+    float4 gr[CH];            // A_0, B_0, 2 m_0,x / R^2, 2 m_0,y / R^2
+    float4 e[CH];             // u_x / R, u_y / R, c1, 1 / R^2
+    float dl[CH];             // -dz u_z / R
+    float4 m0[CH];            // m_0 (x, y, z), R
+    float4 u4[CH];            // u (x, y, z), dz u_z
+    float rk[CH];             // the reference plane r (window index)
+    uint32_t mask[CH];        // reach bits: sub-block s, plane k at bit s SZ + k
+    uint32_t cand[CH];
+    float slot[CH][kParts];
 };
-template <int SZ>
-struct Lds<SZ, true> {
-    float4 pl[SZ][kWave];        // per plane: A_k, B_k, G_k, 2 m_k,x / R^2
-    float pmy[SZ][kWave];        // per plane: 2 m_k,y / R^2
-    float4 e[kWave];
-    float4 m0[kWave];
-    float4 u4[kWave];
-    float rk[kWave];
-    uint32_t mask[kWave];
-    uint32_t cand[kWave];
-    float slot[kWave][kParts];
+template <int SZ, int CH>
+struct Lds<SZ, true, CH> {
+    float4 pl[SZ][CH];        // per plane: A_k, B_k, G_k, 2 m_k,x / R^2
+    float pmy[SZ][CH];        // per plane: 2 m_k,y / R^2
+    float4 e[CH];
+    float4 m0[CH];
+    float4 u4[CH];
+    float rk[CH];
+    uint32_t mask[CH];
+    uint32_t cand[CH];
+    float slot[CH][kParts];
 };
 
 // MODE 0: 16x16 regions, shared reference planes; 1: 16x16 regions, every
@@ -499,7 +499,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     constexpr bool QD = MODE == 2;            // H^ from q_perp
     constexpr int kSub = NS * NS;             // 8x8 sub-blocks of a region
     constexpr int kEdge = 8 * NS;             // region edge in pixels
-    __shared__ Lds<SZ, PR> L;
+    // bucket entries staged at a time: the per-plane values of 8x8 regions
+    // take 32 entries, which keeps the LDS of four waves per SIMD
+    constexpr int kCh = MODE == 2 ? 32 : kWave;
+    __shared__ Lds<SZ, PR, kCh> L;
     const int lane = lane_id();
     const uint32_t item = xcd_remap(blockIdx.x, gridDim.x);
     if (item >= n_items) return;
@@ -540,11 +543,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const float* grad = (const float*)a.grad;
     float* part = (float*)a.partial;
 
-    for (uint32_t cbase = beg; cbase < end; cbase += kWave) {
-        const int nent = (int)((end - cbase) < (uint32_t)kWave ? (end - cbase) : (uint32_t)kWave);
-        for (int q = lane; q < kWave * kParts; q += kWave) (&L.slot[0][0])[q] = 0.0f;
+    const bool st_ok = lane < kCh;            // the lane stages an entry
+    for (uint32_t cbase = beg; cbase < end; cbase += kCh) {
+        const int nent = (int)((end - cbase) < (uint32_t)kCh ? (end - cbase) : (uint32_t)kCh);
+        for (int q = lane; q < kCh * kParts; q += kWave) (&L.slot[0][0])[q] = 0.0f;
         const uint32_t idx = cbase + (uint32_t)lane;
-        bool valid = idx < end;
+        bool valid = st_ok && idx < end;
         const uint32_t pid = valid ? a.ids[idx] : 0u;
         valid = valid && pid < a.n_binned;
         const uint32_t p = valid ? pid : 0u;
@@ -562,6 +566,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
             for (int w0 = kb; w0 < ke; w0 += SZ) {
                 const int nw = ke - w0 < SZ ? ke - w0 : SZ;
                 // ------------------------------------------------ staging
+                int n_cand = 0;
                 {
                     // read the entry afresh for every region and window: what
                     // follows from it would otherwise stay in registers
@@ -634,20 +639,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                             // m_k / R
                             const double mxk = fma(kd, dzuz * ln.x, mx), myk = fma(kd, dzuz * ln.y, my),
                                          mzk = fma(kd, fma(dzuz, ln.z, -a.dz), mz);
-                            L.pl[k][lane] = make_float4((float)(-tc * iR), (float)((ln.w - tc) * iR),
+                            if (st_ok) L.pl[k][lane] = make_float4((float)(-tc * iR), (float)((ln.w - tc) * iR),
                                                         (float)(mxk * iR), (float)(myk * iR));
-                            L.pmy[k][lane] = (float)(mzk * iR);
+                            if (st_ok) L.pmy[k][lane] = (float)(mzk * iR);
                         } else if constexpr (PR) {
                             const double mxk = fma(kd, dzuz * ln.x, mx), myk = fma(kd, dzuz * ln.y, my);
-                            L.pl[k][lane] = make_float4((float)(-tc * iR), (float)((ln.w - tc) * iR),
+                            if (st_ok) L.pl[k][lane] = make_float4((float)(-tc * iR), (float)((ln.w - tc) * iR),
                                                         (float)fma(-m2, iR2, 1.0), (float)(2.0 * mxk * iR2));
-                            L.pmy[k][lane] = (float)(2.0 * myk * iR2);
+                            if (st_ok) L.pmy[k][lane] = (float)(2.0 * myk * iR2);
                         } else {
-                            L.pg[k][lane] = (float)fma(-m2, iR2, 1.0);
+                            if (st_ok) L.pg[k][lane] = (float)fma(-m2, iR2, 1.0);
                         }
                     }
                     if (!valid) mask = 0u;
-                    L.mask[lane] = mask;
+                    if (st_ok) L.mask[lane] = mask;
                     // the reference plane r: the middle of the planes the
                     // strut reaches, so that the shifts k - r and the offsets
                     // m_r stay small (m_k = m_r + (k - r) dm, dm = dz (u_z u -
@@ -661,22 +666,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     const double tcr = fma(rd, dzuz, tc0);
                     const double mxr = fma(rd, dzuz * ln.x, mx), myr = fma(rd, dzuz * ln.y, my),
                                  mzr = fma(rd, fma(dzuz, ln.z, -a.dz), mz);
-                    L.rk[lane] = (float)rr;
-                    L.e[lane] = make_float4((float)(ln.x * iR), (float)(ln.y * iR),
+                    if (st_ok) L.rk[lane] = (float)rr;
+                    if (st_ok) L.e[lane] = make_float4((float)(ln.x * iR), (float)(ln.y * iR),
                                             (float)(2.0 * dzuz * iR), (float)(QD ? iR : iR2));
                     if constexpr (!PR) {
-                        L.dl[lane] = (float)(-dzuz * iR);
-                        L.gr[lane] = make_float4((float)(-tcr * iR), (float)((ln.w - tcr) * iR),
+                        if (st_ok) L.dl[lane] = (float)(-dzuz * iR);
+                        if (st_ok) L.gr[lane] = make_float4((float)(-tcr * iR), (float)((ln.w - tcr) * iR),
                                                  (float)(2.0 * mxr * iR2), (float)(2.0 * myr * iR2));
                     }
-                    L.m0[lane] = make_float4((float)mxr, (float)myr, (float)mzr, (float)Rs);
-                    L.u4[lane] = make_float4(uxf, uyf, (float)ln.z, (float)dzuz);
+                    if (st_ok) L.m0[lane] = make_float4((float)mxr, (float)myr, (float)mzr, (float)Rs);
+                    if (st_ok) L.u4[lane] = make_float4(uxf, uyf, (float)ln.z, (float)dzuz);
                     const uint64_t cm = ballot64(mask != 0u);
                     if (mask != 0u) {
                         const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
                             (uint32_t)(cm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)cm, 0u));
                         L.cand[rank] = (uint32_t)lane;
                     }
+                    n_cand = __popcll(cm);
                 }
                 // dL/dg at the lane's four pixels
                 float Gv[kSub][SZ];
@@ -694,7 +700,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 });
 
                 __builtin_amdgcn_wave_barrier();
-                const int n = __popcll(ballot64(L.mask[lane] != 0u));
+                const int n = n_cand;
 
                 // --------------------------------------------- evaluation
 #pragma unroll 1

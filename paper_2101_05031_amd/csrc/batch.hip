@@ -53,10 +53,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         t /= (uint32_t)a.ntx;
         const int ty = (int)(t % (uint32_t)a.nty);
         t /= (uint32_t)a.nty;
-        if constexpr (std::is_same<T, float>::value && K == LSL_KERNEL_QUARTIC) {
-            __shared__ q32::Lds<SZ, PR> lds[4];
+        if constexpr (std::is_same<T, float>::value && K == LSL_KERNEL_QUARTIC && !PR) {
+            __shared__ q32::Lds<SZ> lds[4];
             for (int sub = wv; sub < nsub * nsub; sub += 4)
-                q32::field_block<SZ, false, SR, PR>(a, a.s_lo + (int)t, tx, ty, sub, lds[wv]);
+                q32::field_block<SZ, false, SR>(a, a.s_lo + (int)t, tx, ty, sub, lds[wv]);
         } else {
             __shared__ Stage<T> stage[4][kWave];
             __shared__ T pend[4][fieldk::pend_elems<T, SZ>()];

@@ -1,5 +1,10 @@
 // Field evaluation (Eq. 6 with the closed form of Eq. 7, Sec. 4 Step 4).
 //
+// The float32 kernel of the paper's kernel (field_q32.hpp) serves lattices
+// whose planes may share reference planes; the method below (field_block.hpp)
+// serves float64, the compact Gaussian and float32 lattices whose planes are
+// coarse against the smallest support (every plane staged from float64).
+//
 // One wave owns an 8x8 pixel block of one tile and one slab of planes; the
 // four waves of a workgroup take the four 8x8 blocks of a 16x16 tile (or
 // four of the blocks of a larger tile).  The wave walks its tile's bucket
@@ -57,9 +62,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     t /= (uint32_t)a.ntx;
     const int ty = (int)(t % (uint32_t)a.nty);
     t /= (uint32_t)a.nty;
-    if constexpr (std::is_same<T, float>::value && K == LSL_KERNEL_QUARTIC) {
-        __shared__ q32::Lds<SZ, PR> lds[4];
-        q32::field_block<SZ, STATS, SR, PR>(a, a.s_lo + (int)t, tx, ty, sub, lds[wv]);
+    // float32, the paper's kernel, shared reference planes: field_q32.hpp;
+    // otherwise (float64, the Gaussian, every plane its own reference)
+    // field_block.hpp
+    if constexpr (std::is_same<T, float>::value && K == LSL_KERNEL_QUARTIC && !PR) {
+        __shared__ q32::Lds<SZ> lds[4];
+        q32::field_block<SZ, STATS, SR>(a, a.s_lo + (int)t, tx, ty, sub, lds[wv]);
     } else {
         __shared__ Stage<T> stage[4][kWave];
         __shared__ T pend[4][fieldk::pend_elems<T, SZ>()];
@@ -107,7 +115,8 @@ lsl_status launch_tkp(const FieldArgs& a, bool stats, uint32_t n_items, hipStrea
     return LSL_OK;
 }
 
-// The per-plane reference form exists for the float32 quartic kernel only.
+// Coarse planes (every plane its own reference) matter to the float32
+// kernel of the paper's kernel only.
 template <typename T, int SZ, int K, bool SR>
 lsl_status launch_tk(const FieldArgs& a, bool stats, uint32_t n_items, hipStream_t st) {
     if constexpr (std::is_same<T, float>::value && K == LSL_KERNEL_QUARTIC) {

@@ -33,9 +33,9 @@
 // e_z), so 2 m.d grows by 2 (k - r) dz u_z (d.u).  The reference planes are the multiples of 8 (r = 8 floor(k / 8)),
 // so a plane's value does not depend on how planes are grouped into slabs.
 // The shift costs accuracy once 7 dz |d| is no longer small against R^2 (the
-// pieces of H grow while H stays small): the library then uses every plane as
-// its own reference (kappa = 0, E, A, B per plane; PLANE_REF below), a choice made
-// once per lattice and grid, so the field stays the same under every tiling.
+// pieces of H grow while H stays small): such lattices (a choice made once
+// per lattice and grid) are sliced by the kernel of field_block.hpp, which
+// stages every plane from float64.
 // H <= rho^2 <= 1, so the clamp to [0, 1] is the max(H, 0) the square root
 // needs.
 //
@@ -68,26 +68,14 @@ namespace q32 {
 
 constexpr int kRun = 8;         // terms per compensated add
 
-// Per-wave LDS of the staging, indexed by the staged lane (bucket entry).
-// Shared reference planes: pg, per plane G_k; gr, per reference group
-// (A_r, B_r, 2 m_r,x^, 2 m_r,y^) with m^ = m / unit^2.  Every plane its own
-// reference: pl (A_k, B_k, G_k, -) and pm (2 m_k,x^, 2 m_k,y^) per plane.
-// e: (u_x^, u_y^, c1, 1 / unit^2); dl: -dz^ u_z; cand: the compacted
-// candidates, lane | plane mask << 8.
-template <int SZ, bool PLANE_REF>
-struct Lds;
+// Per-wave LDS of the staging, indexed by the staged lane (bucket entry):
+// pg, per plane G_k; gr, per reference group (A_r, B_r, 2 m_r,x^, 2 m_r,y^)
+// with m^ = m / unit^2; e: (u_x^, u_y^, c1, 1 / unit^2); dl: -dz^ u_z;
+// cand: the compacted candidates, lane | plane mask << 8.
 template <int SZ>
-struct Lds<SZ, false> {
+struct Lds {
     float pg[SZ][kWave];
     float4 gr[SZ >= 16 ? 3 : (SZ >= 2 ? 2 : 1)][kWave];
-    float4 e[kWave];
-    float dl[kWave];
-    uint32_t cand[kWave];
-};
-template <int SZ>
-struct Lds<SZ, true> {
-    float4 pl[SZ][kWave];
-    float2 pm[SZ][kWave];
     float4 e[kWave];
     float dl[kWave];
     uint32_t cand[kWave];
@@ -123,8 +111,8 @@ __device__ __forceinline__ void comp_add(float g, float& s, float& c) {
 // E, nD and the planes' G_k its staged values) at the pixel d = (dX, dY) of each plane it
 // reaches, added to the open runs of the planes of the slab that starts at
 // plane kb (reference group gb).
-template <int SZ, bool STATS, bool PLANE_REF>
-__device__ __forceinline__ void add_candidate(const Lds<SZ, PLANE_REF>& L, uint32_t e,
+template <int SZ, bool STATS>
+__device__ __forceinline__ void add_candidate(const Lds<SZ>& L, uint32_t e,
                                               uint32_t mask, float4 E, float nD, int kb, int gb,
                                               const float (&Gk)[SZ], float dX, float dY,
                                               float nd2, bool pix, float (&acc_s)[SZ],
@@ -139,31 +127,18 @@ __device__ __forceinline__ void add_candidate(const Lds<SZ, PLANE_REF>& L, uint3
     for_planes<0, SZ>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         if (!((mask >> k) & 1u)) return;
-        float al, be, H;
-        if constexpr (PLANE_REF) {
-            const float4 P = L.pl[k][e];
-            const float2 M = L.pm[k][e];
-            al = P.x - du;
-            be = P.y - du;
-            H = __builtin_amdgcn_fmed3f(
-                __builtin_fmaf(du, du,
-                               __builtin_fmaf(M.x, dX, __builtin_fmaf(M.y, dY, ndd + P.z))),
-                0.0f, 1.0f);
-        } else {
-            const int g = ((kb + k) >> 3) - gb;
-            if (g != gcur) {
-                const float4 Rg = L.gr[g][e];
-                ar = Rg.x - du;
-                br = Rg.y - du;
-                Eg = __builtin_fmaf(du, du,
-                                    __builtin_fmaf(Rg.z, dX, __builtin_fmaf(Rg.w, dY, ndd)));
-                gcur = g;
-            }
-            const float kap = kappa((kb + k) & 7);
-            al = __builtin_fmaf(kap, nD, ar);
-            be = __builtin_fmaf(kap, nD, br);
-            H = __builtin_amdgcn_fmed3f(__builtin_fmaf(kap, P1, Gk[k] + Eg), 0.0f, 1.0f);
+        const int g = ((kb + k) >> 3) - gb;
+        if (g != gcur) {
+            const float4 Rg = L.gr[g][e];
+            ar = Rg.x - du;
+            br = Rg.y - du;
+            Eg = __builtin_fmaf(du, du, __builtin_fmaf(Rg.z, dX, __builtin_fmaf(Rg.w, dY, ndd)));
+            gcur = g;
         }
+        const float kap = kappa((kb + k) & 7);
+        const float al = __builtin_fmaf(kap, nD, ar);
+        const float be = __builtin_fmaf(kap, nD, br);
+        const float H = __builtin_amdgcn_fmed3f(__builtin_fmaf(kap, P1, Gk[k] + Eg), 0.0f, 1.0f);
         const float h = __builtin_amdgcn_sqrtf(H);
         const float ca = __builtin_amdgcn_fmed3f(al, -h, h);
         const float cb = __builtin_amdgcn_fmed3f(be, -h, h);
@@ -185,10 +160,10 @@ __device__ __forceinline__ void add_candidate(const Lds<SZ, PLANE_REF>& L, uint3
     });}
 
 // One wave: the 8x8 block `sub` of tile (tx, ty) over the planes of `slab`
-// in [k0, k0+nk).  PLANE_REF: every plane is its own reference (see above).
-template <int SZ, bool STATS, bool SR, bool PLANE_REF>
+// in [k0, k0+nk).
+template <int SZ, bool STATS, bool SR>
 __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx, int ty, int sub,
-                                            Lds<SZ, PLANE_REF>& L) {
+                                            Lds<SZ>& L) {
     const int lane = lane_id();
     const uint32_t n_binned = a.n_binned, n_pairs = a.n_pairs;
     const int nsub = a.tile / kBlockPix;
@@ -266,7 +241,7 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
         const float vxf = (float)(a.dz * ln.z * ln.x), vyf = (float)(a.dz * ln.z * ln.y);
         const double c2 = a.dz * a.dz * (1.0 - ln.z * ln.z);
         uint32_t pmask = 0u;
-        double tcr = 0.0, m2r = 0.0, c1 = 0.0, mxd = 0.0, myd = 0.0;
+        double tcr = 0.0, m2r = 0.0, c1 = 0.0;
         float mxr = 0.0f, myr = 0.0f;
         int grp = -1, rref = 0;
         // one plane at a time: the float64 temporaries of several planes in
@@ -274,11 +249,11 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
 #pragma unroll 1
         for (int k = 0; k < nvalid; ++k) {
             const int ka = kb + k;
-            const int g = PLANE_REF ? ka : (ka >> 3);
+            const int g = ka >> 3;
             if (g != grp) {
                 // the group's reference plane, in float64
                 grp = g;
-                rref = PLANE_REF ? ka : (g << 3);
+                rref = g << 3;
                 const double z = a.z0 + ((double)rref + 0.5) * a.dz;
                 const double wz = z - az;
                 tcr = fma(wz, ln.z, txy);
@@ -286,14 +261,10 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
                              mz = fma(tcr, ln.z, -wz);
                 m2r = fma(mx, mx, fma(my, my, mz * mz));
                 c1 = -2.0 * a.dz * mz;
-                mxd = mx;
-                myd = my;
                 mxr = (float)mx;
                 myr = (float)my;
-                if constexpr (!PLANE_REF)
-                    L.gr[g - gb][lane] = make_float4((float)(-tcr * iR), (float)((ln.w - tcr) * iR),
-                                                     (float)(2.0 * mx * iR2),
-                                                     (float)(2.0 * my * iR2));
+                L.gr[g - gb][lane] = make_float4((float)(-tcr * iR), (float)((ln.w - tcr) * iR),
+                                                 (float)(2.0 * mx * iR2), (float)(2.0 * my * iR2));
             }
             // plane ka from the reference: tc and |m|^2 (m is orthogonal to u,
             // so |m_k|^2 = |m_r|^2 - 2 kappa dz m_r,z + kappa^2 dz^2 (1 - u_z^2))
@@ -314,13 +285,7 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
             const uint32_t pass = ((zmask >> k) & 1u) &
                                   ((uint32_t)(q <= 0.0f) | (uint32_t)(q * q < Rc2f * D2));
             pmask |= pass << k;
-            const float G = (float)(rho * rho - m2 * iR2);
-            if constexpr (PLANE_REF) {
-                L.pl[k][lane] = make_float4((float)(-tc * iR), (float)((ln.w - tc) * iR), G, 0.0f);
-                L.pm[k][lane] = make_float2((float)(2.0 * mxd * iR2), (float)(2.0 * myd * iR2));
-            } else {
-                L.pg[k][lane] = G;
-            }
+            L.pg[k][lane] = (float)(rho * rho - m2 * iR2);
         }
         L.e[lane] = make_float4((float)(ln.x * iR), (float)(ln.y * iR),
                                 (float)(2.0 * a.dz * ln.z * iR), (float)iR2);
@@ -344,16 +309,14 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
             const uint32_t e = c & 63u;
             const uint32_t mask = __builtin_amdgcn_readfirstlane(c >> 8);
             float Gk[SZ];
-            if constexpr (!PLANE_REF) {
-                for_planes<0, SZ>([&](auto kc) {
-                    constexpr int k = decltype(kc)::value;
-                    Gk[k] = L.pg[k][e];
-                });
-            }
+            for_planes<0, SZ>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                Gk[k] = L.pg[k][e];
+            });
             const uint32_t cn = L.cand[j + 1 < n ? j + 1 : j];
             const float4 En = L.e[cn & 63u];
             const float nDn = L.dl[cn & 63u];
-            add_candidate<SZ, STATS, PLANE_REF>(L, e, mask, E, nD, kb, gb, Gk, dX, dY, nd2, pix,
+            add_candidate<SZ, STATS>(L, e, mask, E, nD, kb, gb, Gk, dX, dY, nd2, pix,
                                                 acc_s, acc_c, run, open, n_cand, n_useful);
             c = cn;
             E = En;

@@ -54,9 +54,9 @@ __global__ __launch_bounds__(256) void k_probe_f64(double* out, int iters, doubl
 // put every pixel inside every strut's support.
 __global__ __launch_bounds__(256) void k_probe_term(float* out, int iters) {
     constexpr int SZ = 8;
-    __shared__ q32::Lds<SZ, false> lds[4];
+    __shared__ q32::Lds<SZ> lds[4];
     const int lane = lane_id(), wv = threadIdx.x >> 6;
-    q32::Lds<SZ, false>& L = lds[wv];
+    q32::Lds<SZ>& L = lds[wv];
     for (int k = 0; k < SZ; ++k) L.pg[k][lane] = 0.6f - 0.01f * (float)k - 0.002f * (float)lane;
     L.gr[0][lane] = make_float4(-0.3f - 0.004f * (float)lane, 0.8f + 0.004f * (float)lane, 0.02f,
                                 -0.03f);
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void k_probe_term(float* out, int iters) {
             const uint32_t cn = L.cand[j + 1 < kWave ? j + 1 : j];
             const float4 En = L.e[cn & 63u];
             const float nDn = L.dl[cn & 63u];
-            q32::add_candidate<SZ, false, false>(L, e, mask, E, nD, 0, 0, Gk, dX, dY, nd2, true,
+            q32::add_candidate<SZ, false>(L, e, mask, E, nD, 0, 0, Gk, dX, dY, nd2, true,
                                                  acc_s, acc_c, run, open, n_cand, n_useful);
             c = cn;
             E = En;
