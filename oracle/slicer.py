@@ -6,14 +6,14 @@ Test infrastructure (see the package docstring).
   height and Step 5 moves up by one layer, so plane k is z0 + (k + 1/2) t.
 * active_set: Eq. (8), the struts whose swept sphere of radius R meets the
   plane, with the lower end written v_s (the paper orders the ends by z).
-* sweep_active_sets: Steps 1-6, the edge list sorted by lower z plus the
-  active list, as a second route to the same sets.
+* sweep_active_sets: the same sets from sorted events along z (where each
+  swept sphere starts and ends), as a second route to them.
 * slice_field: Step 4, the field at every pixel centre of one plane using the
   active struts only; inside where the sum reaches the iso-value.
 
 R is one support for every strut, or an array with one per strut (the
-per-strut variant); the sweep then keeps the list sorted by z_lo - R_i, the
-lower end of each swept sphere, which is z_lo ordering when R is shared.
+per-strut variant); the sweep's start events are then ordered by z_lo - R_i,
+the lower end of each swept sphere, which is z_lo ordering when R is shared.
 """
 from __future__ import annotations
 
@@ -41,22 +41,24 @@ def active_set(zlo, zhi, R, z: float) -> np.ndarray:
 
 
 def sweep_active_sets(zlo, zhi, R, heights):
-    """Steps 1-6: returns the active set (ascending ids) of every plane."""
+    """Eq. (8)'s active sets by events along z, a second route to active_set:
+    each strut's swept sphere spans [b, t] = [z_lo - R, z_hi + R]; sorting
+    the b's and the t's once, the struts started by plane z are a prefix of
+    the b order (b <= z) and those finished are a prefix of the t order
+    (t < z); the active set is the first less the second.  The b order is the
+    paper's edge list sorted by lower end (Sec. 4).  Returns the active set
+    (ascending ids) of every plane."""
     Rv = np.broadcast_to(np.asarray(R, dtype=np.float64), np.shape(zlo))
-    bottom = zlo - Rv                          # lower end of each swept sphere
-    order = np.argsort(bottom, kind="stable")  # the list sorted by it
-    m = len(order)
-    k = 0                                      # first edge not yet added
-    active: list[int] = []
+    b = np.asarray(zlo, dtype=np.float64) - Rv
+    t = np.asarray(zhi, dtype=np.float64) + Rv
+    by_b = np.argsort(b, kind="stable")
+    by_t = np.argsort(t, kind="stable")
+    b_sorted, t_sorted = b[by_b], t[by_t]
     out = []
     for z in heights:
-        # Step 2: add edges until one lies completely above the plane
-        while k < m and not (bottom[order[k]] > z):
-            active.append(int(order[k]))
-            k += 1
-        # Step 3: drop edges lying completely below the plane
-        active = [j for j in active if not (zhi[j] + Rv[j] < z)]
-        out.append(np.array(sorted(active), dtype=np.int64))
+        started = by_b[:np.searchsorted(b_sorted, z, side="right")]
+        finished = by_t[:np.searchsorted(t_sorted, z, side="left")]
+        out.append(np.setdiff1d(started, finished).astype(np.int64))
     return out
 
 

@@ -23,7 +23,8 @@ def test_slice_heights_steps_1_and_5():
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_sweep_equals_eq8(seed):
-    """Steps 1-6 (sorted list + active list) give exactly Eq. (8)'s sets."""
+    """The event sweep (sorted starts and ends of the swept spheres) gives
+    exactly Eq. (8)'s sets."""
     lat = synth.random_lattice(60, 300, 20.0, seed=seed)
     zlo, zhi = S.strut_z_range(lat.nodes, lat.edges)
     heights = S.slice_heights(-3.0, 0.37, 80)
