@@ -12,8 +12,8 @@
  *
  * and p lies inside the solid where g(p) >= C (the paper writes the implicit
  * function as F = -C + g; inside is where the skeleton's sum reaches the
- * iso-value).  Slices are planes z_k = z0 + (k + 1/2) dz (Sec. 4, Steps 1
- * and 5); each plane is sampled at pixel centres
+ * iso-value).  Slices are planes z_k = z0 + (k + 1/2) dz (Sec. 4: the first
+ * half a layer up, one layer apart); each plane is sampled at pixel centres
  * (x0 + (i + 1/2) dx, y0 + (j + 1/2) dy), i < W, j < H, giving a field image,
  * a binary image (Sec. 4) and its marching-squares contours (Sec. 4).
  * Two kernel variants (per-strut supports, a compact Gaussian) are selected
@@ -150,7 +150,7 @@ typedef struct lsl_bins_info {
  * of at most max_pairs bucket entries.  The first group's bucket lists are
  * built at once; later groups are built when their slices are requested,
  * reusing the active struts of the previous group (the active list of
- * Eq. (8), Steps 2-3).
+ * Eq. (8), kept up to date as the sweep of Sec. 4 moves up).
  *
  * Bin set (exact; evaluated in float64 in this operation order, no fused
  * multiply-add): for each strut with ends a, b and each axis with origin o,
@@ -222,7 +222,7 @@ lsl_status lattice_bins_order(const lattice_bins* bins, int32_t* order,
 
 /* ---------------------------------------------------------------------------
  * slice_field -- evaluate g (Eq. 6, closed form of Eq. 7 over arclength) at
- * every pixel centre of planes k0 .. k0+nk-1 (Sec. 4, Step 4).
+ * every pixel centre of planes k0 .. k0+nk-1 (Sec. 4).
  *
  * field: [nk][H][W] of the lattice dtype (required).  bits: optional
  * [nk][H][ceil(W/32)] uint32, bit (i % 32) of word i/32 set where

@@ -9,7 +9,7 @@ native library and imports nothing from it.
 
 Modules
   field     -- kernel (Eq. 5), per-strut integral (Eqs. 6-7), field sums
-  slicer    -- slice heights, active set (Eq. 8), the Steps 1-6 sweep,
+  slicer    -- slice heights, active set (Eq. 8), the event sweep to the same sets,
                per-slice field and the inside test
   binning   -- the (slab, tile, strut) bin set the native binning must equal
   contours  -- marching squares on the binary slice image (Sec. 4)

@@ -2,14 +2,15 @@
 
 Test infrastructure (see the package docstring).
 
-* slice_heights: Step 1 puts the first plane half a layer above the start
-  height and Step 5 moves up by one layer, so plane k is z0 + (k + 1/2) t.
+* slice_heights: the sweep of Sec. 4 puts the first plane half a layer above
+  the start height and moves up one layer per plane, so plane k is
+  z0 + (k + 1/2) t.
 * active_set: Eq. (8), the struts whose swept sphere of radius R meets the
   plane, with the lower end written v_s (the paper orders the ends by z).
 * sweep_active_sets: the same sets from sorted events along z (where each
   swept sphere starts and ends), as a second route to them.
-* slice_field: Step 4, the field at every pixel centre of one plane using the
-  active struts only; inside where the sum reaches the iso-value.
+* slice_field: the field at every pixel centre of one plane using the
+  active struts only (Sec. 4); inside where the sum reaches the iso-value.
 
 R is one support for every strut, or an array with one per strut (the
 per-strut variant); the sweep's start events are then ordered by z_lo - R_i,

@@ -1,8 +1,8 @@
 // Bucket lists of one slab group.
 //
 // The active struts of the group [sa, sb] are the edge-list entries whose
-// slab range meets it (Eq. (8) at slab granularity).  Like Steps 2-3 of the
-// paper's sweep, a group following the previous one keeps the previous active
+// slab range meets it (Eq. (8) at slab granularity).  As the paper's sweep
+// upward does (Sec. 4), a group following the previous one keeps the previous active
 // list minus the struts that ended, then appends the edge-list range that
 // starts in the new slabs.  Each active strut then emits one (bucket, strut)
 // pair per (slab, tile) of its range; a stable radix sort by bucket keeps

@@ -1,4 +1,4 @@
-// Field evaluation (Eq. 6 with the closed form of Eq. 7, Sec. 4 Step 4).
+// Field evaluation (Eq. 6 with the closed form of Eq. 7, Sec. 4).
 //
 // The float32 kernel of the paper's kernel (field_q32.hpp) serves lattices
 // whose planes may share reference planes; the method below (field_block.hpp)

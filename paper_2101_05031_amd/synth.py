@@ -21,7 +21,7 @@ Input recipe (units are mm):
   convention, not part of the method.
 * The kernel support is R = 1.5 x the largest radius the recipe can produce
   (Sec. 3.2 uses 1.5 x the maximal radius), and the iso-value is C = 1.
-* Slices sit at z0 + (k + 1/2) dz with z0 the lowest node (Sec. 4, Step 1).
+* Slices sit at z0 + (k + 1/2) dz with z0 the lowest node (Sec. 4).
 * Pixels are square; the grid covers the lattice's xy bounding box grown by R
   plus two pixels on each side, so that every contour closes inside the image.
 """

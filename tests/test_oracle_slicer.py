@@ -12,9 +12,9 @@ from oracle import slicer as S
 from paper_2101_05031_amd import synth
 
 
-def test_slice_heights_steps_1_and_5():
+def test_slice_heights_half_layer_then_one_layer_apart():
     z = S.slice_heights(2.0, 0.1, 5)
-    # Step 1 starts half a layer up; Step 5 adds one layer per plane
+    # the first plane half a layer up, then one layer per plane (Sec. 4)
     ref = [2.0 + 0.05]
     for _ in range(4):
         ref.append(ref[-1] + 0.1)

@@ -86,7 +86,7 @@ def test_per_strut_binning_order_and_sweep():
                     bk = (s * nty + ty) * ntx + tx
                     want = [i for i in order if OB.bucket_of(r, i, s, ty, tx)]
                     assert list(ids[off[bk]:off[bk + 1]]) == want
-    # the Steps 1-6 sweep, its list sorted by z_lo - R_j, gives Eq. (8)'s sets
+    # the event sweep, its starts ordered by z_lo - R_j, gives Eq. (8)'s sets
     zlo, zhi = OS.strut_z_range(lat.nodes, lat.edges)
     hs = OS.slice_heights(grid.z0, grid.dz, grid.n_slices)
     for z, got in zip(hs, OS.sweep_active_sets(zlo, zhi, lat.support, hs)):
