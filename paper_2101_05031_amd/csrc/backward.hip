@@ -824,37 +824,46 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                         });
                     });
                     // over all sub-blocks, the right-hand ones and the lower ones
-                    float AB = Bs[0], AA = As[0], SXB = 0.0f, SXA = 0.0f, SYB = 0.0f, SYA = 0.0f;
-                    if constexpr (NS == 2) {
-                        SXB = Bs[1] + Bs[3];
-                        SXA = As[1] + As[3];
-                        SYB = Bs[2] + Bs[3];
-                        SYA = As[2] + As[3];
-                        AB = (Bs[0] + Bs[2]) + SXB;
-                        AA = (As[0] + As[2]) + SXA;
-                    }
-                    // sums of G K times the pixel's d_x, d_y and d.u^
-                    const float ABx = __builtin_fmaf(8.0f * dxf, SXB, Dx[0] * AB);
-                    const float ABy = __builtin_fmaf(8.0f * dyf, SYB, Dy[0] * AB);
-                    const float ABu = __builtin_fmaf(e8x, SXB, __builtin_fmaf(e8y, SYB, du0 * AB));
-                    const float AAx = __builtin_fmaf(8.0f * dxf, SXA, Dx[0] * AA);
-                    const float AAy = __builtin_fmaf(8.0f * dyf, SYA, Dy[0] * AA);
-                    const float AAu = __builtin_fmaf(e8x, SXA, __builtin_fmaf(e8y, SYA, du0 * AA));
-                    // sum G K q_perp = m_r sum G K + dm sum (k - r) G K - sum G K d
-                    // + R u sum G K (d.u^), dm = dz u_z u - dz e_z, for K_b and K_a
                     const float4 M = L.m0[e];
                     const float dmx = U.w * U.x, dmy = U.w * U.y, dmz = __builtin_fmaf(U.w, U.z, -dzf);
                     const float rux = M.w * U.x, ruy = M.w * U.y, ruz = M.w * U.z;
-                    float v[kParts] = {
-                        Aw * (1.0f / 16.0f),
-                        Aa,
-                        Ab,
-                        __builtin_fmaf(M.x, AB, __builtin_fmaf(dmx, ABk, __builtin_fmaf(rux, ABu, -ABx))),
-                        __builtin_fmaf(M.y, AB, __builtin_fmaf(dmy, ABk, __builtin_fmaf(ruy, ABu, -ABy))),
-                        __builtin_fmaf(M.z, AB, __builtin_fmaf(dmz, ABk, ruz * ABu)),
-                        __builtin_fmaf(M.x, AA, __builtin_fmaf(dmx, AAk, __builtin_fmaf(rux, AAu, -AAx))),
-                        __builtin_fmaf(M.y, AA, __builtin_fmaf(dmy, AAk, __builtin_fmaf(ruy, AAu, -AAy))),
-                        __builtin_fmaf(M.z, AA, __builtin_fmaf(dmz, AAk, ruz * AAu))};
+                    // sum G K q_perp = m_r sum G K + dm sum (k - r) G K - sum G K d
+                    // + R u sum G K (d.u^), dm = dz u_z u - dz e_z, for K_b and K_a
+                    float v[kParts];
+                    v[0] = Aw * (1.0f / 16.0f);
+                    v[1] = Aa;
+                    v[2] = Ab;
+                    if constexpr (NS == 2) {
+                        // over all sub-blocks, the right-hand and the lower ones
+                        // (d of sub-block (sx, sy) = d_00 + 8 (sx dx, sy dy))
+                        const float SXB = Bs[1] + Bs[3], SXA = As[1] + As[3];
+                        const float SYB = Bs[2] + Bs[3], SYA = As[2] + As[3];
+                        const float AB = (Bs[0] + Bs[2]) + SXB, AA = (As[0] + As[2]) + SXA;
+                        const float ABx = __builtin_fmaf(8.0f * dxf, SXB, Dx[0] * AB);
+                        const float ABy = __builtin_fmaf(8.0f * dyf, SYB, Dy[0] * AB);
+                        const float ABu = __builtin_fmaf(e8x, SXB, __builtin_fmaf(e8y, SYB, du0 * AB));
+                        const float AAx = __builtin_fmaf(8.0f * dxf, SXA, Dx[0] * AA);
+                        const float AAy = __builtin_fmaf(8.0f * dyf, SYA, Dy[0] * AA);
+                        const float AAu = __builtin_fmaf(e8x, SXA, __builtin_fmaf(e8y, SYA, du0 * AA));
+                        v[3] = __builtin_fmaf(M.x, AB, __builtin_fmaf(dmx, ABk, __builtin_fmaf(rux, ABu, -ABx)));
+                        v[4] = __builtin_fmaf(M.y, AB, __builtin_fmaf(dmy, ABk, __builtin_fmaf(ruy, ABu, -ABy)));
+                        v[5] = __builtin_fmaf(M.z, AB, __builtin_fmaf(dmz, ABk, ruz * ABu));
+                        v[6] = __builtin_fmaf(M.x, AA, __builtin_fmaf(dmx, AAk, __builtin_fmaf(rux, AAu, -AAx)));
+                        v[7] = __builtin_fmaf(M.y, AA, __builtin_fmaf(dmy, AAk, __builtin_fmaf(ruy, AAu, -AAy)));
+                        v[8] = __builtin_fmaf(M.z, AA, __builtin_fmaf(dmz, AAk, ruz * AAu));
+                    } else {
+                        // one sub-block: the lane's q_perp at plane r, m_r - d + (d.u) u,
+                        // weights both ends' sums
+                        const float qx = __builtin_fmaf(rux, du0, M.x - Dx[0]);
+                        const float qy = __builtin_fmaf(ruy, du0, M.y - Dy[0]);
+                        const float qz = __builtin_fmaf(ruz, du0, M.z);
+                        v[3] = __builtin_fmaf(qx, Bs[0], dmx * ABk);
+                        v[4] = __builtin_fmaf(qy, Bs[0], dmy * ABk);
+                        v[5] = __builtin_fmaf(qz, Bs[0], dmz * ABk);
+                        v[6] = __builtin_fmaf(qx, As[0], dmx * AAk);
+                        v[7] = __builtin_fmaf(qy, As[0], dmy * AAk);
+                        v[8] = __builtin_fmaf(qz, As[0], dmz * AAk);
+                    }
                     if constexpr (MODE == 0) {
                         // K_a = K_b + 2 J L: the second sums carried J
                         const float Lh = Rg.y - Rg.x;
