@@ -101,6 +101,14 @@ __device__ __forceinline__ void for_planes(F&& f) {
     }
 }
 
+// A wave-uniform float64 value moved to scalar registers.
+__device__ __forceinline__ double uniform(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 __device__ __forceinline__ void comp_add(float g, float& s, float& c) {
     const float sn = s + g;
     c += g - (sn - s);
@@ -185,8 +193,9 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
     const int lx = lane & 7, ly = lane >> 3;
     const int pi = i0 + lx, pj = j0 + ly;
     const bool pix = pi < a.W && pj < a.H;
-    const double cx = a.x0 + ((double)i0 + 4.0) * a.dx;     // centre of the 8x8 centres
-    const double cy = a.y0 + ((double)j0 + 4.0) * a.dy;
+    // centre of the 8x8 centres (uniform: held in scalar registers)
+    const double cx = uniform(a.x0 + ((double)i0 + 4.0) * a.dx);
+    const double cy = uniform(a.y0 + ((double)j0 + 4.0) * a.dy);
     // d in grid units; the strut's values carry its length unit (so one
     // support given per strut is bitwise the same computation as one R)
     const double dXd = ((double)lx - 3.5) * a.dx, dYd = ((double)ly - 3.5) * a.dy;
@@ -206,29 +215,40 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, int slab, int tx
     unsigned long long n_cand = 0, n_useful = 0;
 
     const StrutRec<float>* recs = (const StrutRec<float>*)a.rec;
+    // the bucket entries of the next chunk are read one chunk ahead, and all
+    // of an entry's records at once: one memory round trip per chunk
+    // (read unconditionally from a clamped index, so that the wait for this
+    // chunk's records does not wait for them; lanes past the end are
+    // invalid whatever they read)
+    uint32_t p_next = 0u;
+    if (beg < end) p_next = a.ids[beg + (uint32_t)lane < end ? beg + (uint32_t)lane : end - 1u];
     for (uint32_t cbase = beg; cbase < end; cbase += kWave) {
         // ---------------------------------------------------------- staging
         const uint32_t idx = cbase + (uint32_t)lane;
         bool valid = idx < end;
-        uint32_t p = valid ? a.ids[idx] : 0u;
+        const uint32_t p = p_next;
         valid = valid && p < n_binned;
-        const StrutRec<float> r = recs[valid ? p : 0u];
-        uint32_t zmask = 0u;
-        {
-            const PRange pr = a.pranges[valid ? p : 0u];
-            valid = valid && (int)pr.i0 <= ie && (int)pr.i1 >= i0 && (int)pr.j0 <= je &&
-                    (int)pr.j1 >= j0;
-            const int klo = pr.k0 - kb > 0 ? pr.k0 - kb : 0;
-            const int khi = pr.k1 - kb < SZ - 1 ? pr.k1 - kb : SZ - 1;
-            zmask = valid && klo <= khi ? (2u << khi) - (1u << klo) : 0u;
-        }
+        const uint32_t q = valid ? p : 0u;
+        const StrutRec<float> r = recs[q];
+        // (one 16-byte load: i0 | i1 << 16, j0 | j1 << 16, k0, k1)
+        const uint4 pr = reinterpret_cast<const uint4*>(a.pranges)[q];
         // the strut's direction and length (float64, from the binning)
-        const double4 ln = a.line[valid ? p : 0u];
-        const double ax = (double)r.ax, ay = (double)r.ay, az = (double)r.az;
-        const double Rs = SR ? (double)r.pad : a.R;
+        const double4 ln = a.line[q];
         // lengths in units of R / rho (rho <= 1: the weight folded into the
         // closed form, which scales with the fifth power of length)
-        const double rho = (double)a.rho[valid ? p : 0u];
+        const double rho = (double)a.rho[q];
+        p_next = a.ids[idx + kWave < end ? idx + kWave : end - 1u];
+        uint32_t zmask = 0u;
+        {
+            valid = valid && (int)(pr.x & 0xffffu) <= ie && (int)(pr.x >> 16) >= i0 &&
+                    (int)(pr.y & 0xffffu) <= je && (int)(pr.y >> 16) >= j0;
+            const int pk0 = (int)pr.z, pk1 = (int)pr.w;
+            const int klo = pk0 - kb > 0 ? pk0 - kb : 0;
+            const int khi = pk1 - kb < SZ - 1 ? pk1 - kb : SZ - 1;
+            zmask = valid && klo <= khi ? (2u << khi) - (1u << klo) : 0u;
+        }
+        const double ax = (double)r.ax, ay = (double)r.ay, az = (double)r.az;
+        const double Rs = SR ? (double)r.pad : a.R;
         const double iR = rho / Rs, iR2 = iR * iR;
         // the reach test below runs in float32 against a support widened by
         // 1e-5 relative, far above its rounding, so it never drops a strut
