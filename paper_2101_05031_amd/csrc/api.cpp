@@ -153,6 +153,7 @@ namespace {
 struct Group {
     int32_t sa, sb;
     uint64_t pairs;
+    uint64_t cells;                   // (slab, tile row, column segment, strut) cells, <= pairs
     uint32_t n_active;
     uint32_t n_buckets;
 };
@@ -311,9 +312,11 @@ struct lattice_bins {
     // resident group
     uint32_t* active[2] = {nullptr, nullptr};
     uint32_t* eoff = nullptr;
+    uint32_t* toff = nullptr;          // [cap_active + 1] row-segment cells per active strut
+    uint32_t* roffs = nullptr;         // CSR of the row segments of the largest group
     uint32_t* offsets = nullptr;
     const uint32_t* ids = nullptr;     // bucket entries (points into v0 or v1)
-    const uint32_t* skeys = nullptr;   // their sorted bucket keys (k0 or k1)
+    uint32_t* skeys = nullptr;         // their bucket keys, written for the adjoint (k0 or k1)
     uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
     uint32_t* tmp = nullptr;
     uint32_t* blk = nullptr;
@@ -486,9 +489,18 @@ hipStream_t S(void* s) { return (hipStream_t)s; }
 
 lsl_status plan_groups(lattice_bins* b, const std::vector<uint32_t>& cnt_lo,
                        const std::vector<uint32_t>& cnt_hi,
-                       const std::vector<unsigned long long>& diff) {
+                       const std::vector<unsigned long long>& diff,
+                       const std::vector<uint32_t>& rdiff) {
     const int ns = b->n_slabs;
     b->pairs_slab.assign(ns, 0);
+    // (strut, tile row, column segment) cells per slab: a slab's cells are no
+    // more than its pairs (< 2^32), so the modular running sum is exact
+    std::vector<uint32_t> rows_slab(ns, 0u);
+    uint32_t rrun = 0;
+    for (int s = 0; s < ns; ++s) {
+        rrun += rdiff[s];
+        rows_slab[s] = rrun;
+    }
     b->win_end.assign(ns, 0);
     b->gone.assign(ns, 0);
     uint64_t run = 0;
@@ -516,6 +528,8 @@ lsl_status plan_groups(lattice_bins* b, const std::vector<uint32_t>& cnt_lo,
             p += b->pairs_slab[++e];
         g.sb = e;
         g.pairs = p;
+        g.cells = 0;
+        for (int q = s; q <= e; ++q) g.cells += rows_slab[q];
         if (p >= 0xfffffff0ull) {
             set_error("one slab holds more than 2^32 (slab, tile, strut) pairs; use larger tiles "
                       "or thinner slabs");
@@ -561,8 +575,11 @@ lsl_status ensure_group(lattice_bins* b, int g, hipStream_t st) {
     gb.ntx = b->ntx;
     gb.nty = b->nty;
     gb.n_pairs = (uint32_t)G.pairs;
+    gb.n_cells = (uint32_t)G.cells;
     gb.n_buckets = G.n_buckets;
     gb.eoff = b->eoff;
+    gb.toff = b->toff;
+    gb.roffs = b->roffs;
     gb.offsets = b->offsets;
     gb.keys_out = &b->skeys;
     gb.ids_out = &b->ids;
@@ -737,7 +754,7 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
     const size_t En = std::max<size_t>(E, 1);
     if ((s = b->alloc_t(&klo, En)) || (s = b->alloc_t(&vals, En)) || (s = b->alloc_t(&ka, En)) ||
         (s = b->alloc_t(&va, En)) || (s = b->alloc_t(&rid, En)) || (s = b->alloc_t(&prid, En)) ||
-        (s = b->alloc_t(&cnt, 2 * (size_t)ns + 4)) || (s = b->alloc_t(&diff, (size_t)ns + 1)) ||
+        (s = b->alloc_t(&cnt, 2 * (size_t)ns + 4)) || (s = b->alloc_t(&diff, 2 * ((size_t)ns + 1))) ||
         (s = b->alloc_t(&stmp, radix_tmp_elems(En))))
         return fail(s);
     if (L->dtype == LSL_F64 && (s = b->alloc_t(&khi, En))) return fail(s);
@@ -749,7 +766,7 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
     uint32_t* counters = cnt + 2 * ns;   // [0] n_binned, [1] err, [2] ~smallest support,
                                          // [3] largest r R
     if ((s = fill_u32(cnt, 0u, 2 * (size_t)ns + 4, st)) ||
-        (s = fill_bytes0(diff, ((size_t)ns + 1) * 8, st)))
+        (s = fill_bytes0(diff, 2 * ((size_t)ns + 1) * 8, st)))
         return fail(s);
     PrepArgs pa{};
     pa.nodes = L->nodes;
@@ -778,6 +795,7 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
     pa.cnt_lo = cnt_lo;
     pa.cnt_hi = cnt_hi;
     pa.pair_diff = diff;
+    pa.row_diff = (uint32_t*)(diff + ns + 1);
     pa.n_binned = counters;
     pa.err = counters + 1;
     pa.min_support = counters + 2;
@@ -824,9 +842,13 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
     // read the plan back
     std::vector<uint32_t> h_cnt(2 * (size_t)ns + 4);
     std::vector<unsigned long long> h_diff((size_t)ns + 1);
+    std::vector<uint32_t> h_rdiff((size_t)ns + 1);
     hipError_t he = hipMemcpyAsync(h_cnt.data(), cnt, h_cnt.size() * 4, hipMemcpyDeviceToHost, st);
     if (he == hipSuccess)
         he = hipMemcpyAsync(h_diff.data(), diff, h_diff.size() * 8, hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess)
+        he = hipMemcpyAsync(h_rdiff.data(), diff + ns + 1, h_rdiff.size() * 4,
+                            hipMemcpyDeviceToHost, st);
     if (he == hipSuccess) he = hipStreamSynchronize(st);
     if (he != hipSuccess) {
         set_error(std::string("lattice_bin: ") + hipGetErrorString(he));
@@ -874,7 +896,7 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
     }
     std::vector<uint32_t> vlo(h_cnt.begin(), h_cnt.begin() + ns);
     std::vector<uint32_t> vhi(h_cnt.begin() + ns, h_cnt.begin() + 2 * ns);
-    if ((s = plan_groups(b, vlo, vhi, h_diff))) return fail(s);
+    if ((s = plan_groups(b, vlo, vhi, h_diff, h_rdiff))) return fail(s);
 
     // ---- per-strut arrays in edge-list order
     const size_t nb = std::max<size_t>(b->n_binned, 1);
@@ -923,23 +945,26 @@ lsl_status lattice_bin(const lsl_lattice* L, const lsl_grid* G, const lsl_bin_pa
         b->release(p);
 
     // ---- resident-group buffers sized for the largest group
-    size_t max_act = 1, max_pairs = 1, max_bk = 1, max_cand = 1;
+    size_t max_act = 1, max_pairs = 1, max_bk = 1, max_cand = 1, max_rows = 1;
     for (size_t g = 0; g < b->groups.size(); ++g) {
         const Group& Gr = b->groups[g];
         max_act = std::max<size_t>(max_act, Gr.n_active);
         max_pairs = std::max<size_t>(max_pairs, Gr.pairs);
         max_bk = std::max<size_t>(max_bk, Gr.n_buckets);
+        max_rows = std::max<size_t>(max_rows, (size_t)(Gr.sb - Gr.sa + 1) * (size_t)b->nty *
+                                                  (size_t)((b->ntx + kSegTiles - 1) / kSegTiles));
         max_cand = std::max<size_t>(max_cand, b->win_end[Gr.sb]);
     }
     b->cap_active = max_act;
     b->cap_pairs = max_pairs;
     b->cap_buckets = max_bk;
     if ((s = b->alloc_t(&b->active[0], max_act)) || (s = b->alloc_t(&b->active[1], max_act)) ||
-        (s = b->alloc_t(&b->eoff, max_act + 1)) || (s = b->alloc_t(&b->offsets, max_bk + 1)) ||
+        (s = b->alloc_t(&b->eoff, max_act + 1)) || (s = b->alloc_t(&b->toff, max_act + 1)) ||
+        (s = b->alloc_t(&b->roffs, max_rows + 1)) || (s = b->alloc_t(&b->offsets, max_bk + 1)) ||
         (s = b->alloc_t(&b->k0, max_pairs)) ||
         (s = b->alloc_t(&b->v0, max_pairs)) || (s = b->alloc_t(&b->k1, max_pairs)) ||
         (s = b->alloc_t(&b->v1, max_pairs)) ||
-        (s = b->alloc_t(&b->tmp, group_tmp_elems(max_pairs, max_act, max_cand))) ||
+        (s = b->alloc_t(&b->tmp, group_tmp_elems(max_pairs, max_act, max_cand, max_bk))) ||
         (s = b->alloc_t(&b->blk, max_cand / 2048 + 2)) || (s = b->alloc_t(&b->stats, 4)))
         return fail(s);
     if (!b->groups.empty() && (s = ensure_group(b, 0, st))) return fail(s);
@@ -1502,6 +1527,8 @@ lsl_status slice_field_backward(lattice_bins* b, int32_t k0, int32_t nk, const v
             if (b->emi_group != g) {
                 EmiArgs ea{};
                 ea.keys = b->skeys;
+                ea.offsets = b->offsets;
+                ea.n_buckets = G.n_buckets;
                 ea.ids = b->ids;
                 ea.active = b->active[b->cur_buf];
                 ea.eoff = b->eoff;

@@ -35,6 +35,14 @@ struct SRange {
     int32_t s0, s1;
 };
 
+// The binning groups a tile row's columns in segments of this many tiles.
+constexpr int kSegTiles = 8;
+
+// (slab, tile row, column segment) cells of a box, per slab
+__host__ __device__ inline uint32_t row_segments(const SRange& r) {
+    return (uint32_t)(r.ty1 - r.ty0 + 1) * (uint32_t)(r.tx1 / kSegTiles - r.tx0 / kSegTiles + 1);
+}
+
 // The pixel columns, rows and planes of the same box (inclusive; the
 // binning's integers, from which the tile and slab ranges follow).
 struct PRange {

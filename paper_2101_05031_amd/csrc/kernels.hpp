@@ -25,6 +25,8 @@ struct PrepArgs {
     uint32_t* cnt_lo;                 // [n_slabs] struts whose first slab is s
     uint32_t* cnt_hi;                 // [n_slabs] struts whose last slab is s
     unsigned long long* pair_diff;    // [n_slabs + 1] difference array of pairs
+    uint32_t* row_diff;               // [n_slabs + 1] difference array of (strut, tile row,
+                                      // column segment) cells, modulo 2^32
     uint32_t* n_binned;
     uint32_t* err;                    // bit 0 index, 1 weight, 2 node, 3 support, 4 sigma
     uint32_t* min_support;            // ~(float bits) of the smallest binned support, max-reduced
@@ -76,25 +78,33 @@ struct GroupBuffers {
     int32_t sa, sb;                   // slabs of the group
     int32_t ntx, nty;
     uint32_t n_pairs;
+    uint32_t n_cells;                 // (slab, tile row, column segment, strut) cells,
+                                      // <= n_pairs
     uint32_t n_buckets;
     // outputs
-    uint32_t* eoff;                   // [n_active + 1]
+    uint32_t* eoff;                   // [n_active + 1] pairs before each active strut
+    uint32_t* toff;                   // [n_active + 1] scratch: cells before each
+    uint32_t* roffs;                  // [(sb - sa + 1) nty nseg + 1] scratch: row-segment CSR
     uint32_t* offsets;                // [n_buckets + 1]
-    uint32_t* k0; uint32_t* v0; uint32_t* k1; uint32_t* v1;   // [n_pairs] sort buffers
-    const uint32_t** keys_out;        // out: sorted bucket keys (k0 or k1)
+    uint32_t* k0; uint32_t* v0; uint32_t* k1; uint32_t* v1;   // [n_pairs] work buffers
+    uint32_t** keys_out;              // out: the buffer group_emi fills with the entries'
+                                      // bucket keys (k0 or k1)
     const uint32_t** ids_out;         // out: bucket entries, edge-list positions (v0 or v1)
     uint32_t* tmp;                    // scan / sort scratch
     uint32_t* blk;                    // compaction block counts
 };
-size_t group_tmp_elems(size_t n_pairs, size_t n_active, size_t n_cand);
+size_t group_tmp_elems(size_t n_pairs, size_t n_active, size_t n_cand, size_t n_buckets);
 lsl_status bin_group(const GroupBuffers& g, hipStream_t st);
 
 // Emission index of every bucket entry of the resident group (the position
 // of the (strut, bucket) pair in the strut-major emission order), rebuilt
-// from the sorted keys, the entry's strut and the strut's box.  inv
-// ([n_binned], scratch) receives the inverse of the active list.
+// from the entry's bucket, its strut and the strut's box.  keys receives
+// every entry's bucket (from the offsets), inv ([n_binned], scratch) the
+// inverse of the active list.
 struct EmiArgs {
-    const uint32_t* keys;             // [n_pairs] sorted bucket keys
+    uint32_t* keys;                   // [n_pairs] out: bucket of each entry
+    const uint32_t* offsets;          // [n_buckets + 1]
+    uint32_t n_buckets;
     const uint32_t* ids;              // [n_pairs] edge-list positions
     const uint32_t* active;           // [n_active]
     const uint32_t* eoff;             // [n_active + 1]

@@ -47,6 +47,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
     __shared__ uint32_t h_lo[kLdsSlabs], h_hi[kLdsSlabs];
     __shared__ unsigned long long h_pairs[kLdsSlabs + 1];
+    __shared__ uint32_t h_rows[kLdsSlabs + 1];   // modulo 2^32: a slab's rows are < 2^32
     __shared__ uint32_t h_n;
     const bool lds = a.n_slabs <= kLdsSlabs;
     if (lds) {
@@ -54,103 +55,139 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
             h_lo[i] = 0u;
             h_hi[i] = 0u;
             h_pairs[i] = 0ull;
+            h_rows[i] = 0u;
         }
         if (threadIdx.x == 0) {
             h_pairs[a.n_slabs] = 0ull;
+            h_rows[a.n_slabs] = 0u;
             h_n = 0u;
         }
         __syncthreads();
     }
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = e < a.n_edges;
-    bool binned = false;
-    SRange rg{0, 0, 0, 0, 0, -1};
-    PRange pr{0, 0, 0, 0, 0, -1};
-    uint32_t klo = 0xffffffffu, khi = 0xffffffffu;
-    unsigned long long ntile = 0;
-    float rs_binned = 0.0f;             // the support of a binned strut
-    float wr_binned = 0.0f;             // and its weight times its support
-    if (live) {
-        const int32_t ia = a.edges[2 * e], ib = a.edges[2 * e + 1];
-        const T* nd = (const T*)a.nodes;
-        const T w = ((const T*)a.weight)[e];
-        bool bad = false;
-        if (ia < 0 || ib < 0 || (int64_t)ia >= a.n_nodes || (int64_t)ib >= a.n_nodes) {
-            atomicOr(a.err, 1u);
-            bad = true;
-        }
-        if (!(w >= T(0)) || !isfinite((double)w)) {
-            atomicOr(a.err, 2u);
-            bad = true;
-        }
-        double Rs = a.R;                 // this strut's support
-        if (a.support) {
-            Rs = (double)((const T*)a.support)[e];
-            if (!(Rs > 0.0) || !isfinite(Rs)) {
-                atomicOr(a.err, 8u);
+    // each block takes a contiguous range of edges (few slabs per block's
+    // histograms, flushed once at the end)
+    const int64_t per_block = (a.n_edges + gridDim.x - 1) / gridDim.x;
+    const int64_t e_beg = (int64_t)blockIdx.x * per_block;
+    const int64_t e_end = e_beg + per_block < a.n_edges ? e_beg + per_block : a.n_edges;
+    uint32_t inv_acc = 0u, wr_acc = 0u;     // smallest support, largest r R (as bits)
+    for (int64_t e = e_beg + threadIdx.x; e < e_end; e += blockDim.x) {
+        bool binned = false;
+        SRange rg{0, 0, 0, 0, 0, -1};
+        PRange pr{0, 0, 0, 0, 0, -1};
+        uint32_t klo = 0xffffffffu, khi = 0xffffffffu;
+        unsigned long long ntile = 0;
+        uint32_t nrow = 0;
+        float rs_binned = 0.0f;             // the support of a binned strut
+        float wr_binned = 0.0f;             // and its weight times its support
+        {
+            const int32_t ia = a.edges[2 * e], ib = a.edges[2 * e + 1];
+            const T* nd = (const T*)a.nodes;
+            const T w = ((const T*)a.weight)[e];
+            bool bad = false;
+            if (ia < 0 || ib < 0 || (int64_t)ia >= a.n_nodes || (int64_t)ib >= a.n_nodes) {
+                atomicOr(a.err, 1u);
                 bad = true;
             }
-        }
-        if (!bad && a.max_r_over_sigma > 0.0 && !(Rs <= a.max_r_over_sigma * a.sigma)) {
-            atomicOr(a.err, 16u);
-            bad = true;
-        }
-        if (!bad) {
-            const double ax = (double)nd[3 * ia], ay = (double)nd[3 * ia + 1],
-                         az = (double)nd[3 * ia + 2];
-            const double bx = (double)nd[3 * ib], by = (double)nd[3 * ib + 1],
-                         bz = (double)nd[3 * ib + 2];
-            if (!isfinite(ax) || !isfinite(ay) || !isfinite(az) || !isfinite(bx) ||
-                !isfinite(by) || !isfinite(bz)) {
-                atomicOr(a.err, 4u);
-            } else if ((w != T(0) || a.keep_zero) && !(ax == bx && ay == by && az == bz)) {
-                const AxisRange rz = axis_range(fmin(az, bz) - Rs, fmax(az, bz) + Rs, a.z0,
-                                                a.inv_dz, a.S);
-                const AxisRange rx = axis_range(fmin(ax, bx) - Rs, fmax(ax, bx) + Rs, a.x0,
-                                                a.inv_dx, a.W);
-                const AxisRange ry = axis_range(fmin(ay, by) - Rs, fmax(ay, by) + Rs, a.y0,
-                                                a.inv_dy, a.H);
-                if (rz.ok && rx.ok && ry.ok) {
-                    binned = true;
-                    rs_binned = (float)Rs;
-                    wr_binned = (float)((double)w * Rs);
-                    pr.i0 = (uint16_t)rx.i0;
-                    pr.i1 = (uint16_t)rx.i1;
-                    pr.j0 = (uint16_t)ry.i0;
-                    pr.j1 = (uint16_t)ry.i1;
-                    pr.k0 = rz.i0;
-                    pr.k1 = rz.i1;
-                    rg.s0 = rz.i0 / a.slab;
-                    rg.s1 = rz.i1 / a.slab;
-                    rg.tx0 = (uint16_t)(rx.i0 / a.tile);
-                    rg.tx1 = (uint16_t)(rx.i1 / a.tile);
-                    rg.ty0 = (uint16_t)(ry.i0 / a.tile);
-                    rg.ty1 = (uint16_t)(ry.i1 / a.tile);
-                    ntile = (unsigned long long)(rg.tx1 - rg.tx0 + 1) *
-                            (unsigned long long)(rg.ty1 - rg.ty0 + 1);
-                    const T zlo = nd[3 * ia + 2] < nd[3 * ib + 2] ? nd[3 * ia + 2]
-                                                                  : nd[3 * ib + 2];
-                    if (sizeof(T) == 4) {
-                        klo = float_key((float)zlo);
-                    } else {
-                        const uint64_t k = double_key((double)zlo);
-                        klo = (uint32_t)k;
-                        khi = (uint32_t)(k >> 32);
+            if (!(w >= T(0)) || !isfinite((double)w)) {
+                atomicOr(a.err, 2u);
+                bad = true;
+            }
+            double Rs = a.R;                 // this strut's support
+            if (a.support) {
+                Rs = (double)((const T*)a.support)[e];
+                if (!(Rs > 0.0) || !isfinite(Rs)) {
+                    atomicOr(a.err, 8u);
+                    bad = true;
+                }
+            }
+            if (!bad && a.max_r_over_sigma > 0.0 && !(Rs <= a.max_r_over_sigma * a.sigma)) {
+                atomicOr(a.err, 16u);
+                bad = true;
+            }
+            if (!bad) {
+                const double ax = (double)nd[3 * ia], ay = (double)nd[3 * ia + 1],
+                             az = (double)nd[3 * ia + 2];
+                const double bx = (double)nd[3 * ib], by = (double)nd[3 * ib + 1],
+                             bz = (double)nd[3 * ib + 2];
+                if (!isfinite(ax) || !isfinite(ay) || !isfinite(az) || !isfinite(bx) ||
+                    !isfinite(by) || !isfinite(bz)) {
+                    atomicOr(a.err, 4u);
+                } else if ((w != T(0) || a.keep_zero) && !(ax == bx && ay == by && az == bz)) {
+                    const AxisRange rz = axis_range(fmin(az, bz) - Rs, fmax(az, bz) + Rs, a.z0,
+                                                    a.inv_dz, a.S);
+                    const AxisRange rx = axis_range(fmin(ax, bx) - Rs, fmax(ax, bx) + Rs, a.x0,
+                                                    a.inv_dx, a.W);
+                    const AxisRange ry = axis_range(fmin(ay, by) - Rs, fmax(ay, by) + Rs, a.y0,
+                                                    a.inv_dy, a.H);
+                    if (rz.ok && rx.ok && ry.ok) {
+                        binned = true;
+                        rs_binned = (float)Rs;
+                        wr_binned = (float)((double)w * Rs);
+                        pr.i0 = (uint16_t)rx.i0;
+                        pr.i1 = (uint16_t)rx.i1;
+                        pr.j0 = (uint16_t)ry.i0;
+                        pr.j1 = (uint16_t)ry.i1;
+                        pr.k0 = rz.i0;
+                        pr.k1 = rz.i1;
+                        rg.s0 = rz.i0 / a.slab;
+                        rg.s1 = rz.i1 / a.slab;
+                        rg.tx0 = (uint16_t)(rx.i0 / a.tile);
+                        rg.tx1 = (uint16_t)(rx.i1 / a.tile);
+                        rg.ty0 = (uint16_t)(ry.i0 / a.tile);
+                        rg.ty1 = (uint16_t)(ry.i1 / a.tile);
+                        ntile = (unsigned long long)(rg.tx1 - rg.tx0 + 1) *
+                                (unsigned long long)(rg.ty1 - rg.ty0 + 1);
+                        nrow = row_segments(rg);
+                        const T zlo = nd[3 * ia + 2] < nd[3 * ib + 2] ? nd[3 * ia + 2]
+                                                                      : nd[3 * ib + 2];
+                        if (sizeof(T) == 4) {
+                            klo = float_key((float)zlo);
+                        } else {
+                            const uint64_t k = double_key((double)zlo);
+                            klo = (uint32_t)k;
+                            khi = (uint32_t)(k >> 32);
+                        }
                     }
                 }
             }
+            a.key_lo[e] = klo;
+            if (sizeof(T) == 8) a.key_hi[e] = khi;
+            if (a.key_s0) a.key_s0[e] = binned ? (uint32_t)rg.s0 : (uint32_t)a.n_slabs;
+            a.vals[e] = (uint32_t)e;
+            a.ranges[e] = rg;
+            a.pranges[e] = pr;
         }
-        a.key_lo[e] = klo;
-        if (sizeof(T) == 8) a.key_hi[e] = khi;
-        if (a.key_s0) a.key_s0[e] = binned ? (uint32_t)rg.s0 : (uint32_t)a.n_slabs;
-        a.vals[e] = (uint32_t)e;
-        a.ranges[e] = rg;
-        a.pranges[e] = pr;
+        if (binned) {
+            // (positive floats order as their bits; the complement turns the
+            // minimum into a maximum from zero)
+            const uint32_t iv = ~__float_as_uint(rs_binned), wv = __float_as_uint(wr_binned);
+            inv_acc = iv > inv_acc ? iv : inv_acc;
+            wr_acc = wv > wr_acc ? wv : wr_acc;
+            // plan histograms: struts starting / ending in each slab, and
+            // difference arrays of (slab, tile) pairs and of (slab, tile row,
+            // column segment) cells
+            if (lds) {
+                atomicAdd(&h_lo[rg.s0], 1u);
+                atomicAdd(&h_hi[rg.s1], 1u);
+                atomicAdd(&h_pairs[rg.s0], ntile);
+                atomicAdd(&h_pairs[rg.s1 + 1], 0ull - ntile);
+                atomicAdd(&h_rows[rg.s0], nrow);
+                atomicAdd(&h_rows[rg.s1 + 1], 0u - nrow);
+                atomicAdd(&h_n, 1u);
+            } else {
+                atomicAdd(&a.cnt_lo[rg.s0], 1u);
+                atomicAdd(&a.cnt_hi[rg.s1], 1u);
+                atomicAdd(&a.pair_diff[rg.s0], ntile);
+                atomicAdd(&a.pair_diff[rg.s1 + 1], 0ull - ntile);
+                atomicAdd(&a.row_diff[rg.s0], nrow);
+                atomicAdd(&a.row_diff[rg.s1 + 1], 0u - nrow);
+                atomicAdd(a.n_binned, 1u);
+            }
+        }
     }
-    // the smallest support of a binned strut (positive floats order as their
-    // bits; the complement turns the minimum into a maximum from zero)
+    // the smallest support of a binned strut
     if (a.support && a.min_support) {
-        uint32_t inv = binned ? ~__float_as_uint(rs_binned) : 0u;
+        uint32_t inv = inv_acc;
         for (int d = 32; d >= 1; d >>= 1) {
             const uint32_t o = (uint32_t)__shfl_xor((int)inv, d, kWave);
             inv = inv > o ? inv : o;
@@ -159,39 +196,26 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
     }
     // the largest r R of a binned strut (the float32 field kernel's scale)
     if (a.max_wr) {
-        uint32_t v = binned ? __float_as_uint(wr_binned) : 0u;
+        uint32_t v = wr_acc;
         for (int d = 32; d >= 1; d >>= 1) {
             const uint32_t o = (uint32_t)__shfl_xor((int)v, d, kWave);
             v = v > o ? v : o;
         }
         if ((threadIdx.x & (kWave - 1)) == 0 && v != 0u) atomicMax(a.max_wr, v);
     }
-    // plan histograms: struts starting / ending in each slab, and a
-    // difference array of (slab, tile) pairs
     if (lds) {
-        if (binned) {
-            atomicAdd(&h_lo[rg.s0], 1u);
-            atomicAdd(&h_hi[rg.s1], 1u);
-            atomicAdd(&h_pairs[rg.s0], ntile);
-            atomicAdd(&h_pairs[rg.s1 + 1], 0ull - ntile);
-            atomicAdd(&h_n, 1u);
-        }
         __syncthreads();
         for (int i = threadIdx.x; i < a.n_slabs; i += blockDim.x) {
             if (h_lo[i]) atomicAdd(&a.cnt_lo[i], h_lo[i]);
             if (h_hi[i]) atomicAdd(&a.cnt_hi[i], h_hi[i]);
             if (h_pairs[i]) atomicAdd(&a.pair_diff[i], h_pairs[i]);
+            if (h_rows[i]) atomicAdd(&a.row_diff[i], h_rows[i]);
         }
         if (threadIdx.x == 0) {
             if (h_pairs[a.n_slabs]) atomicAdd(&a.pair_diff[a.n_slabs], h_pairs[a.n_slabs]);
+            if (h_rows[a.n_slabs]) atomicAdd(&a.row_diff[a.n_slabs], h_rows[a.n_slabs]);
             if (h_n) atomicAdd(a.n_binned, h_n);
         }
-    } else if (binned) {
-        atomicAdd(&a.cnt_lo[rg.s0], 1u);
-        atomicAdd(&a.cnt_hi[rg.s1], 1u);
-        atomicAdd(&a.pair_diff[rg.s0], ntile);
-        atomicAdd(&a.pair_diff[rg.s1 + 1], 0ull - ntile);
-        atomicAdd(a.n_binned, 1u);
     }
 }
 
@@ -238,7 +262,14 @@ __global__ void k_gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t*
 
 lsl_status launch_prep(int dtype, const PrepArgs& a, hipStream_t st) {
     if (a.n_edges == 0) return LSL_OK;
-    const unsigned g = (unsigned)((a.n_edges + 255) / 256);
+    int dev = 0, cus = 0;
+    LSL_HIP(hipGetDevice(&dev));
+    LSL_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    // four blocks per compute unit (the histograms' LDS allows that many),
+    // each over a contiguous range of at least 256 edges
+    const int64_t by_edges = (a.n_edges + 255) / 256;
+    const int64_t cap = 4 * (int64_t)(cus > 0 ? cus : 1);
+    const unsigned g = (unsigned)(by_edges < cap ? by_edges : cap);
     if (dtype == LSL_F32)
         k_prep<float><<<g, 256, 0, st>>>(a);
     else
