@@ -204,6 +204,14 @@ __device__ __forceinline__ float2 seg_end(const int8_t* g, int i, int j, int32_t
     return make_float2((float)x, (float)((T)j + (C - gp) / (gq - gp)));
 }
 
+// A boundary cell of the emit pass: its first segment's position, column,
+// and row | case << 28.
+struct MsItem {
+    uint64_t o;
+    uint32_t ci, cj;
+};
+constexpr uint32_t kItems = 128;       // items per wave and round
+
 template <bool SUB, typename T>
 __global__ __launch_bounds__(kMThreads) void k_strip_emit(const uint64_t* img, int32_t nk,
                                                           int32_t W, int32_t H,
@@ -218,6 +226,7 @@ __global__ __launch_bounds__(kMThreads) void k_strip_emit(const uint64_t* img, i
     const uint64_t k = wave / (uint64_t)nby;
     const int by = (int)(wave % (uint64_t)nby);
     const uint64_t* P = img + k * (uint64_t)nby * (uint64_t)nbx;
+    __shared__ MsItem s_items[kMThreads / kWave][kItems];
 
     // per-row totals of the strip (two rows per 64-bit word, 32 bits each)
     uint64_t t2[4] = {0, 0, 0, 0};
@@ -239,56 +248,84 @@ __global__ __launch_bounds__(kMThreads) void k_strip_emit(const uint64_t* img, i
             run += t >> 32;
         }
     }
+    // per 64-block chunk: the boundary cells as items in LDS (each with its
+    // case and the position of its first segment), then one item per lane
+    MsItem* items = s_items[threadIdx.x / kWave];
+    const T* f = SUB ? (const T*)sp.field + k * (uint64_t)W * (uint64_t)H : nullptr;
     for (int bx0 = 0; bx0 < nbx; bx0 += kWave) {
         const int bx = bx0 + lane;
         CellMasks c{};
         if (bx < nbx) c = cell_masks(P, nbx, nby, bx, by, W, H);
-        const int i0 = 8 * bx, j0 = 8 * by;
         // this chunk's per-row counts, four rows of 16 bits per word (a row
-        // of a 64-block chunk holds at most 2 x 8 x 64 = 1024 segments)
+        // of a 64-block chunk holds at most 2 x 8 x 64 = 1024 segments),
+        // their exclusive prefix over the lanes and their totals
+        uint64_t ex[2], all[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             uint64_t v = 0;
 #pragma unroll
             for (int h = 0; h < 4; ++h) v |= (uint64_t)row_count(c, 4 * q + h) << (16 * h);
             const uint64_t inc = wave_incl(v, lane);
-            const uint64_t all = __shfl(inc, kWave - 1, kWave);
-            const uint64_t ex = inc - v;
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                const int r = 4 * q + h;
-                uint64_t o = pos[r] + ((ex >> (16 * h)) & 0xffffull);
-                uint32_t mb = (uint32_t)(c.m >> (8 * r)) & 0xffu;
+            all[q] = __shfl(inc, kWave - 1, kWave);
+            ex[q] = inc - v;
+        }
+        if (ballot64(c.m != 0ull) != 0ull) {
+            // the lane's cells are items exl .. exl + nl - 1 (lane-major)
+            const uint32_t nl = (uint32_t)__popcll(c.m);
+            const uint64_t incl = wave_incl((uint64_t)nl, lane);
+            const uint32_t n_items = (uint32_t)__shfl(incl, kWave - 1, kWave);
+            const uint32_t exl = (uint32_t)incl - nl;
+            for (uint32_t R = 0; R < n_items; R += kItems) {
+                uint64_t mb = c.m;
+                uint32_t t = exl;
+                int rcur = -1;
+                uint64_t o = 0;
                 while (mb) {
-                    const int cc = __ffs(mb) - 1;
-                    mb &= mb - 1u;
-                    const int bit = 8 * r + cc;
+                    const int bit = __ffsll((unsigned long long)mb) - 1;
+                    mb &= mb - 1ull;
+                    const int r = bit >> 3;
+                    if (r != rcur) {
+                        o = pos[r] + ((ex[r >> 2] >> (16 * (r & 3))) & 0xffffull);
+                        rcur = r;
+                    }
                     const int cs = (int)(((c.b0 >> bit) & 1ull) | (((c.b1 >> bit) & 1ull) << 1) |
                                          (((c.b2 >> bit) & 1ull) << 2) |
                                          (((c.b3 >> bit) & 1ull) << 3));
+                    if (t >= R && t < R + kItems)
+                        items[t - R] = MsItem{o, (uint32_t)(8 * bx + (bit & 7)),
+                                              (uint32_t)(8 * by + r) | ((uint32_t)cs << 28)};
+                    o += (uint64_t)seg_count(cs);
+                    ++t;
+                }
+                __builtin_amdgcn_wave_barrier();
+                const uint32_t m = n_items - R < kItems ? n_items - R : kItems;
+                for (uint32_t q = (uint32_t)lane; q < m; q += kWave) {
+                    const MsItem it = items[q];
+                    const int cs = (int)(it.cj >> 28);
+                    const int ci = (int)it.ci, cj = (int)(it.cj & 0x0fffffffu);
                     const int n = seg_count(cs);
-                    const int ci = i0 + cc, cj = j0 + r;
-                    const T* f = SUB ? (const T*)sp.field + k * (uint64_t)W * (uint64_t)H : nullptr;
                     for (int sg = 0; sg < n; ++sg) {
-                        if ((int64_t)(o + sg) < capacity) {
+                        const uint64_t os = it.o + (uint64_t)sg;
+                        if ((int64_t)os < capacity) {
                             int8_t g[4];
                             seg_points(cs, sg, g);
                             uint32_t es = 0, ee = 0;
                             const float2 a = seg_end<SUB, T>(g, ci, cj, W, f, (T)sp.C, &es);
                             const float2 b = seg_end<SUB, T>(g + 2, ci, cj, W, f, (T)sp.C, &ee);
-                            segs[o + sg] = make_float4(a.x, a.y, b.x, b.y);
+                            segs[os] = make_float4(a.x, a.y, b.x, b.y);
                             if (SUB) {
-                                sp.edge_s[o + sg] = es;
-                                sp.edge_e[o + sg] = ee;
-                                sp.cell[o + sg] = (uint32_t)cj * (uint32_t)(W - 1) + (uint32_t)ci;
+                                sp.edge_s[os] = es;
+                                sp.edge_e[os] = ee;
+                                sp.cell[os] = (uint32_t)cj * (uint32_t)(W - 1) + (uint32_t)ci;
                             }
                         }
                     }
-                    o += (uint64_t)n;
                 }
-                pos[r] += (all >> (16 * h)) & 0xffffull;
+                __builtin_amdgcn_wave_barrier();
             }
         }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) pos[r] += (all[r >> 2] >> (16 * (r & 3))) & 0xffffull;
     }
 }
 
