@@ -120,43 +120,6 @@ __device__ __forceinline__ CellMasks cell_masks(const uint64_t* P, int nbx, int 
     return c;
 }
 
-// segments of row r (0..7) of a block: one per boundary cell, two per saddle
-__device__ __forceinline__ uint32_t row_count(const CellMasks& c, int r) {
-    return (uint32_t)(__popc((uint32_t)(c.m >> (8 * r)) & 0xffu) +
-                      __popc((uint32_t)(c.s >> (8 * r)) & 0xffu));
-}
-
-__global__ __launch_bounds__(kMThreads) void k_strip_count(const uint64_t* img, int32_t nk,
-                                                           int32_t W, int32_t H,
-                                                           unsigned long long* tot) {
-    const int lane = lane_id();
-    const int nbx = (W + 7) / 8, nby = (H + 7) / 8;
-    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    if (wave >= (uint64_t)nk * (uint64_t)nby) return;
-    const uint64_t k = wave / (uint64_t)nby;
-    const int by = (int)(wave % (uint64_t)nby);
-    const uint64_t* P = img + k * (uint64_t)nby * (uint64_t)nbx;
-    uint32_t cnt = 0;
-    for (int bx = lane; bx < nbx; bx += kWave) {
-        const CellMasks c = cell_masks(P, nbx, nby, bx, by, W, H);
-        cnt += (uint32_t)(__popcll(c.m) + __popcll(c.s));
-    }
-    for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d, kWave);
-    if (lane == 0) tot[wave] = cnt;
-}
-
-__global__ void k_ms_offsets(const unsigned long long* scan, uint32_t per_plane, int32_t nk,
-                             const unsigned long long* base, int64_t* offsets) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k <= nk) offsets[k] = (int64_t)(scan[(size_t)k * per_plane] + (base ? *base : 0ull));
-}
-
-// base += this call's total (the segments of several calls share one array)
-__global__ void k_ms_advance(unsigned long long* base, const unsigned long long* scan,
-                             size_t n) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *base += scan[n];
-}
-
 // inclusive prefix over the wave's lanes
 __device__ __forceinline__ uint64_t wave_incl(uint64_t v, int lane) {
 #pragma unroll
@@ -171,6 +134,57 @@ __device__ __forceinline__ uint64_t wave_total(uint64_t v) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
     return v;
+}
+
+// segments of row r (0..7) of a block: one per boundary cell, two per saddle
+__device__ __forceinline__ uint32_t row_count(const CellMasks& c, int r) {
+    return (uint32_t)(__popc((uint32_t)(c.m >> (8 * r)) & 0xffu) +
+                      __popc((uint32_t)(c.s >> (8 * r)) & 0xffu));
+}
+
+// Segments per strip (tot) and per row of the strip (rows: two rows per
+// word, 32 bits each, lower row in the low half).
+__global__ __launch_bounds__(kMThreads) void k_strip_count(const uint64_t* img, int32_t nk,
+                                                           int32_t W, int32_t H,
+                                                           unsigned long long* tot,
+                                                           unsigned long long* rows) {
+    const int lane = lane_id();
+    const int nbx = (W + 7) / 8, nby = (H + 7) / 8;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    if (wave >= (uint64_t)nk * (uint64_t)nby) return;
+    const uint64_t k = wave / (uint64_t)nby;
+    const int by = (int)(wave % (uint64_t)nby);
+    const uint64_t* P = img + k * (uint64_t)nby * (uint64_t)nbx;
+    uint64_t t2[4] = {0, 0, 0, 0};
+    for (int bx = lane; bx < nbx; bx += kWave) {
+        const CellMasks c = cell_masks(P, nbx, nby, bx, by, W, H);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            t2[q] += (uint64_t)row_count(c, 2 * q) | ((uint64_t)row_count(c, 2 * q + 1) << 32);
+    }
+    uint64_t cnt = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        t2[q] = wave_total(t2[q]);
+        cnt += (t2[q] & 0xffffffffull) + (t2[q] >> 32);
+    }
+    if (lane == 0) {
+        tot[wave] = cnt;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rows[4 * wave + q] = t2[q];
+    }
+}
+
+__global__ void k_ms_offsets(const unsigned long long* scan, uint32_t per_plane, int32_t nk,
+                             const unsigned long long* base, int64_t* offsets) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k <= nk) offsets[k] = (int64_t)(scan[(size_t)k * per_plane] + (base ? *base : 0ull));
+}
+
+// base += this call's total (the segments of several calls share one array)
+__global__ void k_ms_advance(unsigned long long* base, const unsigned long long* scan,
+                             size_t n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *base += scan[n];
 }
 
 // Optional outputs of the emit pass for sub-pixel segments and chaining:
@@ -216,6 +230,7 @@ template <bool SUB, typename T>
 __global__ __launch_bounds__(kMThreads) void k_strip_emit(const uint64_t* img, int32_t nk,
                                                           int32_t W, int32_t H,
                                                           const unsigned long long* scan,
+                                                          const unsigned long long* rows,
                                                           const unsigned long long* base,
                                                           float4* segs, int64_t capacity,
                                                           SubPix sp) {
@@ -228,20 +243,13 @@ __global__ __launch_bounds__(kMThreads) void k_strip_emit(const uint64_t* img, i
     const uint64_t* P = img + k * (uint64_t)nby * (uint64_t)nbx;
     __shared__ MsItem s_items[kMThreads / kWave][kItems];
 
-    // per-row totals of the strip (two rows per 64-bit word, 32 bits each)
-    uint64_t t2[4] = {0, 0, 0, 0};
-    for (int bx = lane; bx < nbx; bx += kWave) {
-        const CellMasks c = cell_masks(P, nbx, nby, bx, by, W, H);
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            t2[q] += (uint64_t)row_count(c, 2 * q) | ((uint64_t)row_count(c, 2 * q + 1) << 32);
-    }
     uint64_t pos[8];                 // next free position of each row, for this lane
     {
+        // the strip's per-row totals from the count pass
         uint64_t run = scan[wave] + (base ? *base : 0ull);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const uint64_t t = wave_total(t2[q]);
+            const uint64_t t = rows[4 * wave + q];
             pos[2 * q] = run;
             run += t & 0xffffffffull;
             pos[2 * q + 1] = run;
@@ -348,24 +356,35 @@ __global__ __launch_bounds__(kMThreads) void k_ms_codes(const uint64_t* img, int
 }
 
 // Row-major copy of block-major images: word w of row j holds pixels
-// 32 w .. 32 w + 31 (bit x % 32 is pixel x).
+// 32 w .. 32 w + 31 (bit x % 32 is pixel x).  A thread reads the four block
+// words of one output column and block row once and writes its eight rows
+// (byte r of each block word is row r of the block).
 __global__ __launch_bounds__(256) void k_bits_rows(const uint64_t* img, uint64_t n, int32_t W,
                                                    int32_t H, uint32_t* out) {
     const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const int words = (W + 31) / 32, nbx = (W + 7) / 8, nby = (H + 7) / 8;
     const int w = (int)(t % (uint64_t)words);
-    const uint64_t kj = t / (uint64_t)words;
-    const int j = (int)(kj % (uint64_t)H);
-    const uint64_t k = kj / (uint64_t)H;
-    const uint64_t* row = img + (k * (uint64_t)nby + (uint64_t)(j >> 3)) * (uint64_t)nbx;
-    uint32_t v = 0;
+    const uint64_t kb = t / (uint64_t)words;
+    const int by = (int)(kb % (uint64_t)nby);
+    const uint64_t k = kb / (uint64_t)nby;
+    const uint64_t* row = img + (k * (uint64_t)nby + (uint64_t)by) * (uint64_t)nbx;
+    uint64_t q[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int bx = 4 * w + q;
-        if (bx < nbx) v |= (uint32_t)((row[bx] >> (8 * (j & 7))) & 0xffull) << (8 * q);
+    for (int c = 0; c < 4; ++c) {
+        const int bx = 4 * w + c;
+        q[c] = bx < nbx ? row[bx] : 0ull;
     }
-    out[t] = v;
+    uint32_t* o = out + (k * (uint64_t)H + (uint64_t)(8 * by)) * (uint64_t)words + (uint64_t)w;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        if (8 * by + r < H) {
+            uint32_t v = 0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v |= (uint32_t)((q[c] >> (8 * r)) & 0xffull) << (8 * c);
+            o[(uint64_t)r * (uint64_t)words] = v;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -470,11 +489,19 @@ __global__ void k_poly_out(const int64_t* off, int32_t nk, uint64_t total, const
 
 }  // namespace
 
+// tmp: per-strip totals (n + 1, scanned in place), the scan's scratch, then
+// the per-row totals of every strip (4 words per strip)
 size_t contour_tmp_elems(int32_t nk, int32_t W, int32_t H) {
     (void)W;
-    const size_t n = (size_t)nk * (size_t)((H + 7) / 8) + 1;
-    return n + scan_tmp_elems(n);
+    const size_t n = (size_t)nk * (size_t)((H + 7) / 8);
+    return (n + 1) + scan_tmp_elems(n + 1) + 4 * n;
 }
+
+namespace {
+unsigned long long* strip_rows(unsigned long long* tmp, size_t n) {
+    return tmp + (n + 1) + scan_tmp_elems(n + 1);
+}
+}  // namespace
 
 lsl_status launch_contours_count(const uint64_t* img, int32_t nk, int32_t W, int32_t H,
                                  int64_t* offsets, uint8_t* codes, unsigned long long* tmp,
@@ -488,7 +515,8 @@ lsl_status launch_contours_count(const uint64_t* img, int32_t nk, int32_t W, int
     unsigned long long* tot = tmp;
     unsigned long long* stmp = tmp + n + 1;
     if (W > 1 && H > 1)
-        k_strip_count<<<(unsigned)((n + 3) / 4), kMThreads, 0, st>>>(img, nk, W, H, tot);
+        k_strip_count<<<(unsigned)((n + 3) / 4), kMThreads, 0, st>>>(img, nk, W, H, tot,
+                                                                     strip_rows(tmp, n));
     else
         LSL_TRY(fill_bytes0(tot, n * 8, st));
     LSL_HIP(hipGetLastError());
@@ -519,7 +547,8 @@ lsl_status launch_contours_emit(const uint64_t* img, int32_t nk, int32_t W, int3
     const size_t n = (size_t)nk * nby;
     if (W > 1 && H > 1)
         k_strip_emit<false, float><<<(unsigned)((n + 3) / 4), kMThreads, 0, st>>>(
-            img, nk, W, H, tmp, base, (float4*)segs, capacity, SubPix{});
+            img, nk, W, H, tmp, strip_rows((unsigned long long*)tmp, n), base, (float4*)segs,
+            capacity, SubPix{});
     if (base) k_ms_advance<<<1, 64, 0, st>>>(base, tmp, n);
     LSL_HIP(hipGetLastError());
     return LSL_OK;
@@ -527,7 +556,7 @@ lsl_status launch_contours_emit(const uint64_t* img, int32_t nk, int32_t W, int3
 
 lsl_status launch_bits_rows(const uint64_t* img, int32_t nk, int32_t W, int32_t H,
                             uint32_t* bits, hipStream_t st) {
-    const uint64_t n = (uint64_t)nk * (uint64_t)H * (uint64_t)((W + 31) / 32);
+    const uint64_t n = (uint64_t)nk * (uint64_t)((H + 7) / 8) * (uint64_t)((W + 31) / 32);
     if (n == 0) return LSL_OK;
     k_bits_rows<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(img, n, W, H, bits);
     LSL_HIP(hipGetLastError());
@@ -549,10 +578,12 @@ lsl_status launch_polylines(const uint64_t* img, const void* field, int dtype, d
     sp.cell = scratch + 2 * total;
     if (dtype == LSL_F32)
         k_strip_emit<true, float><<<(unsigned)((n + 3) / 4), kMThreads, 0, st>>>(
-            img, nk, W, H, tmp, nullptr, (float4*)segs, (int64_t)total, sp);
+            img, nk, W, H, tmp, strip_rows((unsigned long long*)tmp, n), nullptr,
+            (float4*)segs, (int64_t)total, sp);
     else
         k_strip_emit<true, double><<<(unsigned)((n + 3) / 4), kMThreads, 0, st>>>(
-            img, nk, W, H, tmp, nullptr, (float4*)segs, (int64_t)total, sp);
+            img, nk, W, H, tmp, strip_rows((unsigned long long*)tmp, n), nullptr,
+            (float4*)segs, (int64_t)total, sp);
     LSL_HIP(hipGetLastError());
     if (!chain || !rank) return LSL_OK;
     int32_t* succ = (int32_t*)(scratch + 3 * total);
