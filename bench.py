@@ -175,6 +175,9 @@ def main():
         p = api.slice_autotune(nodes, edges, weight, lat.R, lat.C, grid, slab=slab or 8,
                                **variant)
         tile, slab, autotuned = p["tile"], p["slab"], True
+        # return the candidates' cached buffers (sized for other tiles), so
+        # that the timed steps reuse buffers of their own sizes
+        api.cache_trim()
         print(f"[bench] autotuned tile {tile}, slab {slab}", file=sys.stderr, flush=True)
 
     def binit():
@@ -362,15 +365,16 @@ def main():
     peak = PEAK_FP64_VECTOR if dtype == torch.float64 else PEAK_FP32_VECTOR
     field_s = field_ms * 1e-3
     achieved = useful * FLOP_PER_USEFUL_PAIR / field_s if field_s > 0 else None
-    # HBM bytes per launch from the committed counter summary, for the kernels
-    # whose source has not changed since
+    # HBM bytes per launch from the committed counter summary, taken at this
+    # tile and slab, for the kernels whose source has not changed since
     traffic = {}
     tpath = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
     if os.path.exists(tpath):
         try:
             from paper_2101_05031_amd import build as B
             rec = json.load(open(tpath))
-            for stage, r in rec.get("stages", {}).items():
+            run = rec.get("runs", {}).get(f"tile{info['tile']}_slab{info['slab']}", {})
+            for stage, r in run.get("stages", {}).items():
                 if r.get("kernel_hash") == B.kernel_hash(stage):
                     traffic[stage] = r.get("bytes_per_step")
         except Exception:
