@@ -120,21 +120,41 @@ __device__ __forceinline__ CellMasks cell_masks(const uint64_t* P, int nbx, int 
     return c;
 }
 
-// inclusive prefix over the wave's lanes
-__device__ __forceinline__ uint64_t wave_incl(uint64_t v, int lane) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint64_t t = __shfl_up(v, (unsigned)d, kWave);
-        if (lane >= d) v += t;
-    }
+// v + v of the lane the DPP control selects (0 where it selects none)
+template <int CTRL, int ROWS, int BANKS>
+__device__ __forceinline__ uint32_t dpp_add(uint32_t acc, uint32_t v) {
+    return acc + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, BANKS, false);
+}
+
+// inclusive prefix over the wave's lanes with DPP moves: within rows of 16
+// (shifts by 1, 2, 3 of the inputs, then by 4 and 8 of the partial sums),
+// then across rows (broadcasts of lanes 15 and 31)
+__device__ __forceinline__ uint32_t wave_incl32(uint32_t v) {
+    const uint32_t v0 = v;
+    v = dpp_add<0x111, 0xf, 0xf>(v0, v0);          // row_shr:1
+    v = dpp_add<0x112, 0xf, 0xf>(v, v0);           // row_shr:2
+    v = dpp_add<0x113, 0xf, 0xf>(v, v0);           // row_shr:3
+    v = dpp_add<0x114, 0xf, 0xe>(v, v);            // row_shr:4, lanes 4..15 of a row
+    v = dpp_add<0x118, 0xf, 0xc>(v, v);            // row_shr:8, lanes 8..15
+    v = dpp_add<0x142, 0xa, 0xf>(v, v);            // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xc, 0xf>(v, v);            // row_bcast:31 into rows 2 and 3
     return v;
 }
 
-__device__ __forceinline__ uint64_t wave_total(uint64_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-    return v;
+// the same for 64-bit words of packed counts whose fields never carry (the
+// low halves' sums stay below 2^32)
+__device__ __forceinline__ uint64_t wave_incl(uint64_t v, int) {
+    return (uint64_t)wave_incl32((uint32_t)v) | ((uint64_t)wave_incl32((uint32_t)(v >> 32)) << 32);
 }
+
+__device__ __forceinline__ uint64_t wave_last(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, kWave - 1);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), kWave - 1);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// total over the wave of packed counts that never carry
+__device__ __forceinline__ uint64_t wave_total(uint64_t v) { return wave_last(wave_incl(v, 0)); }
 
 // segments of row r (0..7) of a block: one per boundary cell, two per saddle
 __device__ __forceinline__ uint32_t row_count(const CellMasks& c, int r) {
@@ -274,15 +294,15 @@ __global__ __launch_bounds__(kMThreads) void k_strip_emit(const uint64_t* img, i
 #pragma unroll
             for (int h = 0; h < 4; ++h) v |= (uint64_t)row_count(c, 4 * q + h) << (16 * h);
             const uint64_t inc = wave_incl(v, lane);
-            all[q] = __shfl(inc, kWave - 1, kWave);
+            all[q] = wave_last(inc);
             ex[q] = inc - v;
         }
         if (ballot64(c.m != 0ull) != 0ull) {
             // the lane's cells are items exl .. exl + nl - 1 (lane-major)
             const uint32_t nl = (uint32_t)__popcll(c.m);
-            const uint64_t incl = wave_incl((uint64_t)nl, lane);
-            const uint32_t n_items = (uint32_t)__shfl(incl, kWave - 1, kWave);
-            const uint32_t exl = (uint32_t)incl - nl;
+            const uint32_t incl = wave_incl32(nl);
+            const uint32_t n_items = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+            const uint32_t exl = incl - nl;
             for (uint32_t R = 0; R < n_items; R += kItems) {
                 uint64_t mb = c.m;
                 uint32_t t = exl;
