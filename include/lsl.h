@@ -161,7 +161,9 @@ typedef struct lsl_bins_info {
  * lists the struts covering it in edge-list order.  With per-strut supports
  * (lattice.support) R is R_j in these formulas and the edge list is ordered
  * by (first slab, z of the lower end, id), which keeps each slab's window a
- * prefix of the list; with one R that is the same order.
+ * prefix of the list; with one R that is the same order.  (The lists are
+ * built by a stable sort of (slab, tile row, 8-column segment) cells and a
+ * per-cell count and fill; the bin set and its order are the above.)
  *
  * On success *out holds a new handle.  Synchronises `stream` while it runs
  * (to read back the plan); the first group's bucket lists may still be in
@@ -412,11 +414,11 @@ lsl_status slice_batch(lattice_bins* bins, int32_t k0, int32_t nk, void* field,
 
 /* ---------------------------------------------------------------------------
  * slice_autotune -- choose tile and slab sizes by binning with each
- * candidate and timing the binning (to the end of its device work, after one
- * untimed warm-up binning), the binning of the later slab groups in order (as
- * one pass over all planes does it) and slice_batch's field launch on sampled
- * plane windows of this lattice and grid (the field time scaled to all
- * planes).  params is [host] in/out:
+ * candidate and timing the binning (to the end of its device work, the
+ * faster of two runs, after one untimed warm-up binning), the binning of the
+ * later slab groups in order (as one pass over all planes does it) and
+ * slice_batch's field launch on three sampled windows of 64 planes of this
+ * lattice and grid (the field time scaled to all planes).  params is [host] in/out:
  * nonzero fields are kept, zero fields are filled.  cache_path (optional,
  * [host] C string) is a JSON file of earlier choices keyed by problem shape
  * and kernel variant;
