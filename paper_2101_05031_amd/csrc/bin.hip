@@ -12,9 +12,10 @@
 // One wave per cell then counts the struts covering each of the cell's
 // columns (the bucket sizes, scanned into the offsets) and writes them, in
 // that order.  A strut's box is a few tiles wide, so the sort moves a
-// fraction of the (slab, tile, strut) pairs, and a cell's columns are few.  The adjoint also needs each entry's
-// emission index (its position in the strut-major order of the pairs),
-// which group_emi rebuilds from the entry's bucket and the strut's box.
+// fraction of the (slab, tile, strut) pairs, and a cell's columns are few.
+// The adjoint also needs each entry's emission index (its position in the
+// strut-major order of the pairs), which group_emi rebuilds from the entry's
+// bucket and the strut's box.
 #include "kernels.hpp"
 
 namespace lsl {
