@@ -230,12 +230,14 @@ __global__ void k_csr_offsets(const uint32_t* keys, uint32_t n, uint32_t n_bucke
     for (uint32_t b = kprev; b <= k && b <= n_buckets; ++b) offsets[b] = i;
 }
 
-// keys[i] = b for every entry i of bucket b
-__global__ void k_expand_keys(const uint32_t* offsets, uint32_t n_buckets, uint32_t* keys) {
-    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+// keys[i] = b for every entry i of bucket b: one wave per bucket, its lanes
+// writing consecutive entries
+__global__ __launch_bounds__(256) void k_expand_keys(const uint32_t* offsets, uint32_t n_buckets,
+                                                     uint32_t* keys) {
+    const uint32_t b = blockIdx.x * 4u + (threadIdx.x >> 6);
     if (b >= n_buckets) return;
     const uint32_t e = offsets[b + 1];
-    for (uint32_t i = offsets[b]; i < e; ++i) keys[i] = b;
+    for (uint32_t i = offsets[b] + (uint32_t)lane_id(); i < e; i += kWave) keys[i] = b;
 }
 
 __global__ void k_inverse(const uint32_t* active, uint32_t n, uint32_t* inv) {
@@ -340,7 +342,7 @@ lsl_status bin_group(const GroupBuffers& g, hipStream_t st) {
 
 lsl_status group_emi(const EmiArgs& a, hipStream_t st) {
     if (a.n_pairs && a.n_buckets) {
-        k_expand_keys<<<(a.n_buckets + 255) / 256, 256, 0, st>>>(a.offsets, a.n_buckets, a.keys);
+        k_expand_keys<<<(a.n_buckets + 3) / 4, 256, 0, st>>>(a.offsets, a.n_buckets, a.keys);
         LSL_HIP(hipGetLastError());
     }
     if (a.n_active) k_inverse<<<(a.n_active + 255) / 256, 256, 0, st>>>(a.active, a.n_active, a.inv);
