@@ -469,10 +469,10 @@ struct Lds<SZ, false, CH> {
     float dl[CH];             // -dz u_z / R
     float4 m0[CH];            // m_0 (x, y, z), R
     float4 u4[CH];            // u (x, y, z), dz u_z
-    float rk[CH];             // the reference plane r (window index)
     uint32_t mask[CH];        // reach bits: sub-block s, plane k at bit s SZ + k
-    uint32_t cand[CH];
-    float slot[CH][kParts];
+    uint32_t cand[CH];        // staged lane | entry << 8 | region << 16
+    float slot[CH][kParts];   // per bucket entry of the chunk
+    uint8_t pairs[256];       // (entry, region) pairs: entry | region in group << log2(CH)
 };
 template <int SZ, int CH>
 struct Lds<SZ, true, CH> {
@@ -481,10 +481,11 @@ struct Lds<SZ, true, CH> {
     float4 e[CH];
     float4 m0[CH];
     float4 u4[CH];
-    float rk[CH];
+    float rk[CH];             // the reference plane r (window index)
     uint32_t mask[CH];
     uint32_t cand[CH];
     float slot[CH][kParts];
+    uint8_t pairs[256];
 };
 
 // MODE 0: 16x16 regions, shared reference planes; 1: 16x16 regions, every
@@ -544,6 +545,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     float* part = (float*)a.partial;
 
     const bool st_ok = lane < kCh;            // the lane stages an entry
+    // regions whose (region, entry) pairs are compacted together, and the
+    // bits of an entry index in a pair
+    constexpr int kGrp = 256 / kCh;
+    constexpr int kEntBits = kCh == 64 ? 6 : 5;
+    const int nrg = nreg * nreg;
+    // half extents of a region's pixel centres
+    const double hxr = 0.5 * (kEdge - 1) * fabs(a.dx), hyr = 0.5 * (kEdge - 1) * fabs(a.dy);
     for (uint32_t cbase = beg; cbase < end; cbase += kCh) {
         const int nent = (int)((end - cbase) < (uint32_t)kCh ? (end - cbase) : (uint32_t)kCh);
         for (int q = lane; q < kCh * kParts; q += kWave) (&L.slot[0][0])[q] = 0.0f;
@@ -553,327 +561,393 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         valid = valid && pid < a.n_binned;
         const uint32_t p = valid ? pid : 0u;
 
-        for (int rg = 0; rg < nreg * nreg; ++rg) {
-            const int i0 = tx * a.tile + (rg % nreg) * kEdge;
-            const int j0 = ty * a.tile + (rg / nreg) * kEdge;
-            if (i0 >= ti1 || j0 >= tj1) continue;
-            uint32_t sub_ok = 0u;
-            for (int s = 0; s < kSub; ++s)
-                if (i0 + 8 * (s % NS) < ti1 && j0 + 8 * (s / NS) < tj1) sub_ok |= 1u << s;
-            const double cx = a.x0 + ((double)i0 + 0.5 * kEdge) * a.dx;
-            const double cy = a.y0 + ((double)j0 + 0.5 * kEdge) * a.dy;
-
-            for (int w0 = kb; w0 < ke; w0 += SZ) {
-                const int nw = ke - w0 < SZ ? ke - w0 : SZ;
-                // ------------------------------------------------ staging
-                int n_cand = 0;
-                {
-                    // read the entry afresh for every region and window: what
-                    // follows from it would otherwise stay in registers
-                    // through the evaluation
-                    uint32_t pr = p;
-                    asm volatile("" : "+v"(pr));
-                    const StrutRec<float> r = recs[pr];
-                    const double4 ln = a.line[pr];
+        for (int w0 = kb; w0 < ke; w0 += SZ) {
+            const int nw = ke - w0 < SZ ? ke - w0 : SZ;
+            // the window's plane centres: mid-plane and half extent
+            const double czm = a.z0 + ((double)w0 + 0.5 * (double)nw) * a.dz;
+            const double hzr = 0.5 * (double)(nw - 1) * fabs(a.dz);
+            const double hd = sqrt(fma(hxr, hxr, fma(hyr, hyr, hzr * hzr)));
+            for (int g0 = 0; g0 < nrg; g0 += kGrp) {
+                const int ng = nrg - g0 < kGrp ? nrg - g0 : kGrp;
+                // ------------------------------------- region pre-test
+                // bit q: some pixel centre of region g0 + q, on some plane of
+                // the window, may lie within the support of the entry's
+                // segment.  Every pixel centre lies within hd of the
+                // region's box centre c, so none does when dist(c, segment)
+                // >= R (1 + 1e-4) + hd (the margin keeps every pair whose
+                // float32 terms could be nonzero).
+                uint32_t near = 0u;
+                if (valid) {
+                    const StrutRec<float> r = recs[p];
+                    const double4 ln = a.line[p];
                     const double Rs = SR ? (double)r.pad : a.R;
-                    const double iR = 1.0 / Rs, iR2 = iR * iR;
-                    const float Rc2f = (float)(Rs * Rs * (1.0 + 2e-5));
-                    const double wx = cx - (double)r.ax, wy = cy - (double)r.ay;
-                    const double txy = fma(wx, ln.x, wy * ln.y);
-                    const double wz = a.z0 + ((double)w0 + 0.5) * a.dz - (double)r.az;
-                    const double tc0 = fma(wz, ln.z, txy);
-                    const double mx = fma(tc0, ln.x, -wx), my = fma(tc0, ln.y, -wy),
-                                 mz = fma(tc0, ln.z, -wz);
-                    const double m20 = fma(mx, mx, fma(my, my, mz * mz));
-                    const double dzuz = a.dz * ln.z;
-                    // m_k = m_0 + k dz (u_z u - e_z) is orthogonal to u:
-                    // |m_k|^2 = |m_0|^2 - 2 k dz m_0,z + k^2 dz^2 (1 - u_z^2)
-                    const double c1d = -2.0 * a.dz * mz, c2 = a.dz * a.dz * (1.0 - ln.z * ln.z);
-                    // sub-block centres c + delta_s: the foot moves by
-                    // delta.u along u, the offset m by (delta.u) u - delta
-                    float dus[kSub], cxs[kSub], cys[kSub], css[kSub], tdx[kSub], tdy[kSub];
-                    for (int s = 0; s < kSub; ++s) {
-                        const double ddx = (8.0 * (s % NS) + 4.0 - 0.5 * kEdge) * a.dx;
-                        const double ddy = (8.0 * (s / NS) + 4.0 - 0.5 * kEdge) * a.dy;
-                        const double du = fma(ddx, ln.x, ddy * ln.y);
-                        dus[s] = (float)du;
-                        cxs[s] = (float)fma(du, ln.x, -ddx);
-                        cys[s] = (float)fma(du, ln.y, -ddy);
-                        css[s] = (float)(ddx * ddx + ddy * ddy - du * du);
-                        tdx[s] = (float)(-2.0 * ddx);
-                        tdy[s] = (float)(-2.0 * ddy);
+                    const double thr = fma(Rs, 1.0 + 1e-4, hd), thr2 = thr * thr;
+                    const double wz = czm - (double)r.az;
+                    for (int q = 0; q < ng; ++q) {
+                        const int rg = g0 + q;
+                        const int i0 = tx * a.tile + (rg % nreg) * kEdge;
+                        const int j0 = ty * a.tile + (rg / nreg) * kEdge;
+                        if (i0 >= ti1 || j0 >= tj1) continue;
+                        const double wx = a.x0 + ((double)i0 + 0.5 * kEdge) * a.dx - (double)r.ax;
+                        const double wy = a.y0 + ((double)j0 + 0.5 * kEdge) * a.dy - (double)r.ay;
+                        double tt = fma(wx, ln.x, fma(wy, ln.y, wz * ln.z));
+                        tt = tt < 0.0 ? 0.0 : (tt > ln.w ? ln.w : tt);
+                        const double ex = fma(-tt, ln.x, wx), ey = fma(-tt, ln.y, wy),
+                                     ez = fma(-tt, ln.z, wz);
+                        if (fma(ex, ex, fma(ey, ey, ez * ez)) < thr2) near |= 1u << q;
                     }
-                    const float uxf = (float)ln.x, uyf = (float)ln.y, Lf = (float)ln.w;
-                    const float mxf0 = (float)mx, myf0 = (float)my;
-                    const float vxf = (float)(dzuz * ln.x), vyf = (float)(dzuz * ln.y);
-                    uint32_t mask = 0u;
-#pragma unroll 1
-                    for (int k = 0; k < nw; ++k) {
-                        const double kd = (double)k;
-                        const double tc = fma(kd, dzuz, tc0);
-                        const double m2 = fma(kd * kd, c2, fma(kd, c1d, m20));
-                        const float tcf = (float)tc, m2f = (float)m2, kf = (float)k;
-                        const float mxf = __builtin_fmaf(kf, vxf, mxf0);
-                        const float myf = __builtin_fmaf(kf, vyf, myf0);
-                        uint32_t bits = 0u;
-#pragma unroll
-                        for (int s = 0; s < kSub; ++s) {
-                            // e = F* - c_s, F* the segment's point nearest to
-                            // the sub-block centre; no pixel of the sub-block
-                            // is within R when D^2 - hx |e_x| - hy |e_y| >= R D
-                            const float tcs = tcf + dus[s];
-                            const float dt = __builtin_amdgcn_fmed3f(tcs, 0.0f, Lf) - tcs;
-                            const float ex = __builtin_fmaf(dt, uxf, mxf + cxs[s]);
-                            const float ey = __builtin_fmaf(dt, uyf, myf + cys[s]);
-                            const float m2s =
-                                __builtin_fmaf(tdx[s], mxf, __builtin_fmaf(tdy[s], myf, m2f + css[s]));
-                            const float D2 = __builtin_fmaf(dt, dt, m2s);
-                            const float q = D2 - __builtin_fmaf(hxf, fabsf(ex), hyf * fabsf(ey));
-                            const uint32_t pass =
-                                ((sub_ok >> s) & 1u) &
-                                ((uint32_t)(q <= 0.0f) | (uint32_t)(q * q < Rc2f * D2));
-                            bits |= pass << (s * SZ);
-                        }
-                        mask |= bits << k;
-                        if constexpr (QD) {
-                            // m_k / R
-                            const double mxk = fma(kd, dzuz * ln.x, mx), myk = fma(kd, dzuz * ln.y, my),
-                                         mzk = fma(kd, fma(dzuz, ln.z, -a.dz), mz);
-                            if (st_ok) L.pl[k][lane] = make_float4((float)(-tc * iR), (float)((ln.w - tc) * iR),
-                                                        (float)(mxk * iR), (float)(myk * iR));
-                            if (st_ok) L.pmy[k][lane] = (float)(mzk * iR);
-                        } else if constexpr (PR) {
-                            const double mxk = fma(kd, dzuz * ln.x, mx), myk = fma(kd, dzuz * ln.y, my);
-                            if (st_ok) L.pl[k][lane] = make_float4((float)(-tc * iR), (float)((ln.w - tc) * iR),
-                                                        (float)fma(-m2, iR2, 1.0), (float)(2.0 * mxk * iR2));
-                            if (st_ok) L.pmy[k][lane] = (float)(2.0 * myk * iR2);
-                        } else {
-                            if (st_ok) L.pg[k][lane] = (float)fma(-m2, iR2, 1.0);
-                        }
-                    }
-                    if (!valid) mask = 0u;
-                    if (st_ok) L.mask[lane] = mask;
-                    // the reference plane r: the middle of the planes the
-                    // strut reaches, so that the shifts k - r and the offsets
-                    // m_r stay small (m_k = m_r + (k - r) dm, dm = dz (u_z u -
-                    // e_z), grows without bound along a steep strut)
-                    uint32_t pm = 0u;
-                    for (int s = 0; s < kSub; ++s) pm |= (mask >> (s * SZ)) & ((1u << SZ) - 1u);
-                    // (shared reference planes: the window's first plane, as
-                    // fine planes keep (k - r) dz small against R)
-                    const int rr = (MODE != 0 && pm) ? (__builtin_ctz(pm) + 31 - __builtin_clz(pm)) >> 1 : 0;
-                    const double rd = (double)rr;
-                    const double tcr = fma(rd, dzuz, tc0);
-                    const double mxr = fma(rd, dzuz * ln.x, mx), myr = fma(rd, dzuz * ln.y, my),
-                                 mzr = fma(rd, fma(dzuz, ln.z, -a.dz), mz);
-                    if (st_ok) L.rk[lane] = (float)rr;
-                    if (st_ok) L.e[lane] = make_float4((float)(ln.x * iR), (float)(ln.y * iR),
-                                            (float)(2.0 * dzuz * iR), (float)(QD ? iR : iR2));
-                    if constexpr (!PR) {
-                        if (st_ok) L.dl[lane] = (float)(-dzuz * iR);
-                        if (st_ok) L.gr[lane] = make_float4((float)(-tcr * iR), (float)((ln.w - tcr) * iR),
-                                                 (float)(2.0 * mxr * iR2), (float)(2.0 * myr * iR2));
-                    }
-                    if (st_ok) L.m0[lane] = make_float4((float)mxr, (float)myr, (float)mzr, (float)Rs);
-                    if (st_ok) L.u4[lane] = make_float4(uxf, uyf, (float)ln.z, (float)dzuz);
-                    const uint64_t cm = ballot64(mask != 0u);
-                    if (mask != 0u) {
+                }
+                // (entry, region) pairs, region-major and in entry order
+                // within a region, so every entry's slot receives its
+                // regions' sums in region order
+                int npair = 0;
+                for (int q = 0; q < ng; ++q) {
+                    const bool on = (near >> q) & 1u;
+                    const uint64_t bm = ballot64(on);
+                    if (on) {
                         const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
-                            (uint32_t)(cm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)cm, 0u));
-                        L.cand[rank] = (uint32_t)lane;
+                            (uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
+                        L.pairs[npair + (int)rank] = (uint8_t)((uint32_t)lane | ((uint32_t)q << kEntBits));
                     }
-                    n_cand = __popcll(cm);
+                    npair += __popcll(bm);
                 }
-                // dL/dg at the lane's four pixels
-                float Gv[kSub][SZ];
-                q32::for_planes<0, kSub>([&](auto sc) {
-                    constexpr int s = decltype(sc)::value;
-                    const int pi = i0 + 8 * (s % NS) + lx, pj = j0 + 8 * (s / NS) + ly;
-                    const bool pix = pi < ti1 && pj < tj1;
-                    q32::for_planes<0, SZ>([&](auto kc) {
-                        constexpr int k = decltype(kc)::value;
-                        Gv[s][k] = (pix && k < nw)
-                                       ? grad[((size_t)(w0 + k - a.k0) * (size_t)a.H + (size_t)pj) *
-                                                  (size_t)a.W + (size_t)pi]
-                                       : 0.0f;
-                    });
-                });
-
                 __builtin_amdgcn_wave_barrier();
-                const int n = n_cand;
 
-                // --------------------------------------------- evaluation
-#pragma unroll 1
-                for (int j = 0; j < n; ++j) {
-                    const uint32_t e = L.cand[j];
-                    const uint32_t mask = __builtin_amdgcn_readfirstlane(L.mask[e]);
-                    const float4 E = L.e[e];
-                    const float4 U = L.u4[e];
-                    const float rf = L.rk[e];
-                    float nD = 0.0f;
-                    float4 Rg = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                    float Gk[SZ];
-                    if constexpr (!PR) {
-                        nD = L.dl[e];
-                        Rg = L.gr[e];
-                        q32::for_planes<0, SZ>([&](auto kc) {
-                            constexpr int k = decltype(kc)::value;
-                            Gk[k] = L.pg[k][e];
-                        });
-                    }
-                    // per lane: sum G I, G phi(alpha), G phi(beta); sum G K, sum
-                    // (k - r) G K and sum G K over the right-hand (sx = 1) and
-                    // lower (sy = 1) sub-blocks, whose pixels lie 8 dx, 8 dy
-                    // further (likewise for J)
-                    float Aw = 0.0f, Aa = 0.0f, Ab = 0.0f, ABk = 0.0f, AAk = 0.0f;
-                    float Bs[kSub], As[kSub];                 // per sub-block
-                    q32::for_planes<0, kSub>([&](auto sc) {
-                        constexpr int s = decltype(sc)::value;
-                        Bs[s] = As[s] = 0.0f;
-                    });
-                    const float du0 = __builtin_fmaf(Dx[0], E.x, Dy[0] * E.y);
-                    const float e8x = NS == 2 ? 8.0f * dxf * E.x : 0.0f;
-                    const float e8y = NS == 2 ? 8.0f * dyf * E.y : 0.0f;
-                    q32::for_planes<0, kSub>([&](auto sc) {
-                        constexpr int s = decltype(sc)::value;
-                        const uint32_t ms = (mask >> (s * SZ)) & ((1u << SZ) - 1u);
-                        if (ms == 0u) return;
-                        // one plane's values at a time (not all planes kept
-                        // in registers across the four sub-blocks)
-                        uint32_t es = e;
-                        if constexpr (PR) asm volatile("" : "+v"(es));
-                        const float dX = Dx[s % NS], dY = Dy[s / NS];
-                        // d.u^ (d of sub-block (sx, sy) = d_00 + 8 (sx dx, sy dy))
-                        float du = du0;
-                        if constexpr (s % NS != 0) du += e8x;
-                        if constexpr (s / NS != 0) du += e8y;
-                        float ndd = 0.0f, vx = 0.0f, vy = 0.0f, vz = 0.0f;
-                        if constexpr (QD) {
-                            // q_perp^ = m_k^ - v, v = d^ - (d.u^) u
-                            vx = __builtin_fmaf(-du, U.x, dX * E.w);
-                            vy = __builtin_fmaf(-du, U.y, dY * E.w);
-                            vz = -du * U.z;
-                        } else {
-                            ndd = nd2[s] * E.w;                                  // -|d^|^2
+                for (int pb = 0; pb < npair; pb += kCh) {
+                    // this lane stages pair pb + lane
+                    const bool has = st_ok && pb + lane < npair;
+                    const uint32_t pr8 = has ? (uint32_t)L.pairs[pb + lane] : 0u;
+                    const uint32_t ent = pr8 & (uint32_t)(kCh - 1);
+                    const int rgl = g0 + (int)(pr8 >> kEntBits);
+                    const uint32_t ps = has ? a.ids[cbase + ent] : 0u;
+                    const int i0 = tx * a.tile + (rgl % nreg) * kEdge;
+                    const int j0 = ty * a.tile + (rgl / nreg) * kEdge;
+                    uint32_t sub_ok = 0u;
+                    for (int s = 0; s < kSub; ++s)
+                        if (i0 + 8 * (s % NS) < ti1 && j0 + 8 * (s / NS) < tj1) sub_ok |= 1u << s;
+                    const double cx = a.x0 + ((double)i0 + 0.5 * kEdge) * a.dx;
+                    const double cy = a.y0 + ((double)j0 + 0.5 * kEdge) * a.dy;
+                    // ------------------------------------------------ staging
+                    int n_cand = 0;
+                    {
+                        // read the entry afresh for every pass: what follows from
+                        // it would otherwise stay in registers through the
+                        // evaluation
+                        uint32_t pr = ps;
+                        asm volatile("" : "+v"(pr));
+                        const StrutRec<float> r = recs[pr];
+                        const double4 ln = a.line[pr];
+                        const double Rs = SR ? (double)r.pad : a.R;
+                        const double iR = 1.0 / Rs, iR2 = iR * iR;
+                        const float Rc2f = (float)(Rs * Rs * (1.0 + 2e-5));
+                        const double wx = cx - (double)r.ax, wy = cy - (double)r.ay;
+                        const double txy = fma(wx, ln.x, wy * ln.y);
+                        const double wz = a.z0 + ((double)w0 + 0.5) * a.dz - (double)r.az;
+                        const double tc0 = fma(wz, ln.z, txy);
+                        const double mx = fma(tc0, ln.x, -wx), my = fma(tc0, ln.y, -wy),
+                                     mz = fma(tc0, ln.z, -wz);
+                        const double m20 = fma(mx, mx, fma(my, my, mz * mz));
+                        const double dzuz = a.dz * ln.z;
+                        // m_k = m_0 + k dz (u_z u - e_z) is orthogonal to u:
+                        // |m_k|^2 = |m_0|^2 - 2 k dz m_0,z + k^2 dz^2 (1 - u_z^2)
+                        const double c1d = -2.0 * a.dz * mz, c2 = a.dz * a.dz * (1.0 - ln.z * ln.z);
+                        // sub-block centres c + delta_s: the foot moves by
+                        // delta.u along u, the offset m by (delta.u) u - delta
+                        float dus[kSub], cxs[kSub], cys[kSub], css[kSub], tdx[kSub], tdy[kSub];
+                        for (int s = 0; s < kSub; ++s) {
+                            const double ddx = (8.0 * (s % NS) + 4.0 - 0.5 * kEdge) * a.dx;
+                            const double ddy = (8.0 * (s / NS) + 4.0 - 0.5 * kEdge) * a.dy;
+                            const double du = fma(ddx, ln.x, ddy * ln.y);
+                            dus[s] = (float)du;
+                            cxs[s] = (float)fma(du, ln.x, -ddx);
+                            cys[s] = (float)fma(du, ln.y, -ddy);
+                            css[s] = (float)(ddx * ddx + ddy * ddy - du * du);
+                            tdx[s] = (float)(-2.0 * ddx);
+                            tdy[s] = (float)(-2.0 * ddy);
                         }
-                        float ar = 0.0f, br = 0.0f, Eg = 0.0f, P1 = 0.0f;
-                        if constexpr (!PR) {
-                            ar = Rg.x - du;
-                            br = Rg.y - du;
-                            Eg = __builtin_fmaf(du, du,
-                                                __builtin_fmaf(Rg.z, dX, __builtin_fmaf(Rg.w, dY, ndd)));
-                            P1 = E.z * du;
-                        }
-                        q32::for_planes<0, SZ>([&](auto kc) {
-                            constexpr int k = decltype(kc)::value;
-                            if (!((ms >> k) & 1u)) return;
-                            // k - r (r = 0 with shared reference planes)
-                            const float kap = MODE == 0 ? (float)k : (float)k - rf;
-                            float al, be, Hp;
+                        const float uxf = (float)ln.x, uyf = (float)ln.y, Lf = (float)ln.w;
+                        const float mxf0 = (float)mx, myf0 = (float)my;
+                        const float vxf = (float)(dzuz * ln.x), vyf = (float)(dzuz * ln.y);
+                        uint32_t mask = 0u;
+    #pragma unroll 1
+                        for (int k = 0; k < nw; ++k) {
+                            const double kd = (double)k;
+                            const double tc = fma(kd, dzuz, tc0);
+                            const double m2 = fma(kd * kd, c2, fma(kd, c1d, m20));
+                            const float tcf = (float)tc, m2f = (float)m2, kf = (float)k;
+                            const float mxf = __builtin_fmaf(kf, vxf, mxf0);
+                            const float myf = __builtin_fmaf(kf, vyf, myf0);
+                            uint32_t bits = 0u;
+    #pragma unroll
+                            for (int s = 0; s < kSub; ++s) {
+                                // e = F* - c_s, F* the segment's point nearest to
+                                // the sub-block centre; no pixel of the sub-block
+                                // is within R when D^2 - hx |e_x| - hy |e_y| >= R D
+                                const float tcs = tcf + dus[s];
+                                const float dt = __builtin_amdgcn_fmed3f(tcs, 0.0f, Lf) - tcs;
+                                const float ex = __builtin_fmaf(dt, uxf, mxf + cxs[s]);
+                                const float ey = __builtin_fmaf(dt, uyf, myf + cys[s]);
+                                const float m2s =
+                                    __builtin_fmaf(tdx[s], mxf, __builtin_fmaf(tdy[s], myf, m2f + css[s]));
+                                const float D2 = __builtin_fmaf(dt, dt, m2s);
+                                const float q = D2 - __builtin_fmaf(hxf, fabsf(ex), hyf * fabsf(ey));
+                                const uint32_t pass =
+                                    ((sub_ok >> s) & 1u) &
+                                    ((uint32_t)(q <= 0.0f) | (uint32_t)(q * q < Rc2f * D2));
+                                bits |= pass << (s * SZ);
+                            }
+                            mask |= bits << k;
                             if constexpr (QD) {
-                                const float4 P = L.pl[k][es];
-                                const float qz = L.pmy[k][es] - vz;
-                                const float qx = P.z - vx, qy = P.w - vy;
-                                al = P.x - du;
-                                be = P.y - du;
-                                Hp = 1.0f - __builtin_fmaf(qx, qx, __builtin_fmaf(qy, qy, qz * qz));
+                                // m_k / R
+                                const double mxk = fma(kd, dzuz * ln.x, mx), myk = fma(kd, dzuz * ln.y, my),
+                                             mzk = fma(kd, fma(dzuz, ln.z, -a.dz), mz);
+                                if (st_ok) L.pl[k][lane] = make_float4((float)(-tc * iR), (float)((ln.w - tc) * iR),
+                                                            (float)(mxk * iR), (float)(myk * iR));
+                                if (st_ok) L.pmy[k][lane] = (float)(mzk * iR);
                             } else if constexpr (PR) {
-                                const float4 P = L.pl[k][es];
-                                const float my2 = L.pmy[k][es];
-                                al = P.x - du;
-                                be = P.y - du;
-                                Hp = __builtin_fmaf(du, du,
-                                                    __builtin_fmaf(P.w, dX, __builtin_fmaf(my2, dY, ndd + P.z)));
-                            } else if constexpr (k == 0) {
-                                al = ar;
-                                be = br;
-                                Hp = Gk[0] + Eg;
+                                const double mxk = fma(kd, dzuz * ln.x, mx), myk = fma(kd, dzuz * ln.y, my);
+                                if (st_ok) L.pl[k][lane] = make_float4((float)(-tc * iR), (float)((ln.w - tc) * iR),
+                                                            (float)fma(-m2, iR2, 1.0), (float)(2.0 * mxk * iR2));
+                                if (st_ok) L.pmy[k][lane] = (float)(2.0 * myk * iR2);
                             } else {
-                                al = __builtin_fmaf(kap, nD, ar);
-                                be = __builtin_fmaf(kap, nD, br);
-                                Hp = __builtin_fmaf(kap, P1, Gk[k] + Eg);
+                                if (st_ok) L.pg[k][lane] = (float)fma(-m2, iR2, 1.0);
                             }
-                            const float H = __builtin_amdgcn_fmed3f(Hp, 0.0f, 1.0f);
-                            const float h = __builtin_amdgcn_sqrtf(H);
-                            const float ca = __builtin_amdgcn_fmed3f(al, -h, h);
-                            const float cb = __builtin_amdgcn_fmed3f(be, -h, h);
-                            const float sm = ca + cb, D = cb - ca;
-                            const float s2 = sm * sm, D2 = D * D;
-                            const float A4 = __builtin_fmaf(D2, -1.0f / 3.0f, __builtin_fmaf(H, 4.0f, -s2));
-                            const float V16 = __builtin_fmaf(s2, 4.0f / 3.0f, D2 * (4.0f / 45.0f));
-                            const float Q16 = __builtin_fmaf(A4, A4, D2 * V16);
-                            const float g = Gv[s][k];
-                            const float gD = g * D;
-                            Aw = __builtin_fmaf(gD, Q16, Aw);
-                            const float Jq = gD * A4;                    // 2 G J R
-                            const float xa = __builtin_fmaf(-ca, ca, H), xb = __builtin_fmaf(-cb, cb, H);
-                            const float pa = xa * xa, pb = xb * xb;
-                            Aa = __builtin_fmaf(g, pa, Aa);
-                            Ab = __builtin_fmaf(g, pb, Ab);
-                            const float gd = g * (pb - pa);
-                            // (shared reference planes, fine pixels: J itself
-                            // instead of K_a, one operation less)
-                            const float gKb = __builtin_fmaf(al, Jq, gd);
-                            const float gKa = MODE == 0 ? Jq : __builtin_fmaf(be, Jq, gd);
-                            Bs[s] += gKb;
-                            As[s] += gKa;
-                            if (MODE != 0 || k != 0) {
-                                ABk = __builtin_fmaf(kap, gKb, ABk);
-                                AAk = __builtin_fmaf(kap, gKa, AAk);
-                            }
+                        }
+                        if (!has) mask = 0u;
+                        if (st_ok) L.mask[lane] = mask;
+                        // the reference plane r: the middle of the planes the
+                        // strut reaches, so that the shifts k - r and the offsets
+                        // m_r stay small (m_k = m_r + (k - r) dm, dm = dz (u_z u -
+                        // e_z), grows without bound along a steep strut)
+                        uint32_t pm = 0u;
+                        for (int s = 0; s < kSub; ++s) pm |= (mask >> (s * SZ)) & ((1u << SZ) - 1u);
+                        // (shared reference planes: the window's first plane, as
+                        // fine planes keep (k - r) dz small against R)
+                        const int rr = (MODE != 0 && pm) ? (__builtin_ctz(pm) + 31 - __builtin_clz(pm)) >> 1 : 0;
+                        const double rd = (double)rr;
+                        const double tcr = fma(rd, dzuz, tc0);
+                        const double mxr = fma(rd, dzuz * ln.x, mx), myr = fma(rd, dzuz * ln.y, my),
+                                     mzr = fma(rd, fma(dzuz, ln.z, -a.dz), mz);
+                        if constexpr (PR) {
+                            if (st_ok) L.rk[lane] = (float)rr;
+                        }
+                        if (st_ok) L.e[lane] = make_float4((float)(ln.x * iR), (float)(ln.y * iR),
+                                                (float)(2.0 * dzuz * iR), (float)(QD ? iR : iR2));
+                        if constexpr (!PR) {
+                            if (st_ok) L.dl[lane] = (float)(-dzuz * iR);
+                            if (st_ok) L.gr[lane] = make_float4((float)(-tcr * iR), (float)((ln.w - tcr) * iR),
+                                                     (float)(2.0 * mxr * iR2), (float)(2.0 * myr * iR2));
+                        }
+                        if (st_ok) L.m0[lane] = make_float4((float)mxr, (float)myr, (float)mzr, (float)Rs);
+                        if (st_ok) L.u4[lane] = make_float4(uxf, uyf, (float)ln.z, (float)dzuz);
+                        const uint64_t cm = ballot64(mask != 0u);
+                        if (mask != 0u) {
+                            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(cm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)cm, 0u));
+                            L.cand[rank] = (uint32_t)lane | (ent << 8) | ((uint32_t)rgl << 16);
+                        }
+                        n_cand = __popcll(cm);
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    const int n = n_cand;
+
+                    // --------------------------------------------- evaluation
+                    // dL/dg at the lane's pixels of the candidate's region, loaded
+                    // when the region changes
+                    float Gv[kSub][SZ];
+                    int cur = -1;
+    #pragma unroll 1
+                    for (int j = 0; j < n; ++j) {
+                        const uint32_t c = __builtin_amdgcn_readfirstlane(L.cand[j]);
+                        const uint32_t e = c & 0xffu;
+                        const int crg = (int)(c >> 16);
+                        if (crg != cur) {
+                            cur = crg;
+                            const int ri = tx * a.tile + (crg % nreg) * kEdge;
+                            const int rj = ty * a.tile + (crg / nreg) * kEdge;
+                            q32::for_planes<0, kSub>([&](auto sc) {
+                                constexpr int s = decltype(sc)::value;
+                                const int pi = ri + 8 * (s % NS) + lx, pj = rj + 8 * (s / NS) + ly;
+                                const bool pix = pi < ti1 && pj < tj1;
+                                q32::for_planes<0, SZ>([&](auto kc) {
+                                    constexpr int k = decltype(kc)::value;
+                                    Gv[s][k] = (pix && k < nw)
+                                                   ? grad[((size_t)(w0 + k - a.k0) * (size_t)a.H + (size_t)pj) *
+                                                              (size_t)a.W + (size_t)pi]
+                                                   : 0.0f;
+                                });
+                            });
+                        }
+                        const uint32_t mask = __builtin_amdgcn_readfirstlane(L.mask[e]);
+                        const float4 E = L.e[e];
+                        const float4 U = L.u4[e];
+                        float rf = 0.0f;
+                        if constexpr (PR) rf = L.rk[e];
+                        float nD = 0.0f;
+                        float4 Rg = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                        float Gk[SZ];
+                        if constexpr (!PR) {
+                            nD = L.dl[e];
+                            Rg = L.gr[e];
+                            q32::for_planes<0, SZ>([&](auto kc) {
+                                constexpr int k = decltype(kc)::value;
+                                Gk[k] = L.pg[k][e];
+                            });
+                        }
+                        // per lane: sum G I, G phi(alpha), G phi(beta); sum G K, sum
+                        // (k - r) G K and sum G K over the right-hand (sx = 1) and
+                        // lower (sy = 1) sub-blocks, whose pixels lie 8 dx, 8 dy
+                        // further (likewise for J)
+                        float Aw = 0.0f, Aa = 0.0f, Ab = 0.0f, ABk = 0.0f, AAk = 0.0f;
+                        float Bs[kSub], As[kSub];                 // per sub-block
+                        q32::for_planes<0, kSub>([&](auto sc) {
+                            constexpr int s = decltype(sc)::value;
+                            Bs[s] = As[s] = 0.0f;
                         });
-                    });
-                    // over all sub-blocks, the right-hand ones and the lower ones
-                    const float4 M = L.m0[e];
-                    const float dmx = U.w * U.x, dmy = U.w * U.y, dmz = __builtin_fmaf(U.w, U.z, -dzf);
-                    const float rux = M.w * U.x, ruy = M.w * U.y, ruz = M.w * U.z;
-                    // sum G K q_perp = m_r sum G K + dm sum (k - r) G K - sum G K d
-                    // + R u sum G K (d.u^), dm = dz u_z u - dz e_z, for K_b and K_a
-                    float v[kParts];
-                    v[0] = Aw * (1.0f / 16.0f);
-                    v[1] = Aa;
-                    v[2] = Ab;
-                    if constexpr (NS == 2) {
-                        // over all sub-blocks, the right-hand and the lower ones
-                        // (d of sub-block (sx, sy) = d_00 + 8 (sx dx, sy dy))
-                        const float SXB = Bs[1] + Bs[3], SXA = As[1] + As[3];
-                        const float SYB = Bs[2] + Bs[3], SYA = As[2] + As[3];
-                        const float AB = (Bs[0] + Bs[2]) + SXB, AA = (As[0] + As[2]) + SXA;
-                        const float ABx = __builtin_fmaf(8.0f * dxf, SXB, Dx[0] * AB);
-                        const float ABy = __builtin_fmaf(8.0f * dyf, SYB, Dy[0] * AB);
-                        const float ABu = __builtin_fmaf(e8x, SXB, __builtin_fmaf(e8y, SYB, du0 * AB));
-                        const float AAx = __builtin_fmaf(8.0f * dxf, SXA, Dx[0] * AA);
-                        const float AAy = __builtin_fmaf(8.0f * dyf, SYA, Dy[0] * AA);
-                        const float AAu = __builtin_fmaf(e8x, SXA, __builtin_fmaf(e8y, SYA, du0 * AA));
-                        v[3] = __builtin_fmaf(M.x, AB, __builtin_fmaf(dmx, ABk, __builtin_fmaf(rux, ABu, -ABx)));
-                        v[4] = __builtin_fmaf(M.y, AB, __builtin_fmaf(dmy, ABk, __builtin_fmaf(ruy, ABu, -ABy)));
-                        v[5] = __builtin_fmaf(M.z, AB, __builtin_fmaf(dmz, ABk, ruz * ABu));
-                        v[6] = __builtin_fmaf(M.x, AA, __builtin_fmaf(dmx, AAk, __builtin_fmaf(rux, AAu, -AAx)));
-                        v[7] = __builtin_fmaf(M.y, AA, __builtin_fmaf(dmy, AAk, __builtin_fmaf(ruy, AAu, -AAy)));
-                        v[8] = __builtin_fmaf(M.z, AA, __builtin_fmaf(dmz, AAk, ruz * AAu));
-                    } else {
-                        // one sub-block: the lane's q_perp at plane r, m_r - d + (d.u) u,
-                        // weights both ends' sums
-                        const float qx = __builtin_fmaf(rux, du0, M.x - Dx[0]);
-                        const float qy = __builtin_fmaf(ruy, du0, M.y - Dy[0]);
-                        const float qz = __builtin_fmaf(ruz, du0, M.z);
-                        v[3] = __builtin_fmaf(qx, Bs[0], dmx * ABk);
-                        v[4] = __builtin_fmaf(qy, Bs[0], dmy * ABk);
-                        v[5] = __builtin_fmaf(qz, Bs[0], dmz * ABk);
-                        v[6] = __builtin_fmaf(qx, As[0], dmx * AAk);
-                        v[7] = __builtin_fmaf(qy, As[0], dmy * AAk);
-                        v[8] = __builtin_fmaf(qz, As[0], dmz * AAk);
+                        const float du0 = __builtin_fmaf(Dx[0], E.x, Dy[0] * E.y);
+                        const float e8x = NS == 2 ? 8.0f * dxf * E.x : 0.0f;
+                        const float e8y = NS == 2 ? 8.0f * dyf * E.y : 0.0f;
+                        q32::for_planes<0, kSub>([&](auto sc) {
+                            constexpr int s = decltype(sc)::value;
+                            const uint32_t ms = (mask >> (s * SZ)) & ((1u << SZ) - 1u);
+                            if (ms == 0u) return;
+                            // one plane's values at a time (not all planes kept
+                            // in registers across the four sub-blocks)
+                            uint32_t es = e;
+                            if constexpr (PR) asm volatile("" : "+v"(es));
+                            const float dX = Dx[s % NS], dY = Dy[s / NS];
+                            // d.u^ (d of sub-block (sx, sy) = d_00 + 8 (sx dx, sy dy))
+                            float du = du0;
+                            if constexpr (s % NS != 0) du += e8x;
+                            if constexpr (s / NS != 0) du += e8y;
+                            float ndd = 0.0f, vx = 0.0f, vy = 0.0f, vz = 0.0f;
+                            if constexpr (QD) {
+                                // q_perp^ = m_k^ - v, v = d^ - (d.u^) u
+                                vx = __builtin_fmaf(-du, U.x, dX * E.w);
+                                vy = __builtin_fmaf(-du, U.y, dY * E.w);
+                                vz = -du * U.z;
+                            } else {
+                                ndd = nd2[s] * E.w;                                  // -|d^|^2
+                            }
+                            float ar = 0.0f, br = 0.0f, Eg = 0.0f, P1 = 0.0f;
+                            if constexpr (!PR) {
+                                ar = Rg.x - du;
+                                br = Rg.y - du;
+                                Eg = __builtin_fmaf(du, du,
+                                                    __builtin_fmaf(Rg.z, dX, __builtin_fmaf(Rg.w, dY, ndd)));
+                                P1 = E.z * du;
+                            }
+                            q32::for_planes<0, SZ>([&](auto kc) {
+                                constexpr int k = decltype(kc)::value;
+                                if (!((ms >> k) & 1u)) return;
+                                // k - r (r = 0 with shared reference planes)
+                                const float kap = MODE == 0 ? (float)k : (float)k - rf;
+                                float al, be, Hp;
+                                if constexpr (QD) {
+                                    const float4 P = L.pl[k][es];
+                                    const float qz = L.pmy[k][es] - vz;
+                                    const float qx = P.z - vx, qy = P.w - vy;
+                                    al = P.x - du;
+                                    be = P.y - du;
+                                    Hp = 1.0f - __builtin_fmaf(qx, qx, __builtin_fmaf(qy, qy, qz * qz));
+                                } else if constexpr (PR) {
+                                    const float4 P = L.pl[k][es];
+                                    const float my2 = L.pmy[k][es];
+                                    al = P.x - du;
+                                    be = P.y - du;
+                                    Hp = __builtin_fmaf(du, du,
+                                                        __builtin_fmaf(P.w, dX, __builtin_fmaf(my2, dY, ndd + P.z)));
+                                } else if constexpr (k == 0) {
+                                    al = ar;
+                                    be = br;
+                                    Hp = Gk[0] + Eg;
+                                } else {
+                                    al = __builtin_fmaf(kap, nD, ar);
+                                    be = __builtin_fmaf(kap, nD, br);
+                                    Hp = __builtin_fmaf(kap, P1, Gk[k] + Eg);
+                                }
+                                const float H = __builtin_amdgcn_fmed3f(Hp, 0.0f, 1.0f);
+                                const float h = __builtin_amdgcn_sqrtf(H);
+                                const float ca = __builtin_amdgcn_fmed3f(al, -h, h);
+                                const float cb = __builtin_amdgcn_fmed3f(be, -h, h);
+                                const float sm = ca + cb, D = cb - ca;
+                                const float s2 = sm * sm, D2 = D * D;
+                                const float A4 = __builtin_fmaf(D2, -1.0f / 3.0f, __builtin_fmaf(H, 4.0f, -s2));
+                                const float V16 = __builtin_fmaf(s2, 4.0f / 3.0f, D2 * (4.0f / 45.0f));
+                                const float Q16 = __builtin_fmaf(A4, A4, D2 * V16);
+                                const float g = Gv[s][k];
+                                const float gD = g * D;
+                                Aw = __builtin_fmaf(gD, Q16, Aw);
+                                const float Jq = gD * A4;                    // 2 G J R
+                                const float xa = __builtin_fmaf(-ca, ca, H), xb = __builtin_fmaf(-cb, cb, H);
+                                const float pa = xa * xa, pb = xb * xb;
+                                Aa = __builtin_fmaf(g, pa, Aa);
+                                Ab = __builtin_fmaf(g, pb, Ab);
+                                const float gd = g * (pb - pa);
+                                // (shared reference planes, fine pixels: J itself
+                                // instead of K_a, one operation less)
+                                const float gKb = __builtin_fmaf(al, Jq, gd);
+                                const float gKa = MODE == 0 ? Jq : __builtin_fmaf(be, Jq, gd);
+                                Bs[s] += gKb;
+                                As[s] += gKa;
+                                if (MODE != 0 || k != 0) {
+                                    ABk = __builtin_fmaf(kap, gKb, ABk);
+                                    AAk = __builtin_fmaf(kap, gKa, AAk);
+                                }
+                            });
+                        });
+                        // over all sub-blocks, the right-hand ones and the lower ones
+                        const float4 M = L.m0[e];
+                        const float dmx = U.w * U.x, dmy = U.w * U.y, dmz = __builtin_fmaf(U.w, U.z, -dzf);
+                        const float rux = M.w * U.x, ruy = M.w * U.y, ruz = M.w * U.z;
+                        // sum G K q_perp = m_r sum G K + dm sum (k - r) G K - sum G K d
+                        // + R u sum G K (d.u^), dm = dz u_z u - dz e_z, for K_b and K_a
+                        float v[kParts];
+                        v[0] = Aw * (1.0f / 16.0f);
+                        v[1] = Aa;
+                        v[2] = Ab;
+                        if constexpr (NS == 2) {
+                            // over all sub-blocks, the right-hand and the lower ones
+                            // (d of sub-block (sx, sy) = d_00 + 8 (sx dx, sy dy))
+                            const float SXB = Bs[1] + Bs[3], SXA = As[1] + As[3];
+                            const float SYB = Bs[2] + Bs[3], SYA = As[2] + As[3];
+                            const float AB = (Bs[0] + Bs[2]) + SXB, AA = (As[0] + As[2]) + SXA;
+                            const float ABx = __builtin_fmaf(8.0f * dxf, SXB, Dx[0] * AB);
+                            const float ABy = __builtin_fmaf(8.0f * dyf, SYB, Dy[0] * AB);
+                            const float ABu = __builtin_fmaf(e8x, SXB, __builtin_fmaf(e8y, SYB, du0 * AB));
+                            const float AAx = __builtin_fmaf(8.0f * dxf, SXA, Dx[0] * AA);
+                            const float AAy = __builtin_fmaf(8.0f * dyf, SYA, Dy[0] * AA);
+                            const float AAu = __builtin_fmaf(e8x, SXA, __builtin_fmaf(e8y, SYA, du0 * AA));
+                            v[3] = __builtin_fmaf(M.x, AB, __builtin_fmaf(dmx, ABk, __builtin_fmaf(rux, ABu, -ABx)));
+                            v[4] = __builtin_fmaf(M.y, AB, __builtin_fmaf(dmy, ABk, __builtin_fmaf(ruy, ABu, -ABy)));
+                            v[5] = __builtin_fmaf(M.z, AB, __builtin_fmaf(dmz, ABk, ruz * ABu));
+                            v[6] = __builtin_fmaf(M.x, AA, __builtin_fmaf(dmx, AAk, __builtin_fmaf(rux, AAu, -AAx)));
+                            v[7] = __builtin_fmaf(M.y, AA, __builtin_fmaf(dmy, AAk, __builtin_fmaf(ruy, AAu, -AAy)));
+                            v[8] = __builtin_fmaf(M.z, AA, __builtin_fmaf(dmz, AAk, ruz * AAu));
+                        } else {
+                            // one sub-block: the lane's q_perp at plane r, m_r - d + (d.u) u,
+                            // weights both ends' sums
+                            const float qx = __builtin_fmaf(rux, du0, M.x - Dx[0]);
+                            const float qy = __builtin_fmaf(ruy, du0, M.y - Dy[0]);
+                            const float qz = __builtin_fmaf(ruz, du0, M.z);
+                            v[3] = __builtin_fmaf(qx, Bs[0], dmx * ABk);
+                            v[4] = __builtin_fmaf(qy, Bs[0], dmy * ABk);
+                            v[5] = __builtin_fmaf(qz, Bs[0], dmz * ABk);
+                            v[6] = __builtin_fmaf(qx, As[0], dmx * AAk);
+                            v[7] = __builtin_fmaf(qy, As[0], dmy * AAk);
+                            v[8] = __builtin_fmaf(qz, As[0], dmz * AAk);
+                        }
+                        if constexpr (MODE == 0) {
+                            // K_a = K_b + 2 J L: the second sums carried J
+                            const float Lh = Rg.y - Rg.x;
+                            v[6] = __builtin_fmaf(Lh, v[6], v[3]);
+                            v[7] = __builtin_fmaf(Lh, v[7], v[4]);
+                            v[8] = __builtin_fmaf(Lh, v[8], v[5]);
+                        }
+                        deposit(L.slot[(c >> 8) & 0xffu], v, lane, own);
                     }
-                    if constexpr (MODE == 0) {
-                        // K_a = K_b + 2 J L: the second sums carried J
-                        const float Lh = Rg.y - Rg.x;
-                        v[6] = __builtin_fmaf(Lh, v[6], v[3]);
-                        v[7] = __builtin_fmaf(Lh, v[7], v[4]);
-                        v[8] = __builtin_fmaf(Lh, v[8], v[5]);
-                    }
-                    deposit(L.slot[e], v, lane, own);
+                    __builtin_amdgcn_wave_barrier();
                 }
-                __builtin_amdgcn_wave_barrier();
             }
         }
         __builtin_amdgcn_wave_barrier();
