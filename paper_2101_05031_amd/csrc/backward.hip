@@ -401,17 +401,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
 // regions of 2x2 8x8 sub-blocks (16x16 pixels, one pixel of each sub-block
 // per lane) -- or of one 8x8 block when the pixels are coarse against the
 // smallest support (see below) -- and the slab in windows of at most 8
-// planes.  For 64 bucket entries at a time (one per lane), each region and
-// each window:
+// planes.  For 64 bucket entries at a time (one per lane) and each window:
 //
-//  * staging, per entry: the strut's line around the region centre c
-//    (float64), its values per plane, and the reach test of the field kernel
-//    for every (sub-block, plane), in float32 against the support widened by
-//    1e-5 relative (so that no strut that reaches a pixel is dropped; one
-//    that does not adds exact zeros);
-//  * evaluation, per entry that reaches the region: every lane adds its
-//    pixels' terms over the (sub-block, plane) pairs the strut reaches, and
-//    the wave sums the nine pixel sums once per (strut, region).
+//  * region pre-test, per entry: which regions the strut's support may
+//    reach at all (the distance from the region's box centre to the segment,
+//    in float64, against R (1 + 1e-4) plus the box's half-diagonal); the
+//    (entry, region) pairs that pass are compacted region-major, and the
+//    rest, whose terms would all be exact zeros, are never staged;
+//  * staging, one pair per lane, 64 at a time: the strut's line around its
+//    region's centre c (float64), its values per plane, and the reach test
+//    of the field kernel for every (sub-block, plane), in float32 against
+//    the support widened by 1e-5 relative (so that no strut that reaches a
+//    pixel is dropped; one that does not adds exact zeros);
+//  * evaluation, per staged pair that reaches its region: every lane adds
+//    its pixels' terms over the (sub-block, plane) pairs the strut reaches,
+//    and the wave sums the nine pixel sums once per (strut, region) into the
+//    entry's slot, in region order.
 //
 // Lengths are in units of the strut's support R (hats): H^ = 1 - |q_perp|^2
 // / R^2 <= 1, the ends alpha^ = A_k - d.u^ and beta^ = B_k - d.u^ (A_k =
