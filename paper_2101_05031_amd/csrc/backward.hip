@@ -496,9 +496,13 @@ struct Lds<SZ, true, CH> {
 // MODE 0: 16x16 regions, shared reference planes; 1: 16x16 regions, every
 // plane its own reference; 2: 8x8 regions, every plane its own reference
 // and H^ = 1 - |q_perp^|^2 formed from q_perp itself (coarse pixels against
-// the support: the pieces of H^ above would be large).
+// the support: the pieces of H^ above would be large).  Every plane its own
+// reference with 8-plane windows holds 16.6 KB of LDS per wave, so at most 9
+// waves fit a compute unit: that mode asks for three waves per SIMD (up to
+// 168 registers) rather than four, which it could not reach.
 template <int SZ, bool SR, int MODE>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_backward32(
+__global__ __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(MODE == 1 && SZ == 8 ? 3 : 4))) void k_backward32(
     BackArgs a, uint32_t n_items) {
     constexpr int NS = MODE == 2 ? 1 : 2;     // sub-blocks per region side
     constexpr bool PR = MODE != 0;            // per-plane values in LDS
